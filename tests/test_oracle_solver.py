@@ -1,0 +1,76 @@
+"""Pins of the oracle's solver: FISTA without regularisation converges to the
+nonnegative least-squares solution (SciPy's Lawson-Hanson NNLS), proximal
+gradient without momentum and with an exact prox never increases the
+objective, A = I reaches the prox of p in one step, and the stopping tests."""
+import numpy as np
+import pytest
+from scipy.optimize import nnls
+
+import oracle
+import synth
+
+
+def _tiny_problem(seed=0):
+    rng = np.random.default_rng(seed)
+    ns, ny, nx, nz, K, nt, f, width = 2, 3, 3, 3, 4, 12, 3, 4
+    t0, taps = synth.random_table(nz, f, nt, width, rng, t0_lo=0, t0_hi=nt - width)
+    phi = rng.uniform(0.4, 1.0, size=nz)
+    sp = synth.species(ns, gamma=1.0)
+    S = oracle.switching_matrix(phi, sp.a, sp.b, sp.tau, sp.gamma, K) * 100.0
+    M = oracle.dense_A((ns, ny, nx, nz), K, nt, S, t0, taps)
+    c_true = np.maximum(rng.standard_normal((ns, ny, nx, nz)), 0)
+    p = (M @ c_true.ravel()) + 0.05 * rng.standard_normal(M.shape[0])
+    return M, p, (ns, ny, nx, nz)
+
+
+def test_fista_unregularised_reaches_nnls():
+    M, p, shape = _tiny_problem()
+    A = lambda v: M @ v.ravel()
+    AT = lambda w: (M.T @ w).reshape(shape)
+    lam = np.linalg.eigvalsh(M.T @ M)[-1]
+    c, it = oracle.fista(p, A, AT, 1.0 / lam, 0.0, 0.0, 20000, 1, shape_c=shape)
+    ref, _ = nnls(M, p, maxiter=5000)
+    assert it == 20000
+    np.testing.assert_allclose(c.ravel(), ref, atol=1e-6 * max(1.0, np.abs(ref).max()))
+
+
+def test_ista_objective_never_increases():
+    """Proximal gradient at step 1/L with an exact prox (l1 + nonnegativity,
+    no TV) is a descent method."""
+    M, p, shape = _tiny_problem(1)
+    A = lambda v: M @ v.ravel()
+    AT = lambda w: (M.T @ w).reshape(shape)
+    lam = np.linalg.eigvalsh(M.T @ M)[-1]
+    trace = []
+    oracle.fista(p, A, AT, 1.0 / lam, 0.0, 0.3, 60, 1, momentum=False, trace=trace, shape_c=shape)
+    d = np.diff(trace)
+    assert np.all(d <= 1e-12 * np.abs(np.array(trace[:-1])))
+    assert trace[-1] < trace[0]
+
+
+def test_identity_operator_one_step_is_prox_of_p():
+    rng = np.random.default_rng(2)
+    shape = (1, 3, 4, 5)
+    p = rng.standard_normal(shape)
+    c, _ = oracle.fista(p, lambda v: v, lambda v: v, 1.0, 0.2, 0.1, 1, 30, shape_c=shape)
+    np.testing.assert_allclose(c, oracle.prox_w(p, 0.2, 0.1, 30), atol=0)
+
+
+def test_stopping_rules_fire():
+    M, p, shape = _tiny_problem(3)
+    A = lambda v: M @ v.ravel()
+    AT = lambda w: (M.T @ w).reshape(shape)
+    lam = np.linalg.eigvalsh(M.T @ M)[-1]
+    _, it1 = oracle.fista(p, A, AT, 1.0 / lam, 0.0, 0.0, 5000, 1, eps1=1e-8, shape_c=shape)
+    _, it2 = oracle.fista(p, A, AT, 1.0 / lam, 0.0, 0.0, 5000, 1, eps2=1e-4, shape_c=shape)
+    assert 3 <= it1 < 5000 and 3 <= it2 < 5000
+
+
+def test_fista_trace_reported_and_ends_below_start():
+    M, p, shape = _tiny_problem(4)
+    A = lambda v: M @ v.ravel()
+    AT = lambda w: (M.T @ w).reshape(shape)
+    lam = np.linalg.eigvalsh(M.T @ M)[-1]
+    trace = []
+    oracle.fista(p, A, AT, 1.0 / (1.01 * lam), 0.05, 0.05, 50, 20, trace=trace, shape_c=shape)
+    assert len(trace) == 50 and trace[-1] < trace[0]
