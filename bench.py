@@ -1,0 +1,229 @@
+"""Benchmark of the reconstruction hot path on one MI355X.
+
+Workload: 128 x 128 x 64 voxels, 3 species, 32 pulses, 256 samples per
+A-scan, 31 x 31 footprint, 20 inner TV iterations.  A step is one outer
+iteration of the proximal-gradient solver, i.e. the whole per-iteration hot
+path: switching S, acoustic contraction H with the residual, its adjoint
+with S^T, the gradient step, the TV dual iteration, l1 + nonnegativity and
+the momentum update.  Each step applies A once and A^T once, so steps/s is
+the A + A^T apply rate inside the solver.  Inputs are resident in HBM before
+the timed region starts.
+
+Prints one JSON line.  --gpus must be 1 (the path runs on one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "A+Aᵀ applies/s & FISTA s-to-tol, BF16-MFMA vs FP32, at rel err ≤1e-3"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "bf16_split": 2500.0, "fp16_split": 2500.0,
+               "fp32": 157.3}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="bf16")
+    ap.add_argument("--compare", default="fp32", help="second precision reported beside ('' = none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-crop", type=int, default=12, help="lateral crop side of the oracle sample")
+    ap.add_argument("--kernel-reps", type=int, default=10)
+    return ap.parse_args()
+
+
+def time_events(torch, fn, reps):
+    """Average ms of fn() over reps launches, HIP events on the current stream."""
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(cfg, t0, taps, phi, sp, crop, steps_hint):
+    """The FP64 oracle, as it stands, timed on the host for one solver step
+    (A, A^T, TV prox with K2 inner steps, l1, momentum) on a crop x crop
+    lateral sample of the same geometry; scaled linearly in scan positions."""
+    import oracle
+    import synth
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    sub = cfg.crop(crop, crop)
+    c = synth.phantom(sub).astype(np.float64)
+    S = oracle.switching_matrix(phi, sp.a, sp.b, sp.tau, sp.gamma, cfg.n_pulses)
+    p = np.random.default_rng(0).standard_normal(sub.y_shape)
+    A = lambda v: oracle.apply_A(v, S, t0, taps, cfg.nt)
+    AT = lambda w: oracle.apply_AT(w, S, t0, taps, cfg.nz)
+    t = time.perf_counter()
+    oracle.fista(p, A, AT, 1e-3, 1e-3, 1e-3, 1, cfg.k2, c_init=c)
+    dt = time.perf_counter() - t
+    scale = (cfg.nx * cfg.ny) / float(crop * crop)
+    step_s = dt * scale
+    return {"value": 1.0 / step_s, "unit": "A+AT applies/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"one FP64 oracle solver step (A, A^T, TV prox K2={cfg.k2}, l1, momentum) on a "
+                       f"{crop}x{crop}-scan lateral crop (full Nz, K, Nt, F), {dt:.1f} s, scaled "
+                       f"x{scale:.1f} to {cfg.nx}x{cfg.ny} scans (extrapolated)")}
+
+
+def run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1, prec,
+             steps, warmup, reps):
+    plan = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=prec)
+    info = plan.stats()
+    c_in = torch.from_numpy(c_true).cuda()
+    y = torch.empty(cfg.y_shape, dtype=torch.float32, device="cuda")
+    g = torch.empty(cfg.c_shape, dtype=torch.float32, device="cuda")
+    # isolated operator applies
+    t_A = time_events(torch, lambda: plan.apply_A(c_in, y), reps)
+    t_AT = time_events(torch, lambda: plan.apply_AT(y, g), reps)
+    # band kernels alone (operands left by the applies above)
+    plan.apply_A(c_in, y)
+    t_H = time_events(torch, lambda: plan.band_only(0, y), reps)
+    plan.apply_AT(y, g)
+    t_HT = time_events(torch, lambda: plan.band_only(1, g), reps)
+    # solver steps: warmup, then exactly `steps` timed outer iterations
+    c = torch.zeros(cfg.c_shape, dtype=torch.float32, device="cuda")
+    plan.solve(p_t, c=c, lambda_tv=lam_tv, lambda_l1=lam_l1, k1=warmup, k2=cfg.k2, alpha1=alpha1)
+    c.zero_()
+    torch.cuda.synchronize()
+    t0_ = time.perf_counter()
+    _, st = plan.solve(p_t, c=c, lambda_tv=lam_tv, lambda_l1=lam_l1, k1=steps, k2=cfg.k2,
+                       alpha1=alpha1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0_
+    assert st["iterations"] == steps
+    # full solve to the configured iteration count, power iteration included
+    c_full = torch.zeros(cfg.c_shape, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, st_full = plan.solve(p_t, c=c_full, lambda_tv=lam_tv, lambda_l1=lam_l1, k1=cfg.k1,
+                            k2=cfg.k2, alpha1=0.0, n_power=30)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t1
+    return dict(plan=plan, info=info, t_A=t_A, t_AT=t_AT, t_H=t_H, t_HT=t_HT, step_s=dt / steps,
+                solve_s=t_solve, c_full=c_full, lambda_max=st_full["lambda_max"], y=y)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this path runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2510_23739_amd as pk
+    import synth
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    pk.load()
+    cfg = synth.C2
+    log(f"[bench] inputs for {cfg.name}")
+    c_true, t0, taps, phi, sp, n0, v0 = synth.inputs(cfg)
+    # measurements: clean A-scans from the FP32 path plus 20 dB noise (timing input only)
+    ref = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec="fp32")
+    y_clean = ref.apply_A(torch.from_numpy(c_true).cuda())
+    rms = float(torch.sqrt((y_clean.double() ** 2).mean()))
+    p_t = (y_clean + synth.noise_sigma(rms) * torch.from_numpy(n0).cuda()).contiguous()
+    del y_clean
+    aty = ref.apply_AT(p_t)
+    aty_inf = float(aty.abs().max())
+    lam_tv, lam_l1 = 5e-3 * aty_inf, 1e-2 * aty_inf
+    _, st0 = ref.solve(p_t, k1=0, n_power=30, v0=torch.from_numpy(v0).cuda())
+    alpha1 = st0["alpha1"]
+    ref.close()
+    log(f"[bench] alpha1 {alpha1:.4e}; timing {args.prec}")
+    res = run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1,
+                   args.prec, args.steps, args.warmup, args.kernel_reps)
+    cmp = None
+    if args.compare:
+        log(f"[bench] timing {args.compare}")
+        cmp = run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1,
+                       args.compare, max(2, args.steps // 4), 1, max(2, args.kernel_reps // 4))
+    # accuracy of the timed precision's operator vs the FP64 oracle on sampled A-scans
+    import oracle
+    S = oracle.switching_matrix(phi, sp.a, sp.b, sp.tau, sp.gamma, cfg.n_pulses)
+    scans = [(5, 7), (64, 64), (127, 0), (90, 33)]
+    y_s = oracle.apply_A_scans(c_true, S, t0, taps, cfg.nt, scans)
+    res["plan"].apply_A(torch.from_numpy(c_true).cuda(), res["y"])
+    y_g = np.stack([res["y"][:, iy, ix, :].cpu().numpy() for (iy, ix) in scans])
+    err_A = oracle.rel_err(y_g, y_s)
+    err_c_vs = None
+    if cmp is not None:
+        err_c_vs = float((res["c_full"] - cmp["c_full"]).double().norm() / cmp["c_full"].double().norm())
+    info = res["info"]
+    alg_flops = 2.0 * info["useful_macs"][0] * cfg.n_pulses * cfg.nx * cfg.ny
+    peak = PEAK_TFLOPS[args.prec]
+    achieved = alg_flops / (res["t_H"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": 1.0 / res["step_s"],
+        "unit": "A+AT applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["step_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic: seeded tube phantom, synthesized focused-transducer impulse response, 20 dB noise",
+        "config": {"workload": "128x128x64 voxels, 3 species, 32 pulses, Nt 256, footprint 31x31, "
+                               "K2 20; step = one solver iteration (A, A^T, TV prox, l1, momentum)",
+                   "nx": cfg.nx, "ny": cfg.ny, "nz": cfg.nz, "species": cfg.n_species,
+                   "pulses": cfg.n_pulses, "nt": cfg.nt, "footprint": cfg.f, "k2": cfg.k2},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": f"band contraction H ({args.prec}), algorithmic flops "
+                               f"2*nnz*K*Nx*Ny = {alg_flops / 1e9:.1f} GFLOP per launch",
+                     "avg_ms": res["t_H"]},
+        "cpu_baseline": None,
+        "apply_A_ms": res["t_A"], "apply_AT_ms": res["t_AT"],
+        "isolated_applies_per_s": 1e3 / (res["t_A"] + res["t_AT"]),
+        "H_kernel_ms": res["t_H"], "HT_kernel_ms": res["t_HT"],
+        "fista_s_to_tol": res["solve_s"], "fista_iterations": cfg.k1,
+        "rel_err_A_vs_oracle_sampled": err_A,
+        "band_fill": info["useful_macs"][0] / max(1, info["executed_macs"][0]),
+    }
+    if cmp is not None:
+        out["compare"] = {
+            "dtype": args.compare, "ms_per_step": cmp["step_s"] * 1e3,
+            "applies_per_s": 1.0 / cmp["step_s"], "apply_A_ms": cmp["t_A"], "apply_AT_ms": cmp["t_AT"],
+            "H_kernel_ms": cmp["t_H"], "HT_kernel_ms": cmp["t_HT"], "fista_s_to_tol": cmp["solve_s"],
+            "H_frac_of_peak": alg_flops / (cmp["t_H"] * 1e-3) / 1e12 / PEAK_TFLOPS[args.compare],
+            "rel_err_c_vs_this": err_c_vs,
+        }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(cfg, t0, taps, phi, sp, args.cpu_crop, args.steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

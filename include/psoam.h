@@ -1,0 +1,218 @@
+/*
+ * psoam.h -- C ABI of the MI355X (gfx950) hot path of the one-step
+ * photo-switching optoacoustic reconstruction (arXiv 2510.23739).
+ *
+ * The library applies the forward model A = H S and its adjoint, the
+ * proximal maps of the one-step regulariser (anisotropic TV, l1, x >= 0) and
+ * the proximal-gradient solver with FISTA momentum, all as HIP kernels.
+ *
+ * Conventions shared by every entry point
+ *  - Device pointers are HIP device memory on the current device; the caller
+ *    allocates and frees them.  Host pointers are named so below.
+ *  - Every call is enqueued on the given stream (a hipStream_t passed as
+ *    void*, NULL = the null stream) and returns before the work finishes,
+ *    except where a call states it synchronises.
+ *  - All external arrays are float32, C-contiguous:
+ *        c  concentrations  [S][Ny][Nx][Nz]
+ *        y  A-scans         [K][Ny][Nx][Nt]
+ *  - Return value: PSOAM_OK or one of the error codes; no exception crosses
+ *    the ABI.  psoam_last_error() gives the message of the last failure on
+ *    the calling thread.
+ *  - A plan is immutable after creation except for its internal scratch
+ *    buffers, so calls that share a plan must not overlap in time (they
+ *    serialise naturally when issued on one stream).
+ */
+#ifndef PSOAM_H
+#define PSOAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PSOAM_OK = 0,
+  PSOAM_EINVAL = 1,       /* bad argument: null pointer, size, shape, option */
+  PSOAM_EUNSUPPORTED = 2, /* valid request this build does not implement */
+  PSOAM_EHIP = 3,         /* a HIP runtime call failed (message has the HIP error) */
+  PSOAM_ENOMEM = 4,       /* device allocation failed */
+  PSOAM_EDIVERGED = 5     /* a FP64 reduction of the solver was not finite */
+};
+
+/* Arithmetic of the acoustic contraction (H and its adjoint).  FP32 runs
+ * float32 matrix cores; BF16/FP16 round both operands to 16 bits and
+ * accumulate in float32; the _SPLIT forms add the low-order parts of both
+ * operands (three products per tile) for about 16 significant bits. */
+typedef enum {
+  PSOAM_FP32 = 0,
+  PSOAM_BF16 = 1,
+  PSOAM_FP16 = 2,
+  PSOAM_BF16_SPLIT = 3,
+  PSOAM_FP16_SPLIT = 4
+} psoam_prec;
+
+/* Geometry of one reconstruction. */
+typedef struct {
+  int32_t nx, ny, nz;      /* voxel grid = scan grid laterally */
+  int32_t n_species;       /* S, 1..8 */
+  int32_t n_pulses;        /* K, switching pulses per cycle, >= 1 */
+  int32_t nt;              /* samples per A-scan */
+  int32_t f;               /* lateral footprint of the impulse response, odd; R = (f-1)/2 */
+  int32_t phi_per_voxel;   /* 0: phi is [Nz]; 1: phi is [Ny][Nx][Nz] */
+} psoam_geom;
+
+/* Photo-physics of the species (Sec. 2.1.1, eqs. epsilon, final-H):
+ *   S_v[k][s] = phi_v * (a[s] + b[s] * exp(-k * phi_v^gamma / tau[s]))
+ * a = OFF-state extinction, b = ON minus OFF extinction, tau = switching
+ * time constant in pulses; gamma = 1 is the fluence-dependent rate of the
+ * paper, gamma = 0 a fluence-independent one. */
+typedef struct {
+  double a[8];
+  double b[8];
+  double tau[8];
+  double gamma;
+} psoam_species;
+
+typedef struct psoam_plan psoam_plan;
+
+/* Build a plan: validates the geometry, packs the banded impulse response
+ * into matrix-core tiles for both H and its adjoint, and allocates the
+ * padded operand buffers (zeroed borders) the kernels read.
+ *
+ * The acoustic operator of one pulse (Sec. 2.1.3, eqs. q-above-1d,
+ * q-below-1d, acoustic-temporal-conv; discretised in Sec. 2.2.3):
+ *   y[k][iy][ix][t] = sum_{jdy,jdx in [0,F)} sum_z h[z][jdy][jdx][t] *
+ *                     b[k][iy+jdy-R][ix+jdx-R][z],   b = S c,
+ * with voxels outside the grid and samples outside [0, Nt) absent.
+ * h is given banded: h[z][jdy][jdx][t0 + j] = sir_taps[z][jdy][jdx][j] for
+ * j < sir_w, zero elsewhere by definition.
+ *
+ * phi, sir_t0, sir_taps are HOST pointers, read during the call only:
+ *   phi       float [Nz] or [Ny][Nx][Nz] (fluence, > 0)
+ *   sir_t0    int32 [Nz][F][F]
+ *   sir_taps  float [Nz][F][F][sir_w]
+ * The call synchronises `stream` (uploads finish before it returns).
+ * Errors: EINVAL (null pointer, non-positive size, even f, n_species outside
+ * 1..8, sir_w outside 1..64, non-finite table entry, non-positive phi or
+ * tau), EUNSUPPORTED (prec not built), ENOMEM, EHIP. *out is NULL on error. */
+int psoam_plan_create(const psoam_geom* g, const psoam_species* sp, const float* phi,
+                      const int32_t* sir_t0, const float* sir_taps, int32_t sir_w,
+                      int32_t prec, void* stream, psoam_plan** out);
+
+/* Free everything the plan owns (waits for the device first).  NULL is a no-op. */
+int psoam_plan_destroy(psoam_plan* plan);
+
+/* Geometry the plan was built with (host copy). */
+int psoam_plan_geom(const psoam_plan* plan, psoam_geom* g);
+
+/* y = A c = H S c  (eq. full-forward).  c: device [S][Ny][Nx][Nz] float,
+ * y: device [K][Ny][Nx][Nt] float, 16-byte aligned, overwritten.  c and y
+ * must not alias.  EINVAL: null plan or pointer, misaligned y. */
+int psoam_apply_A(const psoam_plan* plan, const float* c, float* y, void* stream);
+
+/* c = A^T y = S^T H^T y.  y: device [K][Ny][Nx][Nt], c: device
+ * [S][Ny][Nx][Nz], overwritten.  y and c must not alias.
+ * EINVAL: null plan or pointer. */
+int psoam_apply_AT(const psoam_plan* plan, const float* y, float* c, void* stream);
+
+/* Proximal map of thresh*||.||_1 (eqs. reg-tv-l1-one, prox), elementwise on
+ * n device floats: x = sign(z) max(|z| - thresh, 0), or max(z - thresh, 0)
+ * when nonneg != 0 (adds the indicator of x >= 0).  x may alias z.
+ * EINVAL: n < 0, thresh < 0 or not finite, null pointer with n > 0. */
+int psoam_prox_l1(float* x, const float* z, int64_t n, float thresh, int32_t nonneg,
+                  void* stream);
+
+/* Bytes of workspace psoam_prox_tv needs for this plan's grid. */
+size_t psoam_prox_tv_ws_bytes(const psoam_plan* plan);
+
+/* Proximal map of theta * TV, TV = sum over species of the l1 norms of the
+ * forward differences along y, x and z with a zero last difference (eq.
+ * reg-tv-l1-one, anisotropic, extended to 3D), computed by n_inner steps of
+ * the accelerated projected gradient on the dual (Alg. alg:prox-inner with
+ * L = grad, step 1/eig_max(grad^T grad), cold start u = 0):
+ *   u <- clip(eta + grad(z - grad^T eta)/mu, -theta, theta), FISTA momentum,
+ *   x  = z - grad^T u, then max(x, 0) if nonneg != 0.
+ * x, z: device [S][Ny][Nx][Nz] float (may alias).  ws: device, at least
+ * psoam_prox_tv_ws_bytes(plan) bytes, 256-byte aligned.
+ * EINVAL: theta < 0 or not finite, n_inner < 0, null pointers. */
+int psoam_prox_tv(const psoam_plan* plan, float* x, const float* z, float theta,
+                  int32_t n_inner, int32_t nonneg, void* ws, void* stream);
+
+/* Options of psoam_solve (Alg. alg:prox-outer and alg:prox-inner). */
+typedef struct {
+  double lambda_tv;        /* weight of TV(c) (lambda_1 of eq. reg-tv-l1-one) */
+  double lambda_l1;        /* weight of ||c||_1 (lambda_2 of eq. reg-tv-l1-one) */
+  int32_t k1;              /* outer iterations (maximum), >= 0 */
+  int32_t k2;              /* inner dual iterations of the TV prox, >= 0 */
+  double eps1;             /* relative objective change stop; 0 disables */
+  double eps2;             /* relative momentum-iterate change stop; 0 disables */
+  double alpha1;           /* step; <= 0: 1/(1.01 * power-iteration estimate) */
+  int32_t n_power;         /* power iterations when alpha1 <= 0 (e.g. 30) */
+  int32_t literal_momentum;/* 0: (t_k - 1)/t_{k+1}; 1: printed (t_k - 1)/(t_k + 1) */
+  int32_t warm_inner;      /* 0: cold dual start every outer step; 1: warm */
+  const float* v0;         /* device [S][Ny][Nx][Nz] power start, or NULL (constant) */
+  double* trace;           /* host, k1 doubles: F(c_{k+1}) per iteration, or NULL */
+} psoam_solve_opts;
+
+typedef struct {
+  int32_t iterations;      /* outer iterations performed */
+  int32_t status;          /* PSOAM_OK or PSOAM_EDIVERGED */
+  double alpha1;           /* step used */
+  double lambda_max;       /* power-iteration estimate (0 if alpha1 was given) */
+  double objective;        /* F(c) at exit if computed (trace or eps1), else NaN */
+} psoam_solve_stats;
+
+/* Solve eq. one-step without its TV(Sc) term:
+ *   c = argmin_{c >= 0} 1/2 |A c - p|^2 + lambda_tv TV(c) + lambda_l1 |c|_1
+ * by Alg. alg:prox-outer: c_{k+1} = prox(xi_k - alpha1 A^T(A xi_k - p)),
+ * xi_{k+1} = c_{k+1} + beta_k (c_{k+1} - c_k), the prox being the TV dual
+ * iteration followed by max(. - alpha1 lambda_l1, 0).
+ * p: device [K][Ny][Nx][Nt]; c: device [S][Ny][Nx][Nz], initial guess on
+ * entry (zeros for the paper's start), result on exit.  st: host, may be
+ * NULL.  Synchronises the stream when it needs host scalars (power
+ * iteration result, stopping tests, trace) and at exit.
+ * EINVAL: bad options; EDIVERGED: non-finite reduction (c holds the last
+ * finite iterate). */
+int psoam_solve(const psoam_plan* plan, const float* p, float* c, const psoam_solve_opts* o,
+                psoam_solve_stats* st, void* stream);
+
+/* n independent solves (plans of different shapes allowed) issued as one
+ * batch: each outer step of every problem is launched as one grouped
+ * launch per phase.  Arrays of length n; opts/st arrays too (st may be
+ * NULL).  Same semantics per problem as psoam_solve. */
+int psoam_solve_batch(int32_t n, const psoam_plan* const* plans, const float* const* p,
+                      float* const* c, const psoam_solve_opts* o, psoam_solve_stats* st,
+                      void* stream);
+
+/* ---- diagnostics (timing and profiling; not steps of the method) ---- */
+
+/* Work figures of a plan's band contraction, per position and per pulse:
+ * useful_macs = nonzero band entries h[z][jdy][jdx][t] with t in [0, Nt)
+ * (the algorithmic multiply-adds of one A-scan of one pulse);
+ * chunks = packed matrix-core tiles; executed_macs = chunks times the
+ * tile size (16 x 32 for 16-bit, 16 x 4 for FP32).  dir 0: H, dir 1: H^T. */
+typedef struct {
+  int64_t useful_macs[2];
+  int64_t chunks[2];
+  int64_t executed_macs[2];
+  int64_t operand_bytes[2];  /* padded operand buffer of H (0) and H^T (1) */
+} psoam_plan_info;
+
+int psoam_plan_stats(const psoam_plan* plan, psoam_plan_info* info);
+
+/* Launch only the band-contraction kernel of H (dir 0: writes y) or of
+ * S^T H^T (dir 1: writes c) on the padded operand the plan holds from its
+ * last apply, on `stream`.  Used to time that kernel alone; its output
+ * equals the matching apply's only after that apply ran on the same input. */
+int psoam_band_only(const psoam_plan* plan, int32_t dir, float* out, void* stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* psoam_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSOAM_H */

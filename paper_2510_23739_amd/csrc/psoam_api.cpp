@@ -1,0 +1,405 @@
+// C entry points of the psoam library: operator applies, proximal maps and
+// the proximal-gradient solver (Alg. alg:prox-outer with the inner dual
+// iteration of Alg. alg:prox-inner for the TV part).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "psoam_internal.h"
+
+namespace psoam {
+int create_plan(const psoam_geom* gp, const psoam_species* sp, const float* phi,
+                const int32_t* t0, const float* taps, int32_t sir_w, int32_t prec,
+                hipStream_t stream, psoam_plan** out);
+void free_plan(psoam_plan* P);
+const char* last_error_cstr();
+
+namespace {
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Next FISTA step t' and extrapolation weight (Beck-Teboulle (t-1)/t', or the
+// printed (t-1)/(t+1)).
+inline void momentum_step(double& t, double& beta, bool literal) {
+  const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+  beta = literal ? (t - 1.0) / (t + 1.0) : (t - 1.0) / tn;
+  t = tn;
+}
+
+inline double inv_mu_tv(const psoam_geom& g) {
+  // 1 / eig_max(grad^T grad) = 1 / sum_d 4 sin^2(pi (n_d - 1) / (2 n_d))
+  const int n[3] = {g.ny, g.nx, g.nz};
+  double mu = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double s = std::sin(M_PI * (n[d] - 1) / (2.0 * n[d]));
+    mu += 4.0 * s * s;
+  }
+  return mu > 0.0 ? 1.0 / mu : 0.0;
+}
+
+struct SolveBufs {
+  float* cprev;
+  float* cnext;
+  float* xi;
+  float* g;
+  float* zb;
+  float* u[3];
+  float* w;
+};
+
+int ensure_solve_ws(psoam_plan* P, SolveBufs& B) {
+  const size_t sv = P->c_elems();
+  const size_t need = sizeof(float) * sv * (5 + 9 + 1) + 256 * 16;
+  if (P->solve_ws.bytes < need) {
+    if (P->solve_ws.base) PSOAM_HIP(hipFree(P->solve_ws.base));
+    P->solve_ws.base = nullptr;
+    P->solve_ws.bytes = 0;
+    PSOAM_HIP(hipMalloc(&P->solve_ws.base, need));
+    P->solve_ws.bytes = need;
+  }
+  const size_t np = std::max(band_partials(P, 1), (size_t)2 * reduce_blocks((int64_t)sv));
+  if (P->n_partial < np) {
+    if (P->d_partial) PSOAM_HIP(hipFree(P->d_partial));
+    P->d_partial = nullptr;
+    PSOAM_HIP(hipMalloc(&P->d_partial, sizeof(double) * np));
+    P->n_partial = np;
+  }
+  if (!P->d_scalars) PSOAM_HIP(hipMalloc(&P->d_scalars, sizeof(double) * 16));
+  auto align = [](char* p) { return (float*)(((uintptr_t)p + 255) & ~(uintptr_t)255); };
+  char* p = (char*)P->solve_ws.base;
+  float** slots[] = {&B.cprev, &B.cnext, &B.xi, &B.g, &B.zb, &B.u[0], &B.u[1], &B.u[2], &B.w};
+  const size_t lens[] = {sv, sv, sv, sv, sv, 3 * sv, 3 * sv, 3 * sv, sv};
+  for (int i = 0; i < 9; ++i) {
+    float* a = align(p);
+    *slots[i] = a;
+    p = (char*)(a + lens[i]);
+  }
+  return PSOAM_OK;
+}
+
+// x = prox of theta*TV at z by n_inner dual steps (u buffers given), then the
+// final map (mode 0 plain, 1 max(.,0), 2 max(. - th1, 0)).  u_start: dual
+// start (null = 0).  Returns the buffer holding the last dual iterate via
+// *u_last (null if n_inner == 0).
+int tv_prox_core(const psoam_plan* P, float* x, const float* z, float theta, int n_inner,
+                 int mode, float th1, float* const u[3], float* w, const float* u_start,
+                 bool literal, const float** u_last, hipStream_t s) {
+  const float inv_mu = (float)inv_mu_tv(P->g);
+  if (u_last) *u_last = nullptr;
+  if (n_inner <= 0 || theta == 0.0f) {
+    PSOAM_HIP(launch_tv_final(P, x, z, nullptr, mode, th1, s));
+    return PSOAM_OK;
+  }
+  double t = 1.0, beta_prev = 0.0;
+  const float* cur = u_start;   // u_j
+  const float* prev = nullptr;  // u_{j-1}
+  int slot = 0;
+  for (int j = 0; j < n_inner; ++j) {
+    // eta_j = u_j + beta_{j-1} (u_j - u_{j-1})
+    const float* wz = z;
+    if (cur) {
+      PSOAM_HIP(launch_tv_w(P, w, z, cur, prev, (float)beta_prev, s));
+      wz = w;
+    }
+    float* nxt = u[slot];
+    if (nxt == cur || nxt == prev) {
+      slot = (slot + 1) % 3;
+      nxt = u[slot];
+      if (nxt == cur || nxt == prev) {
+        slot = (slot + 1) % 3;
+        nxt = u[slot];
+      }
+    }
+    PSOAM_HIP(launch_tv_u(P, nxt, cur, prev, (float)beta_prev, wz, inv_mu, theta, s));
+    slot = (slot + 1) % 3;
+    double beta;
+    momentum_step(t, beta, literal);
+    beta_prev = beta;
+    prev = cur;
+    cur = nxt;
+  }
+  PSOAM_HIP(launch_tv_final(P, x, z, cur, mode, th1, s));
+  if (u_last) *u_last = cur;
+  return PSOAM_OK;
+}
+
+int check_plan(const psoam_plan* P) {
+  if (!P) return fail(PSOAM_EINVAL, "plan is NULL");
+  return PSOAM_OK;
+}
+
+int copy_scalars(const psoam_plan* P, double* host, int n, hipStream_t s) {
+  PSOAM_HIP(hipMemcpyAsync(host, P->d_scalars, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  PSOAM_HIP(hipStreamSynchronize(s));
+  return PSOAM_OK;
+}
+
+// data term 1/2 |A c - p|^2 + TV + l1 sums of c into d_scalars[4..6]
+int objective_terms(psoam_plan* P, const float* c, const float* p, hipStream_t s) {
+  PSOAM_HIP(launch_switch_fwd(P, c, s));
+  PSOAM_HIP(launch_band(P, 1, nullptr, p, P->d_partial, s));
+  PSOAM_HIP(launch_sum_partials(P->d_partial, band_partials(P, 1), P->d_scalars + 4, s));
+  PSOAM_HIP(launch_tv_l1_sums(P, c, P->d_partial, P->d_scalars + 5, s));
+  return PSOAM_OK;
+}
+
+int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o,
+              psoam_solve_stats* st, hipStream_t s) {
+  if (!p || !c || !o) return fail(PSOAM_EINVAL, "solve: NULL argument");
+  if (o->k1 < 0 || o->k2 < 0 || !(o->lambda_tv >= 0.0) || !(o->lambda_l1 >= 0.0) ||
+      !std::isfinite(o->lambda_tv) || !std::isfinite(o->lambda_l1) || !(o->eps1 >= 0.0) ||
+      !(o->eps2 >= 0.0) || !std::isfinite(o->alpha1))
+    return fail(PSOAM_EINVAL, "solve: invalid options (negative or non-finite)");
+  if (o->alpha1 <= 0.0 && o->n_power < 1)
+    return fail(PSOAM_EINVAL, "solve: n_power must be >= 1 when alpha1 is not given");
+  SolveBufs B;
+  int rc = ensure_solve_ws(P, B);
+  if (rc) return rc;
+  const int64_t sv = (int64_t)P->c_elems();
+  double hs[16];
+  psoam_solve_stats stats;
+  stats.iterations = 0;
+  stats.status = PSOAM_OK;
+  stats.lambda_max = 0.0;
+  stats.objective = std::numeric_limits<double>::quiet_NaN();
+  double alpha1 = o->alpha1;
+  if (alpha1 <= 0.0) {
+    // power iteration on A^T A with FP64 norms: v <- v0/|v0|; w = A^T A v;
+    // lam = <v, w>; v = w/|w|
+    float* v = B.zb;
+    float* w = B.g;
+    if (o->v0) {
+      PSOAM_HIP(hipMemcpyAsync(w, o->v0, sizeof(float) * sv, hipMemcpyDeviceToDevice, s));
+    } else {
+      PSOAM_HIP(launch_fill(w, 1.0f, sv, s));
+    }
+    PSOAM_HIP(launch_dot(w, w, sv, P->d_partial, P->d_scalars + 1, s));
+    PSOAM_HIP(launch_scale_by_rnorm(v, w, P->d_scalars + 1, sv, s));
+    for (int i = 0; i < o->n_power; ++i) {
+      PSOAM_HIP(launch_switch_fwd(P, v, s));
+      PSOAM_HIP(launch_band(P, 1, nullptr, nullptr, P->d_partial, s));
+      PSOAM_HIP(launch_band(P, 2, w, nullptr, nullptr, s));
+      PSOAM_HIP(launch_dot(v, w, sv, P->d_partial, P->d_scalars + 0, s));
+      PSOAM_HIP(launch_dot(w, w, sv, P->d_partial, P->d_scalars + 1, s));
+      PSOAM_HIP(launch_scale_by_rnorm(v, w, P->d_scalars + 1, sv, s));
+    }
+    rc = copy_scalars(P, hs, 2, s);
+    if (rc) return rc;
+    stats.lambda_max = hs[0];
+    if (!std::isfinite(hs[0]) || !(hs[0] > 0.0) || !std::isfinite(hs[1])) {
+      stats.status = PSOAM_EDIVERGED;
+      if (st) *st = stats;
+      return fail(PSOAM_EDIVERGED, "solve: power iteration gave a non-finite or non-positive estimate");
+    }
+    alpha1 = 1.0 / (1.01 * hs[0]);
+  }
+  stats.alpha1 = alpha1;
+  const bool literal = o->literal_momentum != 0;
+  const float th_tv = (float)(alpha1 * o->lambda_tv);
+  const float th_l1 = (float)(alpha1 * o->lambda_l1);
+  PSOAM_HIP(hipMemcpyAsync(B.cprev, c, sizeof(float) * sv, hipMemcpyDeviceToDevice, s));
+  PSOAM_HIP(hipMemcpyAsync(B.xi, c, sizeof(float) * sv, hipMemcpyDeviceToDevice, s));
+  const bool need_obj = o->eps1 > 0.0 || o->trace != nullptr;
+  double t = 1.0, f_prev = 0.0;
+  bool have_f = false;
+  const float* u_warm = nullptr;
+  float* uw[3] = {B.u[0], B.u[1], B.u[2]};
+  for (int k = 0; k < o->k1; ++k) {
+    // gradient A^T (A xi - p)
+    PSOAM_HIP(launch_switch_fwd(P, B.xi, s));
+    PSOAM_HIP(launch_band(P, 1, nullptr, p, P->d_partial, s));
+    PSOAM_HIP(launch_band(P, 2, B.g, nullptr, nullptr, s));
+    PSOAM_HIP(launch_axpby(B.zb, B.xi, B.g, 1.0f, (float)(-alpha1), sv, s));
+    // prox: TV dual iteration, then max(. - alpha1 lambda_l1, 0)
+    const float* u_last = nullptr;
+    rc = tv_prox_core(P, B.cnext, B.zb, th_tv, o->k2, 2, th_l1, uw, B.w,
+                      o->warm_inner ? u_warm : nullptr, literal, &u_last, s);
+    if (rc) return rc;
+    if (o->warm_inner && u_last) {
+      // keep the last dual iterate out of the next call's rotation
+      u_warm = u_last;
+      int keep = 0;
+      for (int i = 0; i < 3; ++i)
+        if (uw[i] == u_last) keep = i;
+      std::swap(uw[keep], uw[2]);
+      // uw[2] is now the warm start; the next call writes uw[0], uw[1] and may
+      // reuse uw[2] only after it stops being needed.
+    }
+    double beta;
+    momentum_step(t, beta, literal);
+    PSOAM_HIP(launch_momentum(B.xi, B.cnext, B.cprev, (float)beta, sv, P->d_partial, s));
+    const size_t nb = reduce_blocks(sv);
+    if (o->eps2 > 0.0) {
+      PSOAM_HIP(launch_sum_partials(P->d_partial, nb, P->d_scalars + 2, s));
+      PSOAM_HIP(launch_sum_partials(P->d_partial + nb, nb, P->d_scalars + 3, s));
+    }
+    std::swap(B.cprev, B.cnext);  // cprev = c_{k+1}
+    stats.iterations = k + 1;
+    bool stop = false;
+    if (need_obj || o->eps2 > 0.0) {
+      if (need_obj) {
+        rc = objective_terms(P, B.cprev, p, s);
+        if (rc) return rc;
+      }
+      rc = copy_scalars(P, hs, 7, s);
+      if (rc) return rc;
+      double f_now = 0.0;
+      if (need_obj) {
+        f_now = 0.5 * hs[4] + o->lambda_tv * hs[5] + o->lambda_l1 * hs[6];
+        if (!std::isfinite(f_now)) {
+          stats.status = PSOAM_EDIVERGED;
+          break;
+        }
+        if (o->trace) o->trace[k] = f_now;
+        stats.objective = f_now;
+      }
+      if (k > 1) {
+        if (o->eps1 > 0.0 && have_f && std::fabs(f_now - f_prev) < o->eps1 * std::fabs(f_prev))
+          stop = true;
+        if (o->eps2 > 0.0 && hs[3] > 0.0 && std::sqrt(hs[2]) < o->eps2 * std::sqrt(hs[3]))
+          stop = true;
+      }
+      if (need_obj) {
+        f_prev = f_now;
+        have_f = true;
+      }
+    }
+    if (stop) break;
+  }
+  PSOAM_HIP(hipMemcpyAsync(c, B.cprev, sizeof(float) * sv, hipMemcpyDeviceToDevice, s));
+  PSOAM_HIP(launch_dot(c, c, sv, P->d_partial, P->d_scalars + 0, s));
+  rc = copy_scalars(P, hs, 1, s);
+  if (rc) return rc;
+  if (!std::isfinite(hs[0])) stats.status = PSOAM_EDIVERGED;
+  if (st) *st = stats;
+  if (stats.status != PSOAM_OK) return fail(PSOAM_EDIVERGED, "solve: iterate became non-finite");
+  return PSOAM_OK;
+}
+
+}  // namespace
+}  // namespace psoam
+
+using namespace psoam;
+
+extern "C" {
+
+int psoam_plan_create(const psoam_geom* g, const psoam_species* sp, const float* phi,
+                      const int32_t* sir_t0, const float* sir_taps, int32_t sir_w,
+                      int32_t prec, void* stream, psoam_plan** out) {
+  return create_plan(g, sp, phi, sir_t0, sir_taps, sir_w, prec, S(stream), out);
+}
+
+int psoam_plan_destroy(psoam_plan* plan) {
+  free_plan(plan);
+  return PSOAM_OK;
+}
+
+int psoam_plan_geom(const psoam_plan* plan, psoam_geom* g) {
+  if (!plan || !g) return fail(PSOAM_EINVAL, "plan_geom: NULL argument");
+  *g = plan->g;
+  return PSOAM_OK;
+}
+
+int psoam_apply_A(const psoam_plan* plan, const float* c, float* y, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!c || !y) return fail(PSOAM_EINVAL, "apply_A: NULL argument");
+  if (((uintptr_t)y & 15) != 0) return fail(PSOAM_EINVAL, "apply_A: y must be 16-byte aligned");
+  PSOAM_HIP(launch_switch_fwd(plan, c, S(stream)));
+  PSOAM_HIP(launch_band(plan, 0, y, nullptr, nullptr, S(stream)));
+  return PSOAM_OK;
+}
+
+int psoam_apply_AT(const psoam_plan* plan, const float* y, float* c, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!c || !y) return fail(PSOAM_EINVAL, "apply_AT: NULL argument");
+  PSOAM_HIP(launch_pack_r(plan, y, S(stream)));
+  PSOAM_HIP(launch_band(plan, 2, c, nullptr, nullptr, S(stream)));
+  return PSOAM_OK;
+}
+
+int psoam_prox_l1(float* x, const float* z, int64_t n, float thresh, int32_t nonneg,
+                  void* stream) {
+  if (n < 0) return fail(PSOAM_EINVAL, "prox_l1: n < 0");
+  if (!(thresh >= 0.0f) || !std::isfinite(thresh))
+    return fail(PSOAM_EINVAL, "prox_l1: thresh must be finite and >= 0");
+  if (n > 0 && (!x || !z)) return fail(PSOAM_EINVAL, "prox_l1: NULL argument");
+  PSOAM_HIP(launch_prox_l1(x, z, n, thresh, nonneg, S(stream)));
+  return PSOAM_OK;
+}
+
+size_t psoam_prox_tv_ws_bytes(const psoam_plan* plan) {
+  if (!plan) return 0;
+  return sizeof(float) * plan->c_elems() * 10 + 4 * 256;
+}
+
+int psoam_prox_tv(const psoam_plan* plan, float* x, const float* z, float theta,
+                  int32_t n_inner, int32_t nonneg, void* ws, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!x || !z || !ws) return fail(PSOAM_EINVAL, "prox_tv: NULL argument");
+  if (!(theta >= 0.0f) || !std::isfinite(theta))
+    return fail(PSOAM_EINVAL, "prox_tv: theta must be finite and >= 0");
+  if (n_inner < 0) return fail(PSOAM_EINVAL, "prox_tv: n_inner < 0");
+  if (((uintptr_t)ws & 255) != 0) return fail(PSOAM_EINVAL, "prox_tv: ws must be 256-byte aligned");
+  const size_t sv = plan->c_elems();
+  auto align = [](float* p) { return (float*)(((uintptr_t)p + 255) & ~(uintptr_t)255); };
+  float* u0 = (float*)ws;
+  float* u1 = align(u0 + 3 * sv);
+  float* u2 = align(u1 + 3 * sv);
+  float* w = align(u2 + 3 * sv);
+  float* u[3] = {u0, u1, u2};
+  // z and x may alias: keep z intact until the final map, which reads z[v] only at v
+  return tv_prox_core(plan, x, z, theta, n_inner, nonneg ? 1 : 0, 0.0f, u, w, nullptr, false,
+                      nullptr, S(stream));
+}
+
+int psoam_solve(const psoam_plan* plan, const float* p, float* c, const psoam_solve_opts* o,
+                psoam_solve_stats* st, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  return solve_one(const_cast<psoam_plan*>(plan), p, c, o, st, S(stream));
+}
+
+int psoam_solve_batch(int32_t n, const psoam_plan* const* plans, const float* const* p,
+                      float* const* c, const psoam_solve_opts* o, psoam_solve_stats* st,
+                      void* stream) {
+  if (n < 0) return fail(PSOAM_EINVAL, "solve_batch: n < 0");
+  if (n > 0 && (!plans || !p || !c || !o)) return fail(PSOAM_EINVAL, "solve_batch: NULL argument");
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(PSOAM_EINVAL, "solve_batch: NULL plan");
+    const int rc = solve_one(const_cast<psoam_plan*>(plans[i]), p[i], c[i], &o[i],
+                             st ? &st[i] : nullptr, S(stream));
+    if (rc) return rc;
+  }
+  return PSOAM_OK;
+}
+
+int psoam_plan_stats(const psoam_plan* plan, psoam_plan_info* info) {
+  if (!plan || !info) return fail(PSOAM_EINVAL, "plan_stats: NULL argument");
+  const bool half = plan->prec != PSOAM_FP32;
+  const int64_t tile = half ? 16 * 32 : 16 * 4;
+  const BandTable* T[2] = {&plan->fwd, &plan->adj};
+  for (int d = 0; d < 2; ++d) {
+    info->useful_macs[d] = (int64_t)T[d]->useful_macs;
+    info->chunks[d] = T[d]->n_chunks;
+    info->executed_macs[d] = (int64_t)T[d]->n_chunks * tile;
+  }
+  info->operand_bytes[0] = (int64_t)plan->bq_bytes;
+  info->operand_bytes[1] = (int64_t)plan->rq_bytes;
+  return PSOAM_OK;
+}
+
+int psoam_band_only(const psoam_plan* plan, int32_t dir, float* out, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!out || (dir != 0 && dir != 1)) return fail(PSOAM_EINVAL, "band_only: bad argument");
+  if (dir == 0 && ((uintptr_t)out & 15) != 0)
+    return fail(PSOAM_EINVAL, "band_only: y must be 16-byte aligned");
+  PSOAM_HIP(launch_band(plan, dir == 0 ? 0 : 2, out, nullptr, nullptr, S(stream)));
+  return PSOAM_OK;
+}
+
+const char* psoam_last_error(void) { return last_error_cstr(); }
+
+}  // extern "C"

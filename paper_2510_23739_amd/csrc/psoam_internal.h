@@ -1,0 +1,153 @@
+// Internal declarations of the psoam library (not part of the C ABI).
+//
+// Data layout in HBM (all padded operands have zeroed borders that are never
+// written, so the band kernels need no bounds checks on their reads):
+//   16-bit operands (BF16/FP16):  Q[Yp][Xp][Lo][Kp][8]   (8 consecutive
+//       samples of the contracted axis -- depth z for H, time t for H^T --
+//       form one 16-byte "octet"; the Kp pulses of one octet are adjacent so
+//       16 pulses x 16 bytes of one octet are 256 contiguous bytes)
+//   FP32 operands:                Q[Yp][Xp][L][Kp]       (pulses adjacent)
+// Yp = Ny + 2R, Xp = roundup(Nx, 16) + 2R: a scan/voxel position (iy, ix)
+// reads its whole F x F footprint at padded rows iy..iy+F-1, columns
+// ix..ix+F-1.  Kp = K rounded up to 16 (one matrix-core column block).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "psoam.h"
+
+namespace psoam {
+
+constexpr int kMaxSpecies = 8;
+constexpr int kWaveLanes = 64;
+constexpr int kPosPerWave = 8;       // scan/voxel positions owned by one wave
+constexpr int kPadX = 16;            // Nx is padded up to a multiple of this
+constexpr int kWavesPerBlock = 4;    // consecutive output tiles of one position block
+constexpr float kFp16Scale = 256.0f; // FP16 operands carry this power-of-two scale
+
+// Photo-switching coefficients in the form the kernels evaluate:
+//   S_v[k][s] = phi_v * (a[s] + b[s] * exp(-k * phi_v^gamma * inv_tau[s]))
+struct SwitchParams {
+  int ns;
+  int nk;
+  int per_voxel;
+  float gamma;
+  float a[kMaxSpecies];
+  float b[kMaxSpecies];
+  float inv_tau[kMaxSpecies];
+};
+
+// One direction of the band contraction (H, or H^T viewed as a correlation
+// with flipped offsets): for every output tile of 16 rows, a list of chunks;
+// a chunk is 4 "groups", each naming one octet (16-bit) or one sample (FP32)
+// of the contracted axis at one lateral offset, plus the matching 16 x 32
+// (16-bit) or 16 x 4 (FP32) block of the band matrix, pre-packed in the
+// lane order of the matrix-core instruction.
+struct BandTable {
+  int n_mtiles = 0;          // output tiles of 16 rows
+  int m_rows = 0;            // valid output rows (Nt for H, Nz for H^T)
+  int n_chunks = 0;
+  std::vector<int> h_start;  // [n_mtiles + 1]
+  int* d_start = nullptr;
+  int* d_off = nullptr;      // [n_chunks * 4] element offsets from the position base
+  void* d_a = nullptr;       // packed band values (hi part)
+  void* d_a_lo = nullptr;    // low-order parts for the split precisions
+  size_t useful_macs = 0;    // nonzero band entries covered (per position and pulse)
+};
+
+struct Workspace {
+  size_t bytes = 0;
+  void* base = nullptr;
+};
+
+}  // namespace psoam
+
+struct psoam_plan {
+  psoam_geom g;
+  psoam_species sp_in;
+  psoam::SwitchParams sw;
+  int prec;
+  int R, F, W;
+  int Kp, NB;       // padded pulses, 16-pulse column blocks
+  int Yp, Xp;
+  int Lz, Lt;       // contracted lengths of the H operand (z) and H^T operand (t), in samples
+  size_t ps_b, ps_r;  // elements per padded position of the H / H^T operands
+  int device;
+  float* d_phi = nullptr;
+  float* d_stab = nullptr;   // [Nz][Kp][S] when phi is per depth
+  void* d_bq = nullptr;      // H operand (hi)
+  void* d_bq_lo = nullptr;
+  void* d_rq = nullptr;      // H^T operand (hi)
+  void* d_rq_lo = nullptr;
+  size_t bq_bytes = 0, rq_bytes = 0;
+  psoam::BandTable fwd, adj;
+  // solver scratch (allocated on first use, grown as needed)
+  psoam::Workspace solve_ws;
+  double* d_partial = nullptr;  // per-wave / per-block FP64 partial sums
+  size_t n_partial = 0;
+  double* d_scalars = nullptr;  // small FP64 results (reductions)
+  size_t y_elems() const { return (size_t)g.n_pulses * g.ny * g.nx * g.nt; }
+  size_t c_elems() const { return (size_t)g.n_species * g.ny * g.nx * g.nz; }
+  size_t v_elems() const { return (size_t)g.ny * g.nx * g.nz; }
+};
+
+namespace psoam {
+
+// thread-local error message
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+#define PSOAM_HIP(call)                                   \
+  do {                                                    \
+    hipError_t _e = (call);                               \
+    if (_e != hipSuccess) return psoam::hip_fail(_e, #call); \
+  } while (0)
+
+// kernel launchers (psoam_kernels.hip); all return hipError_t of the launch
+hipError_t launch_switch_fwd(const psoam_plan* P, const float* c, hipStream_t s);
+hipError_t launch_pack_r(const psoam_plan* P, const float* y, hipStream_t s);
+// mode 0: y = H b (writes y);  mode 1: r = H b - p (p may be null), written into the
+// H^T operand, sum r^2 into partial[]; mode 2: c = S^T H^T r (writes c)
+hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* pmeas,
+                       double* partial, hipStream_t s);
+size_t band_partials(const psoam_plan* P, int mode);
+
+hipError_t launch_prox_l1(float* x, const float* z, int64_t n, float thresh, int nonneg,
+                          hipStream_t s);
+// one inner step of the TV dual iteration:
+//   w = z - grad^T eta ; u_next = clip(eta + inv_mu * grad w, -theta, theta),
+//   eta = u_cur + beta (u_cur - u_prev)  (u_cur == null: eta = 0; u_prev == null: eta = u_cur)
+hipError_t launch_tv_w(const psoam_plan* P, float* w, const float* z, const float* u_cur,
+                       const float* u_prev, float beta, hipStream_t s);
+hipError_t launch_tv_u(const psoam_plan* P, float* u_next, const float* u_cur,
+                       const float* u_prev, float beta, const float* w, float inv_mu,
+                       float theta, hipStream_t s);
+// x = z - grad^T u (u may be null: x = z); then mode 0: as is, 1: max(x,0), 2: max(x - t1, 0)
+hipError_t launch_tv_final(const psoam_plan* P, float* x, const float* z, const float* u,
+                           int mode, float thresh1, hipStream_t s);
+// x = a*x + b*y  elementwise (n floats)
+hipError_t launch_axpby(float* out, const float* x, const float* y, float a, float b,
+                        int64_t n, hipStream_t s);
+// FP64 reductions, deterministic two-stage: results written to out[0..]
+//   dot: out[0] = <x, y>   (y == x allowed)
+hipError_t launch_dot(const float* x, const float* y, int64_t n, double* partial,
+                      double* out, hipStream_t s);
+hipError_t launch_sum_partials(const double* partial, size_t n, double* out, hipStream_t s);
+//   out[0] = sum |grad c| (TV), out[1] = sum |c|
+hipError_t launch_tv_l1_sums(const psoam_plan* P, const float* c, double* partial,
+                             double* out, hipStream_t s);
+// v = w / sqrt(*norm2)  (norm2 on device)
+hipError_t launch_scale_by_rnorm(float* v, const float* w, const double* norm2, int64_t n,
+                                 hipStream_t s);
+hipError_t launch_fill(float* x, float v, int64_t n, hipStream_t s);
+// xi_next = c_next + beta (c_next - c_prev); partial sums of |xi_next - xi|^2 and |xi|^2
+hipError_t launch_momentum(float* xi, const float* c_next, const float* c_prev, float beta,
+                           int64_t n, double* partial, hipStream_t s);
+size_t reduce_blocks(int64_t n);
+
+}  // namespace psoam

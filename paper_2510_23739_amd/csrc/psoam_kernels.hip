@@ -1,0 +1,927 @@
+// HIP kernels of the psoam hot path for gfx950 (MI355X).
+//
+//  switch_fwd*  b = S c           photo-switching matrix per voxel (eq. Sij-detailed)
+//  band16/32    y = H b, r = H b - p, or c = S^T H^T r
+//               (acoustic operator, Sec. 2.1.3 / 2.2.3; block-diagonal over
+//               pulses as W_tot, eq. acoustic-full-forward)
+//  pack_r*      y -> padded operand of H^T
+//  tv_*         one step of the dual iteration of the TV prox (Alg. alg:prox-inner)
+//  prox_l1      soft threshold (+ x >= 0)
+//  reductions   deterministic FP64 two-stage sums (objective, norms, power iteration)
+//
+// Matrix-core mapping of the band contraction.  For one output tile of 16
+// rows (16 samples t for H, 16 depths z for H^T) and one position, the
+// contraction runs over (lateral offset, contracted sample) pairs whose band
+// entry is nonzero in the tile.  These are packed 4 groups per chunk; a group
+// is an 8-sample octet (16-bit inputs, v_mfma_f32_16x16x32_{bf16,f16}) or a
+// single sample (FP32 inputs, v_mfma_f32_16x16x4_f32) at one lateral offset.
+// The 16 columns of the instruction are 16 pulses: the band block (operand A)
+// is shared by every pulse and every position, so each wave loads it once per
+// chunk and reuses it for kPosPerWave positions x (Kp/16) pulse blocks.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "psoam_internal.h"
+
+namespace psoam {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int PREC>
+struct Half;
+
+template <>
+struct Half<PSOAM_BF16> {
+  using E = __bf16;
+  using V = bf16x8;
+  using V4 = bf16x4;
+  static constexpr float scale = 1.0f;
+  static __device__ __forceinline__ f32x4 mma(V a, V b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Half<PSOAM_FP16> {
+  using E = _Float16;
+  using V = f16x8;
+  using V4 = f16x4;
+  static constexpr float scale = kFp16Scale;
+  static __device__ __forceinline__ f32x4 mma(V a, V b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// --------------------------------------------------------------------------
+// photo-switching coefficient S_v[k][s] (eq. final-H with the rate written
+// per pulse as phi^gamma / tau)
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float scoef(const SwitchParams& sw, float phi, int k, int s) {
+  const float pg = (sw.gamma == 0.0f) ? 1.0f : powf(phi, sw.gamma);
+  return phi * (sw.a[s] + sw.b[s] * expf(-(float)k * pg * sw.inv_tau[s]));
+}
+
+__device__ __forceinline__ float coef_at(const SwitchParams& sw, const float* __restrict__ phi,
+                                         const float* __restrict__ stab, int kp, size_t col,
+                                         int z, int k, int s) {
+  if (stab) return stab[((size_t)z * kp + k) * sw.ns + s];
+  return scoef(sw, phi[col + z], k, s);
+}
+
+// b[k][y][x][z] = sum_s S[k][s] c[s][y][x][z] into the 16-bit octet operand.
+// One thread per (y, x, octet, pulse); pulses beyond K are written as zeros.
+template <int PREC, bool SPLIT>
+__global__ __launch_bounds__(256) void switch_fwd16(const float* __restrict__ c,
+                                                    const float* __restrict__ phi,
+                                                    const float* __restrict__ stab,
+                                                    SwitchParams sw,
+                                                    typename Half<PREC>::E* __restrict__ bq,
+                                                    typename Half<PREC>::E* __restrict__ bq_lo,
+                                                    int ny, int nx, int nz, int zo_n, int kp,
+                                                    int xp, int r, size_t ps) {
+  using H = Half<PREC>;
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)ny * nx * zo_n * kp;
+  if (tid >= total) return;
+  const int k = (int)(tid % kp);
+  size_t rest = tid / kp;
+  const int zo = (int)(rest % zo_n);
+  rest /= zo_n;
+  const int x = (int)(rest % nx);
+  const int y = (int)(rest / nx);
+  float b[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) b[j] = 0.0f;
+  if (k < sw.nk) {
+    const size_t col = ((size_t)y * nx + x) * nz;
+    for (int s = 0; s < sw.ns; ++s) {
+      const float* cs = c + (size_t)s * ny * nx * nz + col;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int z = zo * 8 + j;
+        if (z < nz) b[j] += coef_at(sw, phi, stab, kp, col, z, k, s) * cs[z];
+      }
+    }
+  }
+  typename H::V hi, lo;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float v = b[j] * H::scale;
+    hi[j] = (typename H::E)v;
+    lo[j] = (typename H::E)(v - (float)hi[j]);
+  }
+  const size_t o = ((size_t)(y + r) * xp + (x + r)) * ps + ((size_t)zo * kp + k) * 8;
+  *(typename H::V*)(bq + o) = hi;
+  if constexpr (SPLIT) *(typename H::V*)(bq_lo + o) = lo;
+}
+
+// FP32 operand [Yp][Xp][Nz][Kp]: one thread per (y, x, z, pulse), pulses fastest.
+__global__ __launch_bounds__(256) void switch_fwd32(const float* __restrict__ c,
+                                                    const float* __restrict__ phi,
+                                                    const float* __restrict__ stab,
+                                                    SwitchParams sw, float* __restrict__ bq,
+                                                    int ny, int nx, int nz, int kp, int xp,
+                                                    int r, size_t ps) {
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)ny * nx * nz * kp;
+  if (tid >= total) return;
+  const int k = (int)(tid % kp);
+  size_t rest = tid / kp;
+  const int z = (int)(rest % nz);
+  rest /= nz;
+  const int x = (int)(rest % nx);
+  const int y = (int)(rest / nx);
+  float b = 0.0f;
+  if (k < sw.nk) {
+    const size_t col = ((size_t)y * nx + x) * nz;
+    for (int s = 0; s < sw.ns; ++s)
+      b += coef_at(sw, phi, stab, kp, col, z, k, s) * c[(size_t)s * ny * nx * nz + col + z];
+  }
+  bq[((size_t)(y + r) * xp + (x + r)) * ps + (size_t)z * kp + k] = b;
+}
+
+// y[k][y][x][t] -> 16-bit octet operand of H^T at the padded position.
+template <int PREC, bool SPLIT>
+__global__ __launch_bounds__(256) void pack_r16(const float* __restrict__ yin,
+                                                typename Half<PREC>::E* __restrict__ rq,
+                                                typename Half<PREC>::E* __restrict__ rq_lo,
+                                                int nk, int ny, int nx, int nt, int to_n,
+                                                int kp, int xp, int r, size_t ps) {
+  using H = Half<PREC>;
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)ny * nx * to_n * kp;
+  if (tid >= total) return;
+  const int k = (int)(tid % kp);
+  size_t rest = tid / kp;
+  const int to = (int)(rest % to_n);
+  rest /= to_n;
+  const int x = (int)(rest % nx);
+  const int y = (int)(rest / nx);
+  typename H::V hi, lo;
+  const float* src = yin + (((size_t)k * ny + y) * nx + x) * nt;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int t = to * 8 + j;
+    const float v = (k < nk && t < nt) ? src[t] * H::scale : 0.0f;
+    hi[j] = (typename H::E)v;
+    lo[j] = (typename H::E)(v - (float)hi[j]);
+  }
+  const size_t o = ((size_t)(y + r) * xp + (x + r)) * ps + ((size_t)to * kp + k) * 8;
+  *(typename H::V*)(rq + o) = hi;
+  if constexpr (SPLIT) *(typename H::V*)(rq_lo + o) = lo;
+}
+
+// y[k][pos][t] -> rq[pos][t][k] (FP32), transposed through LDS, one block per position.
+__global__ __launch_bounds__(256) void pack_r32(const float* __restrict__ yin,
+                                                float* __restrict__ rq, int nk, int ny, int nx,
+                                                int nt, int lt, int kp, int xp, int r,
+                                                size_t ps) {
+  __shared__ float tile[64][65];
+  const int pos = blockIdx.x;
+  const int y = pos / nx, x = pos % nx;
+  float* dst = rq + ((size_t)(y + r) * xp + (x + r)) * ps;
+  for (int k0 = 0; k0 < kp; k0 += 64) {
+    for (int t0 = 0; t0 < lt; t0 += 64) {
+      for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+        const int kk = i / 64, tt = i % 64;
+        const int k = k0 + kk, t = t0 + tt;
+        tile[kk][tt] = (k < nk && t < nt) ? yin[(((size_t)k * ny + y) * nx + x) * nt + t] : 0.0f;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+        const int tt = i / 64, kk = i % 64;
+        const int k = k0 + kk, t = t0 + tt;
+        if (k < kp && t < lt) dst[(size_t)t * kp + k] = tile[kk][tt];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// band contraction
+// --------------------------------------------------------------------------
+struct BandArgs {
+  const void* q;
+  const void* q_lo;
+  const int* start;
+  const int* off;
+  const void* a;
+  const void* a_lo;
+  int n_mtiles, n_mblk, ny, nx, nxb, m_rows, xp;
+  size_t ps;
+  int nk, kp;
+  float inv_scale;
+  // epilogue
+  float* out;
+  const float* pmeas;
+  void* rq;
+  void* rq_lo;
+  size_t ps_r;
+  int r;
+  float rq_scale;
+  double* partial;
+  SwitchParams sw;
+  const float* phi;
+  const float* stab;
+  int nz, nt;
+};
+
+__device__ __forceinline__ void block_coords(const BandArgs& A, int& mtile, int& iy, int& ix0,
+                                             int& wid) {
+  const int nblocks = gridDim.x;
+  const int b = blockIdx.x;
+  // XCD-aware order: the hardware deals blocks to the 8 XCDs round-robin;
+  // give each XCD a contiguous range of the logical tile order so positions
+  // that share footprint data run on the same L2.
+  const int per = nblocks / 8;
+  int lin = b;
+  if (b < per * 8) lin = (b % 8) * per + b / 8;
+  const int mb = lin % A.n_mblk;
+  const int rest = lin / A.n_mblk;
+  const int xb = rest % A.nxb;
+  iy = rest / A.nxb;
+  const int wave = threadIdx.x >> 6;
+  mtile = mb * kWavesPerBlock + wave;
+  ix0 = xb * kPosPerWave;
+  wid = b * kWavesPerBlock + wave;
+}
+
+template <int NB>
+__device__ __forceinline__ void zero_acc(f32x4 (&acc)[kPosPerWave][NB]) {
+#pragma unroll
+  for (int p = 0; p < kPosPerWave; ++p)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[p][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Epilogue shared by the 16-bit and FP32 kernels (identical accumulator
+// layout: lane l holds rows 4*(l/16)..+3 of column l%16 = pulse).
+// RQ is the element type of the H^T operand written in mode 1.
+template <int MODE, int NB, typename RQE, int RQ_PREC, bool SPLIT>
+__device__ __forceinline__ void band_epilogue(const BandArgs& A,
+                                              f32x4 (&acc)[kPosPerWave][NB], int mtile,
+                                              int iy, int ix0, int wid) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, n = lane & 15;
+  const int row0 = mtile * 16 + 4 * g;
+  if constexpr (MODE == 0) {
+    const int nt = A.nt;
+#pragma unroll
+    for (int p = 0; p < kPosPerWave; ++p) {
+      const int ix = ix0 + p;
+      if (ix >= A.nx) continue;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int k = nb * 16 + n;
+        if (k >= A.nk) continue;
+        float* yo = A.out + (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
+        const f32x4 v = acc[p][nb] * A.inv_scale;
+        if ((nt & 3) == 0 && row0 + 3 < nt) {
+          *(f32x4*)yo = v;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (row0 + j < nt) yo[j] = v[j];
+        }
+      }
+    }
+  } else if constexpr (MODE == 1) {
+    const int nt = A.nt;
+    double ss = 0.0;
+#pragma unroll
+    for (int p = 0; p < kPosPerWave; ++p) {
+      const int ix = ix0 + p;
+      if (ix >= A.nx) continue;
+      const size_t pos = ((size_t)(iy + A.r) * A.xp + (ix + A.r)) * A.ps_r;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int k = nb * 16 + n;
+        if (k >= A.nk) continue;
+        const size_t yi = (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
+        float rv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool ok = row0 + j < nt;
+          float v = acc[p][nb][j] * A.inv_scale;
+          if (A.pmeas && ok) v -= A.pmeas[yi + j];
+          rv[j] = ok ? v : 0.0f;
+          ss += (double)rv[j] * (double)rv[j];
+        }
+        if constexpr (RQ_PREC == PSOAM_FP32) {
+          float* d = (float*)A.rq + pos + (size_t)row0 * A.kp + k;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) d[(size_t)j * A.kp] = rv[j];
+        } else {
+          using H = Half<RQ_PREC>;
+          typename H::V4 hi, lo;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float v = rv[j] * A.rq_scale;
+            hi[j] = (typename H::E)v;
+            lo[j] = (typename H::E)(v - (float)hi[j]);
+          }
+          const size_t o = pos + ((size_t)(row0 >> 3) * A.kp + k) * 8 + ((row0 >> 2) & 1) * 4;
+          *(typename H::V4*)((typename H::E*)A.rq + o) = hi;
+          if constexpr (SPLIT) *(typename H::V4*)((typename H::E*)A.rq_lo + o) = lo;
+        }
+      }
+    }
+    ss = wave_sum(ss);
+    if (lane == 0) A.partial[wid] = ss;
+  } else {
+    // c[s][iy][ix][z] = sum_k S[k][s] bh[k][z]: reduce over the 16 pulse lanes
+    const int nz = A.nz;
+#pragma unroll
+    for (int p = 0; p < kPosPerWave; ++p) {
+      const int ix = ix0 + p;
+      const int ixc = ix < A.nx ? ix : A.nx - 1;
+      const size_t col = ((size_t)iy * A.nx + ixc) * nz;
+      for (int s = 0; s < A.sw.ns; ++s) {
+        float v4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int k = nb * 16 + n;
+          if (k < A.nk) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int z = row0 + j;
+              if (z < nz)
+                v4[j] += coef_at(A.sw, A.phi, A.stab, A.kp, col, z, k, s) *
+                         (acc[p][nb][j] * A.inv_scale);
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+          for (int m = 8; m >= 1; m >>= 1) v4[j] += __shfl_xor(v4[j], m, 64);
+        }
+        if (n == 0 && ix < A.nx) {
+          float* co = A.out + ((size_t)s * A.ny * A.nx) * nz + col + row0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (row0 + j < nz) co[j] = v4[j];
+        }
+      }
+    }
+  }
+}
+
+template <int PREC, bool SPLIT, int NB, int MODE>
+__global__ __launch_bounds__(256) void band16(BandArgs A) {
+  using H = Half<PREC>;
+  using E = typename H::E;
+  using V = typename H::V;
+  int mtile, iy, ix0, wid;
+  block_coords(A, mtile, iy, ix0, wid);
+  const int lane = threadIdx.x & 63;
+  if (mtile >= A.n_mtiles) {
+    if (MODE == 1 && lane == 0) A.partial[wid] = 0.0;
+    return;
+  }
+  const int g = lane >> 4, n = lane & 15;
+  f32x4 acc[kPosPerWave][NB];
+  zero_acc<NB>(acc);
+  const int c0 = A.start[mtile], c1 = A.start[mtile + 1];
+  const size_t base = ((size_t)iy * A.xp + ix0) * A.ps + (size_t)n * 8;
+  const E* q = (const E*)A.q + base;
+  const E* qlo = SPLIT ? (const E*)A.q_lo + base : nullptr;
+  const V* av = (const V*)A.a;
+  const V* avlo = (const V*)A.a_lo;
+  for (int c = c0; c < c1; ++c) {
+    const int off = A.off[c * 4 + g];
+    const V a = av[(size_t)c * kWaveLanes + lane];
+    V alo{};
+    if constexpr (SPLIT) alo = avlo[(size_t)c * kWaveLanes + lane];
+    const E* qc = q + off;
+#pragma unroll
+    for (int p = 0; p < kPosPerWave; ++p) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const V b = *(const V*)(qc + p * A.ps + nb * 128);
+        acc[p][nb] = H::mma(a, b, acc[p][nb]);
+        if constexpr (SPLIT) {
+          const V blo = *(const V*)(qlo + off + p * A.ps + nb * 128);
+          acc[p][nb] = H::mma(a, blo, acc[p][nb]);
+          acc[p][nb] = H::mma(alo, b, acc[p][nb]);
+        }
+      }
+    }
+  }
+  band_epilogue<MODE, NB, E, PREC, SPLIT>(A, acc, mtile, iy, ix0, wid);
+}
+
+template <int NB, int MODE>
+__global__ __launch_bounds__(256) void band32(BandArgs A) {
+  int mtile, iy, ix0, wid;
+  block_coords(A, mtile, iy, ix0, wid);
+  const int lane = threadIdx.x & 63;
+  if (mtile >= A.n_mtiles) {
+    if (MODE == 1 && lane == 0) A.partial[wid] = 0.0;
+    return;
+  }
+  const int g = lane >> 4, n = lane & 15;
+  f32x4 acc[kPosPerWave][NB];
+  zero_acc<NB>(acc);
+  const int c0 = A.start[mtile], c1 = A.start[mtile + 1];
+  const float* q = (const float*)A.q + ((size_t)iy * A.xp + ix0) * A.ps + n;
+  const float* av = (const float*)A.a;
+  for (int c = c0; c < c1; ++c) {
+    const int off = A.off[c * 4 + g];
+    const float a = av[(size_t)c * kWaveLanes + lane];
+    const float* qc = q + off;
+#pragma unroll
+    for (int p = 0; p < kPosPerWave; ++p) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float b = qc[p * A.ps + nb * 16];
+        acc[p][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[p][nb], 0, 0, 0);
+      }
+    }
+  }
+  band_epilogue<MODE, NB, float, PSOAM_FP32, false>(A, acc, mtile, iy, ix0, wid);
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+static inline unsigned blocks_for(size_t n, unsigned bs = 256) {
+  return (unsigned)((n + bs - 1) / bs);
+}
+
+hipError_t launch_switch_fwd(const psoam_plan* P, const float* c, hipStream_t s) {
+  const auto& g = P->g;
+  const float* stab = P->d_stab;
+  switch (P->prec) {
+    case PSOAM_FP32: {
+      const size_t n = (size_t)g.ny * g.nx * g.nz * P->Kp;
+      hipLaunchKernelGGL(switch_fwd32, dim3(blocks_for(n)), dim3(256), 0, s, c, P->d_phi, stab,
+                         P->sw, (float*)P->d_bq, g.ny, g.nx, g.nz, P->Kp, P->Xp, P->R, P->ps_b);
+      break;
+    }
+#define PSOAM_SW16(PR, SP)                                                                  \
+  {                                                                                         \
+    using E = Half<PR>::E;                                                                  \
+    const size_t n = (size_t)g.ny * g.nx * (P->Lz / 8) * P->Kp;                            \
+    hipLaunchKernelGGL((switch_fwd16<PR, SP>), dim3(blocks_for(n)), dim3(256), 0, s, c,     \
+                       P->d_phi, stab, P->sw, (E*)P->d_bq, (E*)P->d_bq_lo, g.ny, g.nx,     \
+                       g.nz, P->Lz / 8, P->Kp, P->Xp, P->R, P->ps_b);                       \
+    break;                                                                                  \
+  }
+    case PSOAM_BF16: PSOAM_SW16(PSOAM_BF16, false)
+    case PSOAM_FP16: PSOAM_SW16(PSOAM_FP16, false)
+    case PSOAM_BF16_SPLIT: PSOAM_SW16(PSOAM_BF16, true)
+    case PSOAM_FP16_SPLIT: PSOAM_SW16(PSOAM_FP16, true)
+#undef PSOAM_SW16
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_r(const psoam_plan* P, const float* y, hipStream_t s) {
+  const auto& g = P->g;
+  switch (P->prec) {
+    case PSOAM_FP32:
+      hipLaunchKernelGGL(pack_r32, dim3(g.ny * g.nx), dim3(256), 0, s, y, (float*)P->d_rq,
+                         g.n_pulses, g.ny, g.nx, g.nt, P->Lt, P->Kp, P->Xp, P->R, P->ps_r);
+      break;
+#define PSOAM_PK16(PR, SP)                                                                  \
+  {                                                                                         \
+    using E = Half<PR>::E;                                                                  \
+    const size_t n = (size_t)g.ny * g.nx * (P->Lt / 8) * P->Kp;                            \
+    hipLaunchKernelGGL((pack_r16<PR, SP>), dim3(blocks_for(n)), dim3(256), 0, s, y,         \
+                       (E*)P->d_rq, (E*)P->d_rq_lo, g.n_pulses, g.ny, g.nx, g.nt, P->Lt / 8, \
+                       P->Kp, P->Xp, P->R, P->ps_r);                                        \
+    break;                                                                                  \
+  }
+    case PSOAM_BF16: PSOAM_PK16(PSOAM_BF16, false)
+    case PSOAM_FP16: PSOAM_PK16(PSOAM_FP16, false)
+    case PSOAM_BF16_SPLIT: PSOAM_PK16(PSOAM_BF16, true)
+    case PSOAM_FP16_SPLIT: PSOAM_PK16(PSOAM_FP16, true)
+#undef PSOAM_PK16
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+static size_t band_blocks(const psoam_plan* P, int mode) {
+  const BandTable& T = (mode == 2) ? P->adj : P->fwd;
+  const int n_mblk = (T.n_mtiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int nxb = (P->g.nx + kPosPerWave - 1) / kPosPerWave;
+  return (size_t)n_mblk * P->g.ny * nxb;
+}
+
+size_t band_partials(const psoam_plan* P, int mode) {
+  return band_blocks(P, mode) * kWavesPerBlock;
+}
+
+template <int MODE>
+static hipError_t launch_band_mode(const psoam_plan* P, BandArgs& A, dim3 grid, hipStream_t s) {
+  const int NB = P->NB;
+#define PSOAM_NB_CASES(KERNEL_T)                                                        \
+  switch (NB) {                                                                         \
+    case 1: hipLaunchKernelGGL((KERNEL_T<1, MODE>), grid, dim3(256), 0, s, A); break;   \
+    case 2: hipLaunchKernelGGL((KERNEL_T<2, MODE>), grid, dim3(256), 0, s, A); break;   \
+    case 3: hipLaunchKernelGGL((KERNEL_T<3, MODE>), grid, dim3(256), 0, s, A); break;   \
+    case 4: hipLaunchKernelGGL((KERNEL_T<4, MODE>), grid, dim3(256), 0, s, A); break;   \
+    default: return hipErrorInvalidValue;                                               \
+  }
+  switch (P->prec) {
+    case PSOAM_FP32: {
+      PSOAM_NB_CASES(band32)
+      break;
+    }
+#define PSOAM_B16(PR, SP)                                                                   \
+  {                                                                                         \
+    switch (NB) {                                                                           \
+      case 1: hipLaunchKernelGGL((band16<PR, SP, 1, MODE>), grid, dim3(256), 0, s, A); break; \
+      case 2: hipLaunchKernelGGL((band16<PR, SP, 2, MODE>), grid, dim3(256), 0, s, A); break; \
+      case 3: hipLaunchKernelGGL((band16<PR, SP, 3, MODE>), grid, dim3(256), 0, s, A); break; \
+      case 4: hipLaunchKernelGGL((band16<PR, SP, 4, MODE>), grid, dim3(256), 0, s, A); break; \
+      default: return hipErrorInvalidValue;                                                 \
+    }                                                                                       \
+    break;                                                                                  \
+  }
+    case PSOAM_BF16: PSOAM_B16(PSOAM_BF16, false)
+    case PSOAM_FP16: PSOAM_B16(PSOAM_FP16, false)
+    case PSOAM_BF16_SPLIT: PSOAM_B16(PSOAM_BF16, true)
+    case PSOAM_FP16_SPLIT: PSOAM_B16(PSOAM_FP16, true)
+#undef PSOAM_B16
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef PSOAM_NB_CASES
+  return hipGetLastError();
+}
+
+hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* pmeas,
+                       double* partial, hipStream_t s) {
+  const BandTable& T = (mode == 2) ? P->adj : P->fwd;
+  const bool split = P->prec == PSOAM_BF16_SPLIT || P->prec == PSOAM_FP16_SPLIT;
+  const bool fp16 = P->prec == PSOAM_FP16 || P->prec == PSOAM_FP16_SPLIT;
+  BandArgs A;
+  A.q = (mode == 2) ? P->d_rq : P->d_bq;
+  A.q_lo = (mode == 2) ? P->d_rq_lo : P->d_bq_lo;
+  A.start = T.d_start;
+  A.off = T.d_off;
+  A.a = T.d_a;
+  A.a_lo = split ? T.d_a_lo : nullptr;
+  A.n_mtiles = T.n_mtiles;
+  A.n_mblk = (T.n_mtiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  A.ny = P->g.ny;
+  A.nx = P->g.nx;
+  A.nxb = (P->g.nx + kPosPerWave - 1) / kPosPerWave;
+  A.m_rows = T.m_rows;
+  A.xp = P->Xp;
+  A.ps = (mode == 2) ? P->ps_r : P->ps_b;
+  A.nk = P->g.n_pulses;
+  A.kp = P->Kp;
+  A.inv_scale = fp16 ? 1.0f / kFp16Scale : 1.0f;
+  A.out = out;
+  A.pmeas = pmeas;
+  A.rq = P->d_rq;
+  A.rq_lo = P->d_rq_lo;
+  A.ps_r = P->ps_r;
+  A.r = P->R;
+  A.rq_scale = fp16 ? kFp16Scale : 1.0f;
+  A.partial = partial;
+  A.sw = P->sw;
+  A.phi = P->d_phi;
+  A.stab = P->d_stab;
+  A.nz = P->g.nz;
+  A.nt = P->g.nt;
+  const dim3 grid((unsigned)band_blocks(P, mode));
+  (void)split;
+  switch (mode) {
+    case 0: return launch_band_mode<0>(P, A, grid, s);
+    case 1: return launch_band_mode<1>(P, A, grid, s);
+    case 2: return launch_band_mode<2>(P, A, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// --------------------------------------------------------------------------
+// elementwise and prox kernels
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void prox_l1_kernel(float* __restrict__ x,
+                                                      const float* __restrict__ z, int64_t n,
+                                                      float th, int nonneg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float v = z[i];
+  if (nonneg) {
+    x[i] = fmaxf(v - th, 0.0f);
+  } else {
+    const float m = fmaxf(fabsf(v) - th, 0.0f);
+    x[i] = copysignf(m, v) * (m > 0.0f ? 1.0f : 0.0f);
+  }
+}
+
+hipError_t launch_prox_l1(float* x, const float* z, int64_t n, float thresh, int nonneg,
+                          hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(prox_l1_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0, s, x, z, n,
+                     thresh, nonneg);
+  return hipGetLastError();
+}
+
+struct Grid3 {
+  int ny, nx, nz;
+  int64_t sv;  // S * V
+};
+
+__device__ __forceinline__ float eta_at(const float* __restrict__ uc, const float* __restrict__ up,
+                                        float beta, int64_t i) {
+  if (!uc) return 0.0f;
+  const float a = uc[i];
+  return up ? a + beta * (a - up[i]) : a;
+}
+
+// (grad^T eta)[v] for component arrays laid out [3][S*V]
+__device__ __forceinline__ float gradT_at(const float* __restrict__ uc, const float* __restrict__ up,
+                                          float beta, const Grid3& G, int64_t v, int y, int x,
+                                          int z) {
+  const int64_t sx = G.nz, sy = (int64_t)G.nx * G.nz;
+  float acc = 0.0f;
+  // component 0: differences along y
+  if (y > 0) acc += eta_at(uc, up, beta, v - sy);
+  if (y < G.ny - 1) acc -= eta_at(uc, up, beta, v);
+  // component 1: along x
+  const float* uc1 = uc ? uc + G.sv : nullptr;
+  const float* up1 = up ? up + G.sv : nullptr;
+  if (x > 0) acc += eta_at(uc1, up1, beta, v - sx);
+  if (x < G.nx - 1) acc -= eta_at(uc1, up1, beta, v);
+  // component 2: along z
+  const float* uc2 = uc ? uc + 2 * G.sv : nullptr;
+  const float* up2 = up ? up + 2 * G.sv : nullptr;
+  if (z > 0) acc += eta_at(uc2, up2, beta, v - 1);
+  if (z < G.nz - 1) acc -= eta_at(uc2, up2, beta, v);
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void tv_w_kernel(float* __restrict__ w,
+                                                   const float* __restrict__ z,
+                                                   const float* __restrict__ uc,
+                                                   const float* __restrict__ up, float beta,
+                                                   Grid3 G) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= G.sv) return;
+  const int iz = (int)(v % G.nz);
+  const int ix = (int)((v / G.nz) % G.nx);
+  const int iy = (int)((v / ((int64_t)G.nz * G.nx)) % G.ny);
+  w[v] = z[v] - gradT_at(uc, up, beta, G, v, iy, ix, iz);
+}
+
+__global__ __launch_bounds__(256) void tv_u_kernel(float* __restrict__ un,
+                                                   const float* __restrict__ uc,
+                                                   const float* __restrict__ up, float beta,
+                                                   const float* __restrict__ w, float inv_mu,
+                                                   float theta, Grid3 G) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= G.sv) return;
+  const int iz = (int)(v % G.nz);
+  const int ix = (int)((v / G.nz) % G.nx);
+  const int iy = (int)((v / ((int64_t)G.nz * G.nx)) % G.ny);
+  const float wv = w[v];
+  const int64_t sx = G.nz, sy = (int64_t)G.nx * G.nz;
+  const float gy = (iy < G.ny - 1) ? w[v + sy] - wv : 0.0f;
+  const float gx = (ix < G.nx - 1) ? w[v + sx] - wv : 0.0f;
+  const float gz = (iz < G.nz - 1) ? w[v + 1] - wv : 0.0f;
+  const float* uc1 = uc ? uc + G.sv : nullptr;
+  const float* up1 = up ? up + G.sv : nullptr;
+  const float* uc2 = uc ? uc + 2 * G.sv : nullptr;
+  const float* up2 = up ? up + 2 * G.sv : nullptr;
+  un[v] = fminf(fmaxf(eta_at(uc, up, beta, v) + inv_mu * gy, -theta), theta);
+  un[G.sv + v] = fminf(fmaxf(eta_at(uc1, up1, beta, v) + inv_mu * gx, -theta), theta);
+  un[2 * G.sv + v] = fminf(fmaxf(eta_at(uc2, up2, beta, v) + inv_mu * gz, -theta), theta);
+}
+
+__global__ __launch_bounds__(256) void tv_final_kernel(float* __restrict__ x,
+                                                       const float* __restrict__ z,
+                                                       const float* __restrict__ u, int mode,
+                                                       float th1, Grid3 G) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= G.sv) return;
+  const int iz = (int)(v % G.nz);
+  const int ix = (int)((v / G.nz) % G.nx);
+  const int iy = (int)((v / ((int64_t)G.nz * G.nx)) % G.ny);
+  float r = z[v] - gradT_at(u, nullptr, 0.0f, G, v, iy, ix, iz);
+  if (mode == 1) r = fmaxf(r, 0.0f);
+  if (mode == 2) r = fmaxf(r - th1, 0.0f);
+  x[v] = r;
+}
+
+static Grid3 grid3(const psoam_plan* P) {
+  Grid3 G;
+  G.ny = P->g.ny;
+  G.nx = P->g.nx;
+  G.nz = P->g.nz;
+  G.sv = (int64_t)P->c_elems();
+  return G;
+}
+
+hipError_t launch_tv_w(const psoam_plan* P, float* w, const float* z, const float* u_cur,
+                       const float* u_prev, float beta, hipStream_t s) {
+  const Grid3 G = grid3(P);
+  hipLaunchKernelGGL(tv_w_kernel, dim3(blocks_for((size_t)G.sv)), dim3(256), 0, s, w, z, u_cur,
+                     u_prev, beta, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_tv_u(const psoam_plan* P, float* u_next, const float* u_cur,
+                       const float* u_prev, float beta, const float* w, float inv_mu,
+                       float theta, hipStream_t s) {
+  const Grid3 G = grid3(P);
+  hipLaunchKernelGGL(tv_u_kernel, dim3(blocks_for((size_t)G.sv)), dim3(256), 0, s, u_next,
+                     u_cur, u_prev, beta, w, inv_mu, theta, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_tv_final(const psoam_plan* P, float* x, const float* z, const float* u,
+                           int mode, float thresh1, hipStream_t s) {
+  const Grid3 G = grid3(P);
+  hipLaunchKernelGGL(tv_final_kernel, dim3(blocks_for((size_t)G.sv)), dim3(256), 0, s, x, z, u,
+                     mode, thresh1, G);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void axpby_kernel(float* __restrict__ out,
+                                                    const float* __restrict__ x,
+                                                    const float* __restrict__ y, float a,
+                                                    float b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * x[i] + b * y[i];
+}
+
+hipError_t launch_axpby(float* out, const float* x, const float* y, float a, float b, int64_t n,
+                        hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(axpby_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0, s, out, x, y, a, b,
+                     n);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(float* __restrict__ x, float v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+hipError_t launch_fill(float* x, float v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0, s, x, v, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reductions
+constexpr int kRedBlocks = 1024;
+
+size_t reduce_blocks(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (size_t)(b < kRedBlocks ? (b > 0 ? b : 1) : kRedBlocks);
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void dot_kernel(const float* __restrict__ x,
+                                                  const float* __restrict__ y, int64_t n,
+                                                  double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    acc += (double)x[i] * (double)y[i];
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ partial,
+                                                           int64_t n, double* __restrict__ out) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += partial[i];
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[0] = r;
+}
+
+hipError_t launch_dot(const float* x, const float* y, int64_t n, double* partial, double* out,
+                      hipStream_t s) {
+  const size_t nb = reduce_blocks(n);
+  hipLaunchKernelGGL(dot_kernel, dim3((unsigned)nb), dim3(256), 0, s, x, y, n, partial);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double* partial, size_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)n, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void tv_l1_kernel(const float* __restrict__ c, Grid3 G,
+                                                    double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double tvs = 0.0, l1 = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t sx = G.nz, sy = (int64_t)G.nx * G.nz;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < G.sv; v += stride) {
+    const int iz = (int)(v % G.nz);
+    const int ix = (int)((v / G.nz) % G.nx);
+    const int iy = (int)((v / ((int64_t)G.nz * G.nx)) % G.ny);
+    const float cv = c[v];
+    l1 += fabs((double)cv);
+    if (iy < G.ny - 1) tvs += fabs((double)c[v + sy] - (double)cv);
+    if (ix < G.nx - 1) tvs += fabs((double)c[v + sx] - (double)cv);
+    if (iz < G.nz - 1) tvs += fabs((double)c[v + 1] - (double)cv);
+  }
+  const double r0 = block_sum(tvs, sh);
+  const double r1 = block_sum(l1, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = r0;
+    partial[gridDim.x + blockIdx.x] = r1;
+  }
+}
+
+hipError_t launch_tv_l1_sums(const psoam_plan* P, const float* c, double* partial, double* out,
+                             hipStream_t s) {
+  const Grid3 G = grid3(P);
+  const size_t nb = reduce_blocks(G.sv);
+  hipLaunchKernelGGL(tv_l1_kernel, dim3((unsigned)nb), dim3(256), 0, s, c, G, partial);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial + nb, (int64_t)nb,
+                     out + 1);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void scale_rnorm_kernel(float* __restrict__ v,
+                                                          const float* __restrict__ w,
+                                                          const double* __restrict__ norm2,
+                                                          int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double inv = 1.0 / sqrt(norm2[0]);
+  v[i] = (float)((double)w[i] * inv);
+}
+
+hipError_t launch_scale_by_rnorm(float* v, const float* w, const double* norm2, int64_t n,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(scale_rnorm_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0, s, v, w,
+                     norm2, n);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void momentum_kernel(float* __restrict__ xi,
+                                                       const float* __restrict__ cn,
+                                                       const float* __restrict__ cp, float beta,
+                                                       int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double dd = 0.0, nn = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float a = cn[i];
+    const float xn = a + beta * (a - cp[i]);
+    const float xo = xi[i];
+    dd += ((double)xn - (double)xo) * ((double)xn - (double)xo);
+    nn += (double)xo * (double)xo;
+    xi[i] = xn;
+  }
+  const double r0 = block_sum(dd, sh);
+  const double r1 = block_sum(nn, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = r0;
+    partial[gridDim.x + blockIdx.x] = r1;
+  }
+}
+
+hipError_t launch_momentum(float* xi, const float* c_next, const float* c_prev, float beta,
+                           int64_t n, double* partial, hipStream_t s) {
+  const size_t nb = reduce_blocks(n);
+  hipLaunchKernelGGL(momentum_kernel, dim3((unsigned)nb), dim3(256), 0, s, xi, c_next, c_prev,
+                     beta, n, partial);
+  return hipGetLastError();
+}
+
+}  // namespace psoam

@@ -1,0 +1,345 @@
+// Plan construction: validation, photo-switching table, padded operand
+// buffers and the packing of the banded impulse response into matrix-core
+// tiles for H (output tiles over samples t) and H^T (output tiles over
+// depths z).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "psoam_internal.h"
+
+namespace psoam {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+inline uint16_t to_bf16(float f) {
+  // round to nearest even, NaN preserved
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+inline float from_bf16(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+inline uint16_t to_f16(float f) {
+  _Float16 h = (_Float16)f;  // host conversion rounds to nearest even
+  uint16_t u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
+
+inline float from_f16(uint16_t u) {
+  _Float16 h;
+  std::memcpy(&h, &u, 2);
+  return (float)h;
+}
+
+struct Group {
+  int jy, jx, l;  // lateral offset indices (already flipped for H^T) and contracted index
+};
+
+// Packs one direction.  `col_rows(jy, jx, l)` is not used; instead the caller
+// provides, per output tile, the groups and a function that fills the tile.
+struct Packer {
+  bool half;           // 16-bit octet groups (8 samples) or FP32 single samples
+  int prec;
+  std::vector<int> start;
+  std::vector<int> off;
+  std::vector<uint16_t> a16, a16lo;
+  std::vector<float> a32;
+};
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? PSOAM_ENOMEM : PSOAM_EHIP;
+}
+
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+// Build the table of one direction.
+//  dir 0 (H):   output rows t (tiles of 16 over Nt), contracted axis z
+//  dir 1 (H^T): output rows z (tiles of 16 over Nz), contracted axis t, offsets flipped
+static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* taps,
+                       BandTable& T) {
+  const auto& g = P->g;
+  const int F = P->F, W = P->W;
+  const bool half = P->prec != PSOAM_FP32;
+  const bool split = P->prec == PSOAM_BF16_SPLIT || P->prec == PSOAM_FP16_SPLIT;
+  const bool fp16 = P->prec == PSOAM_FP16 || P->prec == PSOAM_FP16_SPLIT;
+  const int out_len = dir == 0 ? g.nt : g.nz;
+  const int n_mt = (out_len + 15) / 16;
+  const int gw = half ? 8 : 1;                     // samples per group
+  const int lc = dir == 0 ? P->Lz : P->Lt;         // padded contracted length
+  const int n_l = lc / gw;                         // groups along the contracted axis
+  const size_t ps = dir == 0 ? P->ps_b : P->ps_r;
+  // mark[(tile*F + jy)*F + jx][l]
+  const size_t n_off = (size_t)F * F;
+  std::vector<uint8_t> mark((size_t)n_mt * n_off * n_l, 0);
+  size_t useful = 0;
+  for (int z = 0; z < g.nz; ++z)
+    for (int jdy = 0; jdy < F; ++jdy)
+      for (int jdx = 0; jdx < F; ++jdx) {
+        const size_t col = ((size_t)z * F + jdy) * F + jdx;
+        for (int j = 0; j < W; ++j) {
+          const float v = taps[col * W + j];
+          const int t = t0[col] + j;
+          if (v == 0.0f || t < 0 || t >= g.nt) continue;
+          ++useful;
+          int tile, jy, jx, l;
+          if (dir == 0) {
+            tile = t / 16; jy = jdy; jx = jdx; l = z / gw;
+          } else {
+            tile = z / 16; jy = F - 1 - jdy; jx = F - 1 - jdx; l = t / gw;
+          }
+          mark[((size_t)tile * n_off + (size_t)jy * F + jx) * n_l + l] = 1;
+        }
+      }
+  T.n_mtiles = n_mt;
+  T.m_rows = out_len;
+  T.useful_macs = useful;
+  T.h_start.assign(n_mt + 1, 0);
+  std::vector<Group> groups;
+  std::vector<int> tile_of_chunk;
+  std::vector<Group> chunk_groups;  // 4 per chunk
+  for (int tile = 0; tile < n_mt; ++tile) {
+    groups.clear();
+    for (int jy = 0; jy < F; ++jy)
+      for (int jx = 0; jx < F; ++jx)
+        for (int l = 0; l < n_l; ++l)
+          if (mark[((size_t)tile * n_off + (size_t)jy * F + jx) * n_l + l]) groups.push_back({jy, jx, l});
+    const int nch = (int)((groups.size() + 3) / 4);
+    T.h_start[tile + 1] = T.h_start[tile] + nch;
+    for (int i = 0; i < nch * 4; ++i)
+      chunk_groups.push_back(i < (int)groups.size() ? groups[i] : Group{-1, -1, -1});
+  }
+  const int n_chunks = T.h_start[n_mt];
+  T.n_chunks = n_chunks;
+  std::vector<int> off((size_t)n_chunks * 4, 0);
+  std::vector<float> vals((size_t)n_chunks * 64 * gw, 0.0f);  // lane-major packed values
+  for (int tile = 0; tile < n_mt; ++tile) {
+    for (int c = T.h_start[tile]; c < T.h_start[tile + 1]; ++c) {
+      for (int gi = 0; gi < 4; ++gi) {
+        const Group& G = chunk_groups[(size_t)c * 4 + gi];
+        if (G.jy < 0) continue;  // padding group: offset 0, zero band values
+        off[(size_t)c * 4 + gi] =
+            (int)(((size_t)G.jy * P->Xp + G.jx) * ps + (size_t)G.l * gw * P->Kp);
+        const int jdy = dir == 0 ? G.jy : F - 1 - G.jy;
+        const int jdx = dir == 0 ? G.jx : F - 1 - G.jx;
+        if (dir == 0) {
+          // rows t of the tile, contracted z in the group
+          for (int e = 0; e < gw; ++e) {
+            const int z = G.l * gw + e;
+            if (z >= g.nz) continue;
+            const size_t col = ((size_t)z * F + jdy) * F + jdx;
+            for (int j = 0; j < W; ++j) {
+              const int t = t0[col] + j;
+              if (t < tile * 16 || t >= tile * 16 + 16 || t >= g.nt) continue;
+              const int lane = 16 * gi + (t - tile * 16);
+              vals[((size_t)c * 64 + lane) * gw + e] = taps[col * W + j];
+            }
+          }
+        } else {
+          // rows z of the tile, contracted t in the group
+          for (int zi = 0; zi < 16; ++zi) {
+            const int z = tile * 16 + zi;
+            if (z >= g.nz) continue;
+            const size_t col = ((size_t)z * F + jdy) * F + jdx;
+            for (int j = 0; j < W; ++j) {
+              const int t = t0[col] + j;
+              if (t < 0 || t >= g.nt || t / gw != G.l) continue;
+              const int lane = 16 * gi + zi;
+              vals[((size_t)c * 64 + lane) * gw + (t - G.l * gw)] = taps[col * W + j];
+            }
+          }
+        }
+      }
+    }
+  }
+  // upload
+  PSOAM_HIP(hipMalloc(&T.d_start, sizeof(int) * (n_mt + 1)));
+  PSOAM_HIP(hipMemcpy(T.d_start, T.h_start.data(), sizeof(int) * (n_mt + 1), hipMemcpyHostToDevice));
+  const size_t nc = n_chunks > 0 ? (size_t)n_chunks : 1;
+  PSOAM_HIP(hipMalloc(&T.d_off, sizeof(int) * 4 * nc));
+  if (n_chunks) PSOAM_HIP(hipMemcpy(T.d_off, off.data(), sizeof(int) * 4 * n_chunks, hipMemcpyHostToDevice));
+  if (!half) {
+    PSOAM_HIP(hipMalloc(&T.d_a, sizeof(float) * 64 * nc));
+    if (n_chunks) PSOAM_HIP(hipMemcpy(T.d_a, vals.data(), sizeof(float) * 64 * n_chunks, hipMemcpyHostToDevice));
+  } else {
+    std::vector<uint16_t> hi(vals.size()), lo(vals.size());
+    for (size_t i = 0; i < vals.size(); ++i) {
+      if (fp16) {
+        hi[i] = to_f16(vals[i]);
+        lo[i] = to_f16(vals[i] - from_f16(hi[i]));
+      } else {
+        hi[i] = to_bf16(vals[i]);
+        lo[i] = to_bf16(vals[i] - from_bf16(hi[i]));
+      }
+    }
+    PSOAM_HIP(hipMalloc(&T.d_a, sizeof(uint16_t) * 512 * nc));
+    if (n_chunks) PSOAM_HIP(hipMemcpy(T.d_a, hi.data(), sizeof(uint16_t) * 512 * n_chunks, hipMemcpyHostToDevice));
+    if (split) {
+      PSOAM_HIP(hipMalloc(&T.d_a_lo, sizeof(uint16_t) * 512 * nc));
+      if (n_chunks) PSOAM_HIP(hipMemcpy(T.d_a_lo, lo.data(), sizeof(uint16_t) * 512 * n_chunks, hipMemcpyHostToDevice));
+    }
+  }
+  return PSOAM_OK;
+}
+
+static void free_table(BandTable& T) {
+  if (T.d_start) (void)hipFree(T.d_start);
+  if (T.d_off) (void)hipFree(T.d_off);
+  if (T.d_a) (void)hipFree(T.d_a);
+  if (T.d_a_lo) (void)hipFree(T.d_a_lo);
+  T.d_start = nullptr;
+  T.d_off = nullptr;
+  T.d_a = T.d_a_lo = nullptr;
+}
+
+void free_plan(psoam_plan* P) {
+  if (!P) return;
+  (void)hipSetDevice(P->device);
+  (void)hipDeviceSynchronize();
+  free_table(P->fwd);
+  free_table(P->adj);
+  void* bufs[] = {P->d_phi, P->d_stab, P->d_bq, P->d_bq_lo, P->d_rq, P->d_rq_lo,
+                  P->solve_ws.base, P->d_partial, P->d_scalars};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete P;
+}
+
+int create_plan(const psoam_geom* gp, const psoam_species* sp, const float* phi,
+                const int32_t* t0, const float* taps, int32_t sir_w, int32_t prec,
+                hipStream_t stream, psoam_plan** out) {
+  if (!out) return fail(PSOAM_EINVAL, "plan_create: out is NULL");
+  *out = nullptr;
+  if (!gp || !sp || !phi || !t0 || !taps) return fail(PSOAM_EINVAL, "plan_create: NULL argument");
+  const psoam_geom g = *gp;
+  if (g.nx <= 0 || g.ny <= 0 || g.nz <= 0 || g.nt <= 0 || g.n_pulses <= 0)
+    return fail(PSOAM_EINVAL, "plan_create: sizes must be positive");
+  if (g.f <= 0 || (g.f % 2) == 0) return fail(PSOAM_EINVAL, "plan_create: footprint f must be odd and positive");
+  if (g.n_species < 1 || g.n_species > kMaxSpecies)
+    return fail(PSOAM_EINVAL, "plan_create: n_species must be in 1..8");
+  if (sir_w < 1 || sir_w > 64) return fail(PSOAM_EINVAL, "plan_create: sir_w must be in 1..64");
+  if (g.phi_per_voxel != 0 && g.phi_per_voxel != 1)
+    return fail(PSOAM_EINVAL, "plan_create: phi_per_voxel must be 0 or 1");
+  if (prec < PSOAM_FP32 || prec > PSOAM_FP16_SPLIT)
+    return fail(PSOAM_EUNSUPPORTED, "plan_create: unknown precision");
+  if (g.n_pulses > 64) return fail(PSOAM_EUNSUPPORTED, "plan_create: at most 64 pulses");
+  for (int s = 0; s < g.n_species; ++s) {
+    if (!std::isfinite(sp->a[s]) || !std::isfinite(sp->b[s]) || !(sp->tau[s] > 0.0) ||
+        !std::isfinite(sp->tau[s]))
+      return fail(PSOAM_EINVAL, "plan_create: species constants must be finite, tau > 0");
+  }
+  if (!std::isfinite(sp->gamma)) return fail(PSOAM_EINVAL, "plan_create: gamma not finite");
+  const size_t nphi = g.phi_per_voxel ? (size_t)g.ny * g.nx * g.nz : (size_t)g.nz;
+  for (size_t i = 0; i < nphi; ++i)
+    if (!(phi[i] > 0.0f) || !std::isfinite(phi[i])) return fail(PSOAM_EINVAL, "plan_create: phi must be finite and > 0");
+  const size_t ntab = (size_t)g.nz * g.f * g.f;
+  for (size_t i = 0; i < ntab * sir_w; ++i)
+    if (!std::isfinite(taps[i])) return fail(PSOAM_EINVAL, "plan_create: non-finite impulse-response tap");
+  for (size_t i = 0; i < ntab; ++i)
+    if (t0[i] < -(1 << 28) || t0[i] > (1 << 28)) return fail(PSOAM_EINVAL, "plan_create: band start out of range");
+
+  psoam_plan* P = new (std::nothrow) psoam_plan();
+  if (!P) return fail(PSOAM_ENOMEM, "plan_create: host allocation failed");
+  P->g = g;
+  P->sp_in = *sp;
+  P->prec = prec;
+  P->F = g.f;
+  P->R = (g.f - 1) / 2;
+  P->W = sir_w;
+  P->Kp = (g.n_pulses + 15) / 16 * 16;
+  P->NB = P->Kp / 16;
+  P->Yp = g.ny + 2 * P->R;
+  P->Xp = (g.nx + kPadX - 1) / kPadX * kPadX + 2 * P->R;
+  const bool half = prec != PSOAM_FP32;
+  const bool split = prec == PSOAM_BF16_SPLIT || prec == PSOAM_FP16_SPLIT;
+  P->Lz = half ? (g.nz + 7) / 8 * 8 : g.nz;
+  P->Lt = (g.nt + 15) / 16 * 16;
+  P->ps_b = (size_t)P->Lz * P->Kp;
+  P->ps_r = (size_t)P->Lt * P->Kp;
+  (void)hipGetDevice(&P->device);
+  auto& sw = P->sw;
+  sw.ns = g.n_species;
+  sw.nk = g.n_pulses;
+  sw.per_voxel = g.phi_per_voxel;
+  sw.gamma = (float)sp->gamma;
+  for (int s = 0; s < kMaxSpecies; ++s) {
+    sw.a[s] = s < g.n_species ? (float)sp->a[s] : 0.0f;
+    sw.b[s] = s < g.n_species ? (float)sp->b[s] : 0.0f;
+    sw.inv_tau[s] = s < g.n_species ? (float)(1.0 / sp->tau[s]) : 0.0f;
+  }
+  int rc = PSOAM_OK;
+  auto bail = [&](int code) {
+    free_plan(P);
+    return code;
+  };
+#define PLAN_HIP(call)                                  \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return bail(hip_fail(_e, #call)); \
+  } while (0)
+  PLAN_HIP(hipMalloc(&P->d_phi, sizeof(float) * nphi));
+  PLAN_HIP(hipMemcpy(P->d_phi, phi, sizeof(float) * nphi, hipMemcpyHostToDevice));
+  if (!g.phi_per_voxel) {
+    // per-depth switching table S[z][k][s] (zero for padded pulses), computed in double
+    std::vector<float> st((size_t)g.nz * P->Kp * g.n_species, 0.0f);
+    for (int z = 0; z < g.nz; ++z)
+      for (int k = 0; k < g.n_pulses; ++k)
+        for (int s = 0; s < g.n_species; ++s) {
+          const double ph = phi[z];
+          const double pg = sp->gamma == 0.0 ? 1.0 : std::pow(ph, sp->gamma);
+          st[((size_t)z * P->Kp + k) * g.n_species + s] =
+              (float)(ph * (sp->a[s] + sp->b[s] * std::exp(-(double)k * pg / sp->tau[s])));
+        }
+    PLAN_HIP(hipMalloc(&P->d_stab, sizeof(float) * st.size()));
+    PLAN_HIP(hipMemcpy(P->d_stab, st.data(), sizeof(float) * st.size(), hipMemcpyHostToDevice));
+  }
+  const size_t esz = half ? 2 : 4;
+  P->bq_bytes = (size_t)P->Yp * P->Xp * P->ps_b * esz;
+  P->rq_bytes = (size_t)P->Yp * P->Xp * P->ps_r * esz;
+  PLAN_HIP(hipMalloc(&P->d_bq, P->bq_bytes));
+  PLAN_HIP(hipMalloc(&P->d_rq, P->rq_bytes));
+  PLAN_HIP(hipMemsetAsync(P->d_bq, 0, P->bq_bytes, stream));
+  PLAN_HIP(hipMemsetAsync(P->d_rq, 0, P->rq_bytes, stream));
+  if (split) {
+    PLAN_HIP(hipMalloc(&P->d_bq_lo, P->bq_bytes));
+    PLAN_HIP(hipMalloc(&P->d_rq_lo, P->rq_bytes));
+    PLAN_HIP(hipMemsetAsync(P->d_bq_lo, 0, P->bq_bytes, stream));
+    PLAN_HIP(hipMemsetAsync(P->d_rq_lo, 0, P->rq_bytes, stream));
+  }
+  rc = build_table(P, 0, t0, taps, P->fwd);
+  if (rc != PSOAM_OK) return bail(rc);
+  rc = build_table(P, 1, t0, taps, P->adj);
+  if (rc != PSOAM_OK) return bail(rc);
+  PLAN_HIP(hipStreamSynchronize(stream));
+#undef PLAN_HIP
+  *out = P;
+  return PSOAM_OK;
+}
+
+}  // namespace psoam

@@ -1,0 +1,239 @@
+"""GPU parity: the HIP path against the FP64 oracle on the same seeded inputs.
+
+Tolerances are normwise relative errors (the paper's NRMSE).  FP32 matrix
+cores with float32 accumulation: 1e-5 for the operators (the FP32
+configuration's stated tolerance).  BF16/FP16 round both operands to 8/11
+significant bits, so one product carries up to 2^-8 / 2^-11 relative error
+and a sum of independent such errors is of that order normwise: 8e-3 (BF16),
+1.5e-3 (FP16); the split forms keep ~16 bits: 2e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import lib_plan, oracle_S, ragged_cfg, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TOL_OP = {"fp32": 1e-5, "bf16": 8e-3, "fp16": 1.5e-3, "bf16_split": 2e-5, "fp16_split": 2e-5}
+
+
+@pytest.fixture(scope="module")
+def c1():
+    cfg = synth.C1
+    c_true, t0, taps, phi, sp, n0, v0 = synth.inputs(cfg)
+    S = oracle_S(cfg, phi, sp)
+    return cfg, c_true, t0, taps, phi, sp, n0, v0, S
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16_split", "fp16_split"])
+def test_apply_A_and_AT_C1(c1, prec):
+    torch = torch_cuda()
+    cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
+    say(f"[parity] C1 apply_A/AT prec={prec}")
+    plan = lib_plan(cfg, t0, taps, phi, sp, prec)
+    c = torch.from_numpy(c_true).cuda()
+    y = plan.apply_A(c)
+    y_ref = oracle.apply_A(c_true, S, t0, taps, cfg.nt)
+    e = oracle.rel_err(y.cpu().numpy(), y_ref)
+    say(f"   rel err A = {e:.3e}")
+    assert e <= TOL_OP[prec]
+    yr = np.random.default_rng(1).standard_normal(cfg.y_shape).astype(np.float32)
+    g = plan.apply_AT(torch.from_numpy(yr).cuda())
+    g_ref = oracle.apply_AT(yr, S, t0, taps, cfg.nz)
+    e = oracle.rel_err(g.cpu().numpy(), g_ref)
+    say(f"   rel err AT = {e:.3e}")
+    assert e <= TOL_OP[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16_split", "fp16"])
+def test_ragged_random_table(prec):
+    """Sizes off every tile boundary, per-voxel fluence with the fluence-
+    dependent rate, asymmetric random band running off both ends."""
+    torch = torch_cuda()
+    cfg, t0, taps, phi, sp = ragged_cfg(3)
+    say(f"[parity] ragged prec={prec}")
+    S = oracle_S(cfg, phi, sp)
+    plan = lib_plan(cfg, t0, taps, phi, sp, prec)
+    rng = np.random.default_rng(4)
+    c = rng.standard_normal(cfg.c_shape).astype(np.float32)
+    y = plan.apply_A(torch.from_numpy(c).cuda()).cpu().numpy()
+    e = oracle.rel_err(y, oracle.apply_A(c, S, t0, taps, cfg.nt))
+    say(f"   rel err A = {e:.3e}")
+    assert e <= TOL_OP[prec]
+    yr = rng.standard_normal(cfg.y_shape).astype(np.float32)
+    g = plan.apply_AT(torch.from_numpy(yr).cuda()).cpu().numpy()
+    e = oracle.rel_err(g, oracle.apply_AT(yr, S, t0, taps, cfg.nz))
+    say(f"   rel err AT = {e:.3e}")
+    assert e <= TOL_OP[prec]
+
+
+def test_point_source_fp32(c1):
+    """A unit voxel gives the synthesised impulse response times the switching
+    curve at every scan of its footprint (checked against the oracle's
+    element-wise definition)."""
+    torch = torch_cuda()
+    cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
+    plan = lib_plan(cfg, t0, taps, phi, sp, "fp32")
+    c = np.zeros(cfg.c_shape, np.float32)
+    c[1, 3, 30, 9] = 1.0   # near a lateral border
+    y = plan.apply_A(torch.from_numpy(c).cuda()).cpu().numpy()
+    y_ref = oracle.apply_A(c, S, t0, taps, cfg.nt)
+    assert oracle.rel_err(y, y_ref) <= 1e-6
+    assert np.count_nonzero(y[:, 10:, :20]) == 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_dot_product_identity(c1, prec):
+    torch = torch_cuda()
+    cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
+    plan = lib_plan(cfg, t0, taps, phi, sp, prec)
+    rng = np.random.default_rng(7)
+    x = torch.from_numpy(rng.standard_normal(cfg.c_shape).astype(np.float32)).cuda()
+    yv = torch.from_numpy(rng.standard_normal(cfg.y_shape).astype(np.float32)).cuda()
+    lhs = float((plan.apply_A(x).double() * yv.double()).sum())
+    rhs = float((x.double() * plan.apply_AT(yv).double()).sum())
+    scale = float(plan.apply_A(x).double().norm() * yv.double().norm())
+    say(f"[parity] dot test {prec}: |lhs-rhs|/scale = {abs(lhs - rhs) / scale:.3e}")
+    assert abs(lhs - rhs) <= (1e-6 if prec == "fp32" else 2e-3) * scale
+
+
+def test_prox_l1_matches_closed_form():
+    torch = torch_cuda()
+    import paper_2510_23739_amd as pk
+    z = np.random.default_rng(2).standard_normal(100003).astype(np.float32)
+    z[:5] = [0.25, -0.25, 0.0, 0.2500001, -0.2499999]
+    th = np.float32(0.25)
+    zt = torch.from_numpy(z).cuda()
+    x1 = pk.prox_l1(zt, float(th), nonneg=True).cpu().numpy()
+    np.testing.assert_array_equal(x1, np.maximum(z - th, np.float32(0)))
+    x2 = pk.prox_l1(zt, float(th), nonneg=False).cpu().numpy()
+    ref = np.sign(z) * np.maximum(np.abs(z) - th, np.float32(0))
+    np.testing.assert_array_equal(x2, ref.astype(np.float32))
+    # in place
+    pk.prox_l1(zt, float(th), nonneg=True, x=zt)
+    np.testing.assert_array_equal(zt.cpu().numpy(), x1)
+
+
+@pytest.mark.parametrize("n_inner,theta,nonneg", [(20, 0.05, False), (50, 0.3, True), (0, 0.1, True), (7, 0.0, False)])
+def test_prox_tv_matches_oracle(c1, n_inner, theta, nonneg):
+    torch = torch_cuda()
+    cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
+    plan = lib_plan(cfg, t0, taps, phi, sp, "fp32")
+    z = (c_true + 0.2 * np.random.default_rng(5).standard_normal(cfg.c_shape)).astype(np.float32)
+    x = plan.prox_tv(torch.from_numpy(z).cuda(), theta, n_inner, nonneg=nonneg).cpu().numpy()
+    ref = oracle.prox_tv(z, theta, n_inner, nonneg=nonneg)
+    e = oracle.rel_err(x, ref)
+    say(f"[parity] prox_tv K2={n_inner} theta={theta}: rel err {e:.3e}")
+    assert e <= 1e-5
+
+
+def test_prox_tv_ragged_inplace():
+    torch = torch_cuda()
+    cfg, t0, taps, phi, sp = ragged_cfg(1)
+    plan = lib_plan(cfg, t0, taps, phi, sp, "fp32")
+    z = np.random.default_rng(8).standard_normal(cfg.c_shape).astype(np.float32)
+    zt = torch.from_numpy(z).cuda()
+    plan.prox_tv(zt, 0.2, 25, nonneg=False, x=zt)
+    e = oracle.rel_err(zt.cpu().numpy(), oracle.prox_tv(z, 0.2, 25))
+    assert e <= 1e-5
+
+
+def _c1_problem(c1):
+    cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
+    y_clean = oracle.apply_A(c_true.astype(np.float64), S, t0, taps, cfg.nt)
+    sig = synth.noise_sigma(float(np.sqrt(np.mean(y_clean ** 2))))
+    p = (y_clean + sig * n0).astype(np.float32)
+    A = lambda v: oracle.apply_A(v, S, t0, taps, cfg.nt)
+    AT = lambda w: oracle.apply_AT(w, S, t0, taps, cfg.nz)
+    aty = np.abs(AT(p.astype(np.float64))).max()
+    lam_tv, lam_l1 = 5e-3 * aty, 1e-2 * aty
+    return p, A, AT, lam_tv, lam_l1
+
+
+def test_power_iteration_matches_oracle(c1):
+    torch = torch_cuda()
+    cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
+    p, A, AT, lam_tv, lam_l1 = _c1_problem(c1)
+    lam_ref = oracle.power_iteration(A, AT, v0, 30)
+    plan = lib_plan(cfg, t0, taps, phi, sp, "fp32")
+    _, st = plan.solve(torch.from_numpy(p).cuda(), k1=0, n_power=30,
+                       v0=torch.from_numpy(v0).cuda())
+    say(f"[parity] power iteration: gpu {st['lambda_max']:.8e} oracle {lam_ref:.8e}")
+    assert st["lambda_max"] == pytest.approx(lam_ref, rel=1e-5)
+    assert st["alpha1"] == pytest.approx(1.0 / (1.01 * lam_ref), rel=1e-5)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16_split", 1e-4), ("bf16", 1e-2)])
+def test_fista_C1_matches_oracle(c1, prec, tol):
+    """C1 end to end: 20 FISTA iterations, 20 dual TV iterations, TV + l1 +
+    nonnegativity, the oracle's step passed in; concentrations compared."""
+    torch = torch_cuda()
+    cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
+    p, A, AT, lam_tv, lam_l1 = _c1_problem(c1)
+    lam = oracle.power_iteration(A, AT, v0, 30)
+    alpha1 = 1.0 / (1.01 * lam)
+    c_ref, it = oracle.fista(p.astype(np.float64), A, AT, alpha1, lam_tv, lam_l1, cfg.k1, cfg.k2,
+                             shape_c=cfg.c_shape)
+    plan = lib_plan(cfg, t0, taps, phi, sp, prec)
+    c, st = plan.solve(torch.from_numpy(p).cuda(), lambda_tv=lam_tv, lambda_l1=lam_l1,
+                       k1=cfg.k1, k2=cfg.k2, alpha1=alpha1)
+    e = oracle.rel_err(c.cpu().numpy(), c_ref)
+    say(f"[parity] FISTA C1 {prec}: iterations {st['iterations']} rel err c = {e:.3e}")
+    assert st["iterations"] == cfg.k1
+    assert e <= tol
+    # the reconstruction moved toward the phantom
+    assert oracle.rel_err(c.cpu().numpy(), c_true) < 1.0
+
+
+def test_fista_trace_and_stopping(c1):
+    torch = torch_cuda()
+    cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
+    p, A, AT, lam_tv, lam_l1 = _c1_problem(c1)
+    lam = oracle.power_iteration(A, AT, v0, 30)
+    alpha1 = 1.0 / (1.01 * lam)
+    tr_ref = []
+    oracle.fista(p.astype(np.float64), A, AT, alpha1, lam_tv, lam_l1, 6, 10, trace=tr_ref,
+                 shape_c=cfg.c_shape)
+    plan = lib_plan(cfg, t0, taps, phi, sp, "fp32")
+    _, st, tr = plan.solve(torch.from_numpy(p).cuda(), lambda_tv=lam_tv, lambda_l1=lam_l1, k1=6,
+                           k2=10, alpha1=alpha1, trace=True)
+    np.testing.assert_allclose(tr, tr_ref, rtol=1e-5)
+    _, it_ref = oracle.fista(p.astype(np.float64), A, AT, alpha1, 0.0, 0.0, 400, 1, eps2=1e-3,
+                             shape_c=cfg.c_shape)
+    _, st2 = plan.solve(torch.from_numpy(p).cuda(), k1=400, k2=1, alpha1=alpha1, eps2=1e-3)
+    say(f"[parity] eps2 stop: gpu {st2['iterations']} oracle {it_ref}")
+    assert abs(st2["iterations"] - it_ref) <= 1
+
+
+def test_autograd_backward_is_adjoint(c1):
+    """torch.autograd through A: the gradient of 1/2|A c - p|^2 equals
+    A^T (A c - p) of the oracle; central differences agree (the objective is
+    quadratic, so only rounding remains)."""
+    torch = torch_cuda()
+    import paper_2510_23739_amd as pk
+    cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
+    p, A, AT, lam_tv, lam_l1 = _c1_problem(c1)
+    plan = lib_plan(cfg, t0, taps, phi, sp, "fp32")
+    c0 = (0.5 * c_true).astype(np.float32)
+    c = torch.from_numpy(c0).cuda().requires_grad_(True)
+    pt = torch.from_numpy(p).cuda()
+    loss = 0.5 * ((pk.A(c, plan) - pt) ** 2).sum()
+    loss.backward()
+    g_ref = AT(A(c0.astype(np.float64)) - p)
+    e = oracle.rel_err(c.grad.cpu().numpy(), g_ref)
+    say(f"[parity] autograd gradient rel err {e:.3e}")
+    assert e <= 1e-5
+    # central differences along the gradient direction, in float64 on the loss
+    d = torch.from_numpy(g_ref / np.linalg.norm(g_ref)).float().cuda()
+    h = 1e-2 * float(np.linalg.norm(c0))
+
+    def f(cc):
+        r = plan.apply_A(cc.contiguous()).double() - pt.double()
+        return 0.5 * float((r * r).sum())
+    with torch.no_grad():
+        fd = (f(c + h * d) - f(c - h * d)) / (2 * h)
+    an = float((c.grad.double() * d.double()).sum())
+    say(f"[parity] finite difference {fd:.8e} analytic {an:.8e}")
+    assert fd == pytest.approx(an, rel=1e-5)
