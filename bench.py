@@ -65,7 +65,8 @@ def time_events(torch, fn, reps):
 def cpu_baseline(cfg, t0, taps, phi, sp, crop, steps_hint):
     """The FP64 oracle, as it stands, timed on the host for one solver step
     (A, A^T, TV prox with K2 inner steps, l1, momentum) on a crop x crop
-    lateral sample of the same geometry; scaled linearly in scan positions."""
+    lateral sample of the same geometry; scaled by the number of (scan,
+    offset) pairs evaluated, which is what the oracle's time follows."""
     import oracle
     import synth
     try:
@@ -82,12 +83,17 @@ def cpu_baseline(cfg, t0, taps, phi, sp, crop, steps_hint):
     t = time.perf_counter()
     oracle.fista(p, A, AT, 1e-3, 1e-3, 1e-3, 1, cfg.k2, c_init=c)
     dt = time.perf_counter() - t
-    scale = (cfg.nx * cfg.ny) / float(crop * crop)
+
+    def pairs(n):
+        # (scan, offset) pairs with the voxel inside an n-wide grid, per axis
+        return sum(max(0, n - abs(d)) for d in range(-cfg.r, cfg.r + 1))
+    scale = (pairs(cfg.nx) * pairs(cfg.ny)) / float(pairs(crop) ** 2)
     step_s = dt * scale
     return {"value": 1.0 / step_s, "unit": "A+AT applies/s", "cores": int(cores), "kind": "oracle",
             "sample": (f"one FP64 oracle solver step (A, A^T, TV prox K2={cfg.k2}, l1, momentum) on a "
                        f"{crop}x{crop}-scan lateral crop (full Nz, K, Nt, F), {dt:.1f} s, scaled "
-                       f"x{scale:.1f} to {cfg.nx}x{cfg.ny} scans (extrapolated)")}
+                       f"x{scale:.1f} by the number of (scan, offset) pairs to {cfg.nx}x{cfg.ny} "
+                       f"scans (extrapolated)")}
 
 
 def run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1, prec,

@@ -252,12 +252,10 @@ __device__ __forceinline__ void block_coords(const BandArgs& A, int& mtile, int&
   wid = b * kWavesPerBlock + wave;
 }
 
-template <int NB>
-__device__ __forceinline__ void zero_acc(f32x4 (&acc)[kPosPerWave][NB]) {
+template <int NP>
+__device__ __forceinline__ void zero_acc(f32x4 (&acc)[NP]) {
 #pragma unroll
-  for (int p = 0; p < kPosPerWave; ++p)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[p][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int p = 0; p < NP; ++p) acc[p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -266,101 +264,88 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Epilogue shared by the 16-bit and FP32 kernels (identical accumulator
-// layout: lane l holds rows 4*(l/16)..+3 of column l%16 = pulse).
-// RQ is the element type of the H^T operand written in mode 1.
-template <int MODE, int NB, typename RQE, int RQ_PREC, bool SPLIT>
-__device__ __forceinline__ void band_epilogue(const BandArgs& A,
-                                              f32x4 (&acc)[kPosPerWave][NB], int mtile,
-                                              int iy, int ix0, int wid) {
+// Epilogue of one 16-pulse block for NP consecutive positions, shared by all
+// band kernels (identical accumulator layout: lane l holds output rows
+// 4*(l/16)..+3 of column l%16 = pulse kbase + l%16).
+//  mode 0: y rows written;  mode 1: r = y - p into the H^T operand, sum r^2
+//  into ss;  mode 2: c[s] (+)= sum_k S[k][s] bh[k] (first block writes, later
+//  blocks add, always by the same lane, so the order is fixed).
+template <int MODE, int NP, int RQ_PREC, bool SPLIT>
+__device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[NP], int mtile,
+                                          int iy, int ix0, int kbase, bool first, double& ss) {
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, n = lane & 15;
   const int row0 = mtile * 16 + 4 * g;
+  const int k = kbase + n;
   if constexpr (MODE == 0) {
     const int nt = A.nt;
+    if (k >= A.nk) return;
 #pragma unroll
-    for (int p = 0; p < kPosPerWave; ++p) {
+    for (int p = 0; p < NP; ++p) {
       const int ix = ix0 + p;
       if (ix >= A.nx) continue;
+      float* yo = A.out + (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
+      const f32x4 v = acc[p] * A.inv_scale;
+      if ((nt & 3) == 0 && row0 + 3 < nt) {
+        *(f32x4*)yo = v;
+      } else {
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int k = nb * 16 + n;
-        if (k >= A.nk) continue;
-        float* yo = A.out + (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
-        const f32x4 v = acc[p][nb] * A.inv_scale;
-        if ((nt & 3) == 0 && row0 + 3 < nt) {
-          *(f32x4*)yo = v;
-        } else {
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (row0 + j < nt) yo[j] = v[j];
-        }
+        for (int j = 0; j < 4; ++j)
+          if (row0 + j < nt) yo[j] = v[j];
       }
     }
   } else if constexpr (MODE == 1) {
     const int nt = A.nt;
-    double ss = 0.0;
+    if (k >= A.nk) return;
 #pragma unroll
-    for (int p = 0; p < kPosPerWave; ++p) {
+    for (int p = 0; p < NP; ++p) {
       const int ix = ix0 + p;
       if (ix >= A.nx) continue;
       const size_t pos = ((size_t)(iy + A.r) * A.xp + (ix + A.r)) * A.ps_r;
+      const size_t yi = (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
+      float rv[4];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int k = nb * 16 + n;
-        if (k >= A.nk) continue;
-        const size_t yi = (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
-        float rv[4];
+      for (int j = 0; j < 4; ++j) {
+        const bool ok = row0 + j < nt;
+        float v = acc[p][j] * A.inv_scale;
+        if (A.pmeas && ok) v -= A.pmeas[yi + j];
+        rv[j] = ok ? v : 0.0f;
+        ss += (double)rv[j] * (double)rv[j];
+      }
+      if constexpr (RQ_PREC == PSOAM_FP32) {
+        float* d = (float*)A.rq + pos + (size_t)row0 * A.kp + k;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) d[(size_t)j * A.kp] = rv[j];
+      } else {
+        using H = Half<RQ_PREC>;
+        typename H::V4 hi, lo;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const bool ok = row0 + j < nt;
-          float v = acc[p][nb][j] * A.inv_scale;
-          if (A.pmeas && ok) v -= A.pmeas[yi + j];
-          rv[j] = ok ? v : 0.0f;
-          ss += (double)rv[j] * (double)rv[j];
+          const float v = rv[j] * A.rq_scale;
+          hi[j] = (typename H::E)v;
+          lo[j] = (typename H::E)(v - (float)hi[j]);
         }
-        if constexpr (RQ_PREC == PSOAM_FP32) {
-          float* d = (float*)A.rq + pos + (size_t)row0 * A.kp + k;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) d[(size_t)j * A.kp] = rv[j];
-        } else {
-          using H = Half<RQ_PREC>;
-          typename H::V4 hi, lo;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const float v = rv[j] * A.rq_scale;
-            hi[j] = (typename H::E)v;
-            lo[j] = (typename H::E)(v - (float)hi[j]);
-          }
-          const size_t o = pos + ((size_t)(row0 >> 3) * A.kp + k) * 8 + ((row0 >> 2) & 1) * 4;
-          *(typename H::V4*)((typename H::E*)A.rq + o) = hi;
-          if constexpr (SPLIT) *(typename H::V4*)((typename H::E*)A.rq_lo + o) = lo;
-        }
+        const size_t o = pos + ((size_t)(row0 >> 3) * A.kp + k) * 8 + ((row0 >> 2) & 1) * 4;
+        *(typename H::V4*)((typename H::E*)A.rq + o) = hi;
+        if constexpr (SPLIT) *(typename H::V4*)((typename H::E*)A.rq_lo + o) = lo;
       }
     }
-    ss = wave_sum(ss);
-    if (lane == 0) A.partial[wid] = ss;
   } else {
-    // c[s][iy][ix][z] = sum_k S[k][s] bh[k][z]: reduce over the 16 pulse lanes
+    // c[s][iy][ix][z] (+)= sum_k S[k][s] bh[k][z]: reduce over the 16 pulse lanes
     const int nz = A.nz;
 #pragma unroll
-    for (int p = 0; p < kPosPerWave; ++p) {
+    for (int p = 0; p < NP; ++p) {
       const int ix = ix0 + p;
       const int ixc = ix < A.nx ? ix : A.nx - 1;
       const size_t col = ((size_t)iy * A.nx + ixc) * nz;
       for (int s = 0; s < A.sw.ns; ++s) {
         float v4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (k < A.nk) {
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int k = nb * 16 + n;
-          if (k < A.nk) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int z = row0 + j;
-              if (z < nz)
-                v4[j] += coef_at(A.sw, A.phi, A.stab, A.kp, col, z, k, s) *
-                         (acc[p][nb][j] * A.inv_scale);
-            }
+          for (int j = 0; j < 4; ++j) {
+            const int z = row0 + j;
+            if (z < nz)
+              v4[j] = coef_at(A.sw, A.phi, A.stab, A.kp, col, z, k, s) * (acc[p][j] * A.inv_scale);
           }
         }
 #pragma unroll
@@ -372,13 +357,16 @@ __device__ __forceinline__ void band_epilogue(const BandArgs& A,
           float* co = A.out + ((size_t)s * A.ny * A.nx) * nz + col + row0;
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            if (row0 + j < nz) co[j] = v4[j];
+            if (row0 + j < nz) co[j] = first ? v4[j] : co[j] + v4[j];
         }
       }
     }
   }
 }
 
+// Band kernel reading its operand straight from global memory: one wave owns
+// one output tile x kPosPerWave positions x all pulse blocks.  Used when the
+// staged variant below does not fit in LDS, and for FP32.
 template <int PREC, bool SPLIT, int NB, int MODE>
 __global__ __launch_bounds__(256) void band16(BandArgs A) {
   using H = Half<PREC>;
@@ -392,8 +380,9 @@ __global__ __launch_bounds__(256) void band16(BandArgs A) {
     return;
   }
   const int g = lane >> 4, n = lane & 15;
-  f32x4 acc[kPosPerWave][NB];
-  zero_acc<NB>(acc);
+  f32x4 acc[NB][kPosPerWave];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) zero_acc(acc[nb]);
   const int c0 = A.start[mtile], c1 = A.start[mtile + 1];
   const size_t base = ((size_t)iy * A.xp + ix0) * A.ps + (size_t)n * 8;
   const E* q = (const E*)A.q + base;
@@ -411,16 +400,23 @@ __global__ __launch_bounds__(256) void band16(BandArgs A) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const V b = *(const V*)(qc + p * A.ps + nb * 128);
-        acc[p][nb] = H::mma(a, b, acc[p][nb]);
+        acc[nb][p] = H::mma(a, b, acc[nb][p]);
         if constexpr (SPLIT) {
           const V blo = *(const V*)(qlo + off + p * A.ps + nb * 128);
-          acc[p][nb] = H::mma(a, blo, acc[p][nb]);
-          acc[p][nb] = H::mma(alo, b, acc[p][nb]);
+          acc[nb][p] = H::mma(a, blo, acc[nb][p]);
+          acc[nb][p] = H::mma(alo, b, acc[nb][p]);
         }
       }
     }
   }
-  band_epilogue<MODE, NB, E, PREC, SPLIT>(A, acc, mtile, iy, ix0, wid);
+  double ss = 0.0;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+    epi_block<MODE, kPosPerWave, PREC, SPLIT>(A, acc[nb], mtile, iy, ix0, nb * 16, nb == 0, ss);
+  if constexpr (MODE == 1) {
+    ss = wave_sum(ss);
+    if (lane == 0) A.partial[wid] = ss;
+  }
 }
 
 template <int NB, int MODE>
@@ -433,8 +429,9 @@ __global__ __launch_bounds__(256) void band32(BandArgs A) {
     return;
   }
   const int g = lane >> 4, n = lane & 15;
-  f32x4 acc[kPosPerWave][NB];
-  zero_acc<NB>(acc);
+  f32x4 acc[NB][kPosPerWave];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) zero_acc(acc[nb]);
   const int c0 = A.start[mtile], c1 = A.start[mtile + 1];
   const float* q = (const float*)A.q + ((size_t)iy * A.xp + ix0) * A.ps + n;
   const float* av = (const float*)A.a;
@@ -447,11 +444,164 @@ __global__ __launch_bounds__(256) void band32(BandArgs A) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const float b = qc[p * A.ps + nb * 16];
-        acc[p][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[p][nb], 0, 0, 0);
+        acc[nb][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[nb][p], 0, 0, 0);
       }
     }
   }
-  band_epilogue<MODE, NB, float, PSOAM_FP32, false>(A, acc, mtile, iy, ix0, wid);
+  double ss = 0.0;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+    epi_block<MODE, kPosPerWave, PSOAM_FP32, false>(A, acc[nb], mtile, iy, ix0, nb * 16, nb == 0,
+                                                    ss);
+  if constexpr (MODE == 1) {
+    ss = wave_sum(ss);
+    if (lane == 0) A.partial[wid] = ss;
+  }
+}
+
+// --------------------------------------------------------------------------
+// LDS-staged band kernel (16-bit operands).
+//
+// A workgroup owns kLdsRows consecutive output rows (one per wave) x
+// kLdsPos consecutive positions x one output tile of 16 rows.  Input rows
+// are streamed through LDS: padded input row iy0 + j is staged once (only the
+// octets the tile needs for the dy values j - r of its waves, one 16-pulse
+// block at a time) and every wave whose dy = j - wave is in the footprint
+// contracts against it.  The band blocks come from a chunk list per
+// (tile, dy); each group names (octet, dx), so the operand of position p is
+// the staged column p + dx.
+// --------------------------------------------------------------------------
+constexpr int kStageBatch = 8;
+
+struct LdsArgs {
+  const int* lstart;       // [n_mtiles * F + 1]
+  const uint32_t* lgrp;    // [chunks * 4]: octet << 16 | dx  (octet 0xffff = padding group)
+  const uint32_t* win;     // [n_mtiles * (F + kLdsRows - 1)]: obase << 16 | ocnt
+  const void* la;
+  const void* la_lo;
+  int f, yp, nyb, nxb, lds_elems;
+};
+
+template <int PREC, bool SPLIT, int MODE>
+__global__ __launch_bounds__(256) void band16_lds(BandArgs A, LdsArgs L) {
+  using H = Half<PREC>;
+  using E = typename H::E;
+  using V = typename H::V;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  E* sh = (E*)smem_raw;
+  E* sh_lo = sh + L.lds_elems;
+  const int nblocks = gridDim.x;
+  const int b = blockIdx.x;
+  const int per = nblocks / 8;
+  int lin = b;
+  if (b < per * 8) lin = (b % 8) * per + b / 8;
+  const int xb = lin % L.nxb;
+  const int rest = lin / L.nxb;
+  const int yb = rest % L.nyb;
+  const int mtile = rest / L.nyb;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, n = lane & 15;
+  const int iy0 = yb * kLdsRows, ix0 = xb * kLdsPos;
+  const int iy = iy0 + wave;
+  const bool row_ok = iy < A.ny;
+  const int F = L.f;
+  const int XW = kLdsPos + F - 1;
+  const int nwin = F + kLdsRows - 1;
+  const V* av = (const V*)L.la;
+  const V* avlo = (const V*)L.la_lo;
+  const E* q = (const E*)A.q;
+  const E* qlo = (const E*)A.q_lo;
+  double ss = 0.0;
+  const int nb_n = A.kp / 16;
+  for (int pb = 0; pb < nb_n; ++pb) {
+    f32x4 acc[kLdsPos];
+    zero_acc(acc);
+    for (int j = 0; j < nwin; ++j) {
+      const uint32_t win = L.win[mtile * nwin + j];
+      const int ocnt = (int)(win & 0xffffu), obase = (int)(win >> 16);
+      const int yrow = iy0 + j;
+      if (ocnt == 0 || yrow >= L.yp) continue;  // uniform over the block
+      __syncthreads();  // the previous row's contractions are done with LDS
+      const size_t row_base = (size_t)yrow * A.xp * A.ps;
+      const int items = ocnt * XW * 16;
+      // batches of kStageBatch 16-byte loads per thread, all in flight before the LDS writes
+      for (int base = 0; base < items; base += 256 * kStageBatch) {
+        V tmp[kStageBatch];
+        V tmp_lo[SPLIT ? kStageBatch : 1];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+          const int it = base + u * 256 + (int)threadIdx.x;
+          if (it < items) {
+            const int nn = it & 15;
+            const int r2 = it >> 4;
+            const int xi = r2 % XW;
+            const int oi = r2 / XW;
+            const size_t so = row_base + (size_t)(ix0 + xi) * A.ps +
+                              ((size_t)(obase + oi) * A.kp + pb * 16 + nn) * 8;
+            tmp[u] = *(const V*)(q + so);
+            if constexpr (SPLIT) tmp_lo[u] = *(const V*)(qlo + so);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+          const int it = base + u * 256 + (int)threadIdx.x;
+          if (it < items) {
+            *(V*)(sh + it * 8) = tmp[u];
+            if constexpr (SPLIT) *(V*)(sh_lo + it * 8) = tmp_lo[u];
+          }
+        }
+      }
+      __syncthreads();
+      const int dy = j - wave;
+      if (row_ok && dy >= 0 && dy < F) {
+        const int c0 = L.lstart[mtile * F + dy], c1 = L.lstart[mtile * F + dy + 1];
+        // the next chunk's group word and band block are loaded while this one runs
+        uint32_t gr_n = 0;
+        V a_n{}, alo_n{};
+        if (c0 < c1) {
+          gr_n = L.lgrp[c0 * 4 + g];
+          a_n = av[(size_t)c0 * kWaveLanes + lane];
+          if constexpr (SPLIT) alo_n = avlo[(size_t)c0 * kWaveLanes + lane];
+        }
+        for (int c = c0; c < c1; ++c) {
+          const uint32_t gr = gr_n;
+          const V a = a_n;
+          const V alo = alo_n;
+          if (c + 1 < c1) {
+            gr_n = L.lgrp[(c + 1) * 4 + g];
+            a_n = av[(size_t)(c + 1) * kWaveLanes + lane];
+            if constexpr (SPLIT) alo_n = avlo[(size_t)(c + 1) * kWaveLanes + lane];
+          }
+          const int dx = (int)(gr & 0xffffu);
+          const int o = (int)(gr >> 16);
+          const int oo = (o == 0xffff) ? 0 : o - obase;
+          const int bofs = ((oo * XW + dx) * 16 + n) * 8;
+          constexpr int kHalf = kLdsPos / 2;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            V bv[kHalf];
+#pragma unroll
+            for (int p = 0; p < kHalf; ++p) bv[p] = *(const V*)(sh + bofs + (h * kHalf + p) * 128);
+#pragma unroll
+            for (int p = 0; p < kHalf; ++p) {
+              acc[h * kHalf + p] = H::mma(a, bv[p], acc[h * kHalf + p]);
+              if constexpr (SPLIT) {
+                const V blo = *(const V*)(sh_lo + bofs + (h * kHalf + p) * 128);
+                acc[h * kHalf + p] = H::mma(a, blo, acc[h * kHalf + p]);
+                acc[h * kHalf + p] = H::mma(alo, bv[p], acc[h * kHalf + p]);
+              }
+            }
+          }
+        }
+      }
+    }
+    if (row_ok) epi_block<MODE, kLdsPos, PREC, SPLIT>(A, acc, mtile, iy, ix0, pb * 16, pb == 0, ss);
+  }
+  if constexpr (MODE == 1) {
+    ss = wave_sum(ss);
+    if (lane == 0) A.partial[(size_t)b * kLdsRows + wave] = ss;
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -518,15 +668,62 @@ hipError_t launch_pack_r(const psoam_plan* P, const float* y, hipStream_t s) {
   return hipGetLastError();
 }
 
+static bool use_lds(const psoam_plan* P, int mode) {
+  const BandTable& T = (mode == 2) ? P->adj : P->fwd;
+  return P->prec != PSOAM_FP32 && T.lds_ok;
+}
+
 static size_t band_blocks(const psoam_plan* P, int mode) {
   const BandTable& T = (mode == 2) ? P->adj : P->fwd;
+  if (use_lds(P, mode)) {
+    const size_t nyb = (P->g.ny + kLdsRows - 1) / kLdsRows;
+    const size_t nxb = (P->g.nx + kLdsPos - 1) / kLdsPos;
+    return (size_t)T.n_mtiles * nyb * nxb;
+  }
   const int n_mblk = (T.n_mtiles + kWavesPerBlock - 1) / kWavesPerBlock;
   const int nxb = (P->g.nx + kPosPerWave - 1) / kPosPerWave;
   return (size_t)n_mblk * P->g.ny * nxb;
 }
 
 size_t band_partials(const psoam_plan* P, int mode) {
-  return band_blocks(P, mode) * kWavesPerBlock;
+  return band_blocks(P, mode) * (use_lds(P, mode) ? kLdsRows : kWavesPerBlock);
+}
+
+template <int MODE>
+static hipError_t launch_band_lds(const psoam_plan* P, const BandTable& T, BandArgs& A,
+                                  dim3 grid, hipStream_t s) {
+  LdsArgs L;
+  L.lstart = T.d_lstart;
+  L.lgrp = T.d_lgrp;
+  L.win = T.d_win;
+  L.la = T.d_la;
+  L.la_lo = T.d_la_lo;
+  L.f = P->F;
+  L.yp = P->Yp;
+  L.nyb = (P->g.ny + kLdsRows - 1) / kLdsRows;
+  L.nxb = (P->g.nx + kLdsPos - 1) / kLdsPos;
+  const bool split = P->prec == PSOAM_BF16_SPLIT || P->prec == PSOAM_FP16_SPLIT;
+  L.lds_elems = (int)(T.lds_bytes / sizeof(uint16_t) / (split ? 2 : 1));
+  const size_t lds = T.lds_bytes;
+#define PSOAM_LDS(PR, SP)                                                                   \
+  {                                                                                         \
+    auto kern = band16_lds<PR, SP, MODE>;                                                   \
+    if (lds > 64 * 1024)                                                                    \
+      (void)hipFuncSetAttribute((const void*)kern,                                          \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);      \
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, A, L);                                \
+    break;                                                                                  \
+  }
+  switch (P->prec) {
+    case PSOAM_BF16: PSOAM_LDS(PSOAM_BF16, false)
+    case PSOAM_FP16: PSOAM_LDS(PSOAM_FP16, false)
+    case PSOAM_BF16_SPLIT: PSOAM_LDS(PSOAM_BF16, true)
+    case PSOAM_FP16_SPLIT: PSOAM_LDS(PSOAM_FP16, true)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef PSOAM_LDS
+  return hipGetLastError();
 }
 
 template <int MODE>
@@ -606,6 +803,14 @@ hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* p
   A.nt = P->g.nt;
   const dim3 grid((unsigned)band_blocks(P, mode));
   (void)split;
+  if (use_lds(P, mode)) {
+    switch (mode) {
+      case 0: return launch_band_lds<0>(P, T, A, grid, s);
+      case 1: return launch_band_lds<1>(P, T, A, grid, s);
+      case 2: return launch_band_lds<2>(P, T, A, grid, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (mode) {
     case 0: return launch_band_mode<0>(P, A, grid, s);
     case 1: return launch_band_mode<1>(P, A, grid, s);

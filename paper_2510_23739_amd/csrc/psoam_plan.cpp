@@ -4,7 +4,9 @@
 // depths z).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -52,17 +54,6 @@ struct Group {
   int jy, jx, l;  // lateral offset indices (already flipped for H^T) and contracted index
 };
 
-// Packs one direction.  `col_rows(jy, jx, l)` is not used; instead the caller
-// provides, per output tile, the groups and a function that fills the tile.
-struct Packer {
-  bool half;           // 16-bit octet groups (8 samples) or FP32 single samples
-  int prec;
-  std::vector<int> start;
-  std::vector<int> off;
-  std::vector<uint16_t> a16, a16lo;
-  std::vector<float> a32;
-};
-
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -79,9 +70,12 @@ int hip_fail(hipError_t e, const char* what) {
 
 const char* last_error_cstr() { return g_last_error.c_str(); }
 
-// Build the table of one direction.
+// Build the tables of one direction.
 //  dir 0 (H):   output rows t (tiles of 16 over Nt), contracted axis z
 //  dir 1 (H^T): output rows z (tiles of 16 over Nz), contracted axis t, offsets flipped
+// Two packings of the same band blocks: chunks per output tile (global-operand
+// kernel, offsets relative to the position base) and, for 16-bit operands,
+// chunks per (tile, dy) for the LDS-staged kernel (groups as octet << 16 | dx).
 static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* taps,
                        BandTable& T) {
   const auto& g = P->g;
@@ -120,9 +114,70 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   T.n_mtiles = n_mt;
   T.m_rows = out_len;
   T.useful_macs = useful;
+
+  // band values of one group into lane-major chunk storage
+  auto fill = [&](std::vector<float>& vals, int c, int gi, const Group& G, int tile) {
+    const int jdy = dir == 0 ? G.jy : F - 1 - G.jy;
+    const int jdx = dir == 0 ? G.jx : F - 1 - G.jx;
+    if (dir == 0) {
+      for (int e = 0; e < gw; ++e) {
+        const int z = G.l * gw + e;
+        if (z >= g.nz) continue;
+        const size_t col = ((size_t)z * F + jdy) * F + jdx;
+        for (int j = 0; j < W; ++j) {
+          const int t = t0[col] + j;
+          if (t < tile * 16 || t >= tile * 16 + 16 || t >= g.nt) continue;
+          const int lane = 16 * gi + (t - tile * 16);
+          vals[((size_t)c * 64 + lane) * gw + e] = taps[col * W + j];
+        }
+      }
+    } else {
+      for (int zi = 0; zi < 16; ++zi) {
+        const int z = tile * 16 + zi;
+        if (z >= g.nz) continue;
+        const size_t col = ((size_t)z * F + jdy) * F + jdx;
+        for (int j = 0; j < W; ++j) {
+          const int t = t0[col] + j;
+          if (t < 0 || t >= g.nt || t / gw != G.l) continue;
+          const int lane = 16 * gi + zi;
+          vals[((size_t)c * 64 + lane) * gw + (t - G.l * gw)] = taps[col * W + j];
+        }
+      }
+    }
+  };
+  auto upload_vals = [&](const std::vector<float>& vals, int n_chunks, void** hi_out,
+                         void** lo_out) -> int {
+    const size_t nc = n_chunks > 0 ? (size_t)n_chunks : 1;
+    if (!half) {
+      PSOAM_HIP(hipMalloc(hi_out, sizeof(float) * 64 * nc));
+      if (n_chunks)
+        PSOAM_HIP(hipMemcpy(*hi_out, vals.data(), sizeof(float) * 64 * n_chunks, hipMemcpyHostToDevice));
+      return PSOAM_OK;
+    }
+    std::vector<uint16_t> hi(vals.size()), lo(vals.size());
+    for (size_t i = 0; i < vals.size(); ++i) {
+      if (fp16) {
+        hi[i] = to_f16(vals[i]);
+        lo[i] = to_f16(vals[i] - from_f16(hi[i]));
+      } else {
+        hi[i] = to_bf16(vals[i]);
+        lo[i] = to_bf16(vals[i] - from_bf16(hi[i]));
+      }
+    }
+    PSOAM_HIP(hipMalloc(hi_out, sizeof(uint16_t) * 512 * nc));
+    if (n_chunks)
+      PSOAM_HIP(hipMemcpy(*hi_out, hi.data(), sizeof(uint16_t) * 512 * n_chunks, hipMemcpyHostToDevice));
+    if (split) {
+      PSOAM_HIP(hipMalloc(lo_out, sizeof(uint16_t) * 512 * nc));
+      if (n_chunks)
+        PSOAM_HIP(hipMemcpy(*lo_out, lo.data(), sizeof(uint16_t) * 512 * n_chunks, hipMemcpyHostToDevice));
+    }
+    return PSOAM_OK;
+  };
+
+  // ---- packing 1: per output tile (all offsets mixed)
   T.h_start.assign(n_mt + 1, 0);
   std::vector<Group> groups;
-  std::vector<int> tile_of_chunk;
   std::vector<Group> chunk_groups;  // 4 per chunk
   for (int tile = 0; tile < n_mt; ++tile) {
     groups.clear();
@@ -137,85 +192,116 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   }
   const int n_chunks = T.h_start[n_mt];
   T.n_chunks = n_chunks;
-  std::vector<int> off((size_t)n_chunks * 4, 0);
-  std::vector<float> vals((size_t)n_chunks * 64 * gw, 0.0f);  // lane-major packed values
-  for (int tile = 0; tile < n_mt; ++tile) {
-    for (int c = T.h_start[tile]; c < T.h_start[tile + 1]; ++c) {
-      for (int gi = 0; gi < 4; ++gi) {
-        const Group& G = chunk_groups[(size_t)c * 4 + gi];
-        if (G.jy < 0) continue;  // padding group: offset 0, zero band values
-        off[(size_t)c * 4 + gi] =
-            (int)(((size_t)G.jy * P->Xp + G.jx) * ps + (size_t)G.l * gw * P->Kp);
-        const int jdy = dir == 0 ? G.jy : F - 1 - G.jy;
-        const int jdx = dir == 0 ? G.jx : F - 1 - G.jx;
-        if (dir == 0) {
-          // rows t of the tile, contracted z in the group
-          for (int e = 0; e < gw; ++e) {
-            const int z = G.l * gw + e;
-            if (z >= g.nz) continue;
-            const size_t col = ((size_t)z * F + jdy) * F + jdx;
-            for (int j = 0; j < W; ++j) {
-              const int t = t0[col] + j;
-              if (t < tile * 16 || t >= tile * 16 + 16 || t >= g.nt) continue;
-              const int lane = 16 * gi + (t - tile * 16);
-              vals[((size_t)c * 64 + lane) * gw + e] = taps[col * W + j];
-            }
-          }
-        } else {
-          // rows z of the tile, contracted t in the group
-          for (int zi = 0; zi < 16; ++zi) {
-            const int z = tile * 16 + zi;
-            if (z >= g.nz) continue;
-            const size_t col = ((size_t)z * F + jdy) * F + jdx;
-            for (int j = 0; j < W; ++j) {
-              const int t = t0[col] + j;
-              if (t < 0 || t >= g.nt || t / gw != G.l) continue;
-              const int lane = 16 * gi + zi;
-              vals[((size_t)c * 64 + lane) * gw + (t - G.l * gw)] = taps[col * W + j];
-            }
-          }
+  {
+    std::vector<int> off((size_t)n_chunks * 4, 0);
+    std::vector<float> vals((size_t)n_chunks * 64 * gw, 0.0f);
+    for (int tile = 0; tile < n_mt; ++tile)
+      for (int c = T.h_start[tile]; c < T.h_start[tile + 1]; ++c)
+        for (int gi = 0; gi < 4; ++gi) {
+          const Group& G = chunk_groups[(size_t)c * 4 + gi];
+          if (G.jy < 0) continue;  // padding group: offset 0, zero band values
+          off[(size_t)c * 4 + gi] =
+              (int)(((size_t)G.jy * P->Xp + G.jx) * ps + (size_t)G.l * gw * P->Kp);
+          fill(vals, c, gi, G, tile);
         }
+    PSOAM_HIP(hipMalloc(&T.d_start, sizeof(int) * (n_mt + 1)));
+    PSOAM_HIP(hipMemcpy(T.d_start, T.h_start.data(), sizeof(int) * (n_mt + 1), hipMemcpyHostToDevice));
+    const size_t nc = n_chunks > 0 ? (size_t)n_chunks : 1;
+    PSOAM_HIP(hipMalloc(&T.d_off, sizeof(int) * 4 * nc));
+    if (n_chunks) PSOAM_HIP(hipMemcpy(T.d_off, off.data(), sizeof(int) * 4 * n_chunks, hipMemcpyHostToDevice));
+    if (int rc = upload_vals(vals, n_chunks, &T.d_a, &T.d_a_lo)) return rc;
+  }
+  if (!half) return PSOAM_OK;
+
+  // ---- packing 2: per (tile, dy) for the LDS-staged kernel
+  std::vector<int> lstart((size_t)n_mt * F + 1, 0);
+  std::vector<Group> lgroups;
+  std::vector<int> lo_l((size_t)n_mt * F, 1 << 30), hi_l((size_t)n_mt * F, -1);
+  for (int tile = 0; tile < n_mt; ++tile)
+    for (int jy = 0; jy < F; ++jy) {
+      const size_t key = (size_t)tile * F + jy;
+      size_t cnt = 0;
+      for (int jx = 0; jx < F; ++jx)
+        for (int l = 0; l < n_l; ++l)
+          if (mark[((size_t)tile * n_off + (size_t)jy * F + jx) * n_l + l]) {
+            lgroups.push_back({jy, jx, l});
+            ++cnt;
+            lo_l[key] = std::min(lo_l[key], l);
+            hi_l[key] = std::max(hi_l[key], l);
+          }
+      const size_t nch = (cnt + 3) / 4;
+      for (size_t i = cnt; i < nch * 4; ++i) lgroups.push_back({-1, -1, -1});
+      lstart[key + 1] = lstart[key] + (int)nch;
+    }
+  const int l_chunks = lstart[(size_t)n_mt * F];
+  T.l_chunks = l_chunks;
+  const int nwin = F + kLdsRows - 1;
+  std::vector<uint32_t> win((size_t)n_mt * nwin, 0);
+  int max_oct = 0;
+  for (int tile = 0; tile < n_mt; ++tile)
+    for (int j = 0; j < nwin; ++j) {
+      int lo = 1 << 30, hi = -1;
+      for (int r = 0; r < kLdsRows; ++r) {
+        const int dy = j - r;
+        if (dy < 0 || dy >= F) continue;
+        const size_t key = (size_t)tile * F + dy;
+        if (hi_l[key] < 0) continue;
+        lo = std::min(lo, lo_l[key]);
+        hi = std::max(hi, hi_l[key]);
+      }
+      if (hi >= 0) {
+        const int cnt = hi - lo + 1;
+        max_oct = std::max(max_oct, cnt);
+        win[(size_t)tile * nwin + j] = ((uint32_t)lo << 16) | (uint32_t)cnt;
       }
     }
-  }
-  // upload
-  PSOAM_HIP(hipMalloc(&T.d_start, sizeof(int) * (n_mt + 1)));
-  PSOAM_HIP(hipMemcpy(T.d_start, T.h_start.data(), sizeof(int) * (n_mt + 1), hipMemcpyHostToDevice));
-  const size_t nc = n_chunks > 0 ? (size_t)n_chunks : 1;
-  PSOAM_HIP(hipMalloc(&T.d_off, sizeof(int) * 4 * nc));
-  if (n_chunks) PSOAM_HIP(hipMemcpy(T.d_off, off.data(), sizeof(int) * 4 * n_chunks, hipMemcpyHostToDevice));
-  if (!half) {
-    PSOAM_HIP(hipMalloc(&T.d_a, sizeof(float) * 64 * nc));
-    if (n_chunks) PSOAM_HIP(hipMemcpy(T.d_a, vals.data(), sizeof(float) * 64 * n_chunks, hipMemcpyHostToDevice));
-  } else {
-    std::vector<uint16_t> hi(vals.size()), lo(vals.size());
-    for (size_t i = 0; i < vals.size(); ++i) {
-      if (fp16) {
-        hi[i] = to_f16(vals[i]);
-        lo[i] = to_f16(vals[i] - from_f16(hi[i]));
-      } else {
-        hi[i] = to_bf16(vals[i]);
-        lo[i] = to_bf16(vals[i] - from_bf16(hi[i]));
-      }
+  T.max_oct = max_oct;
+  const int XW = kLdsPos + F - 1;
+  T.lds_bytes = (size_t)max_oct * XW * 16 * 8 * sizeof(uint16_t) * (split ? 2 : 1);
+  // PSOAM_BAND_GLOBAL=1 keeps the plan on the global-operand kernel (tests cover both)
+  const char* force_global = std::getenv("PSOAM_BAND_GLOBAL");
+  T.lds_ok = n_l < 0xffff && F < 0xffff && T.lds_bytes <= (size_t)kLdsMaxBytes &&
+             !(force_global && force_global[0] == '1');
+  if (!T.lds_ok) return PSOAM_OK;
+  std::vector<uint32_t> lgrp((size_t)l_chunks * 4, 0);
+  std::vector<float> lvals((size_t)l_chunks * 64 * gw, 0.0f);
+  for (int tile = 0; tile < n_mt; ++tile)
+    for (int jy = 0; jy < F; ++jy) {
+      const size_t key = (size_t)tile * F + jy;
+      for (int c = lstart[key]; c < lstart[key + 1]; ++c)
+        for (int gi = 0; gi < 4; ++gi) {
+          const Group& G = lgroups[(size_t)c * 4 + gi];
+          if (G.jy < 0) {
+            lgrp[(size_t)c * 4 + gi] = 0xffffu << 16;
+            continue;
+          }
+          lgrp[(size_t)c * 4 + gi] = ((uint32_t)G.l << 16) | (uint32_t)G.jx;
+          fill(lvals, c, gi, G, tile);
+        }
     }
-    PSOAM_HIP(hipMalloc(&T.d_a, sizeof(uint16_t) * 512 * nc));
-    if (n_chunks) PSOAM_HIP(hipMemcpy(T.d_a, hi.data(), sizeof(uint16_t) * 512 * n_chunks, hipMemcpyHostToDevice));
-    if (split) {
-      PSOAM_HIP(hipMalloc(&T.d_a_lo, sizeof(uint16_t) * 512 * nc));
-      if (n_chunks) PSOAM_HIP(hipMemcpy(T.d_a_lo, lo.data(), sizeof(uint16_t) * 512 * n_chunks, hipMemcpyHostToDevice));
-    }
-  }
+  PSOAM_HIP(hipMalloc(&T.d_lstart, sizeof(int) * lstart.size()));
+  PSOAM_HIP(hipMemcpy(T.d_lstart, lstart.data(), sizeof(int) * lstart.size(), hipMemcpyHostToDevice));
+  PSOAM_HIP(hipMalloc(&T.d_lgrp, sizeof(uint32_t) * std::max<size_t>(lgrp.size(), 4)));
+  if (!lgrp.empty())
+    PSOAM_HIP(hipMemcpy(T.d_lgrp, lgrp.data(), sizeof(uint32_t) * lgrp.size(), hipMemcpyHostToDevice));
+  PSOAM_HIP(hipMalloc(&T.d_win, sizeof(uint32_t) * win.size()));
+  PSOAM_HIP(hipMemcpy(T.d_win, win.data(), sizeof(uint32_t) * win.size(), hipMemcpyHostToDevice));
+  if (int rc = upload_vals(lvals, l_chunks, &T.d_la, &T.d_la_lo)) return rc;
   return PSOAM_OK;
 }
 
 static void free_table(BandTable& T) {
-  if (T.d_start) (void)hipFree(T.d_start);
-  if (T.d_off) (void)hipFree(T.d_off);
-  if (T.d_a) (void)hipFree(T.d_a);
-  if (T.d_a_lo) (void)hipFree(T.d_a_lo);
+  void* ptrs[] = {T.d_start, T.d_off, T.d_a, T.d_a_lo, T.d_lstart, T.d_lgrp, T.d_win, T.d_la,
+                  T.d_la_lo};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
   T.d_start = nullptr;
   T.d_off = nullptr;
   T.d_a = T.d_a_lo = nullptr;
+  T.d_lstart = nullptr;
+  T.d_lgrp = nullptr;
+  T.d_win = nullptr;
+  T.d_la = T.d_la_lo = nullptr;
 }
 
 void free_plan(psoam_plan* P) {

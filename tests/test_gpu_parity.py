@@ -47,11 +47,15 @@ def test_apply_A_and_AT_C1(c1, prec):
     assert e <= TOL_OP[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16_split", "fp16"])
-def test_ragged_random_table(prec):
+@pytest.mark.parametrize("prec,kernel", [("fp32", "global"), ("bf16", "lds"), ("bf16_split", "lds"),
+                                         ("fp16", "lds"), ("bf16", "global"),
+                                         ("bf16_split", "global")])
+def test_ragged_random_table(prec, kernel, monkeypatch):
     """Sizes off every tile boundary, per-voxel fluence with the fluence-
-    dependent rate, asymmetric random band running off both ends."""
+    dependent rate, asymmetric random band running off both ends; both the
+    LDS-staged and the global-operand band kernels."""
     torch = torch_cuda()
+    monkeypatch.setenv("PSOAM_BAND_GLOBAL", "1" if kernel == "global" else "0")
     cfg, t0, taps, phi, sp = ragged_cfg(3)
     say(f"[parity] ragged prec={prec}")
     S = oracle_S(cfg, phi, sp)
