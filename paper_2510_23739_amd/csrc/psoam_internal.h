@@ -29,7 +29,6 @@ constexpr int kPosPerWave = 8;       // scan/voxel positions owned by one wave
 constexpr int kPadX = 16;            // Nx is padded up to a multiple of this
 constexpr int kWavesPerBlock = 4;    // consecutive output tiles of one position block
 constexpr float kFp16Scale = 256.0f; // FP16 operands carry this power-of-two scale
-constexpr int kLdsRows = 4;          // staged kernel: output rows per workgroup (one per wave)
 constexpr int kLdsPos = 16;          // staged kernel: positions per wave
 constexpr int kLdsMaxBytes = 160 * 1024;
 
@@ -63,14 +62,16 @@ struct BandTable {
   size_t useful_macs = 0;    // nonzero band entries covered (per position and pulse)
   // staged (LDS) variant, 16-bit operands: chunks listed per (tile, dy)
   bool lds_ok = false;
+  int rows = 4;                // output rows (waves) per workgroup: 4 or 8
   int l_chunks = 0;
   int max_oct = 0;             // widest staged octet window
   size_t lds_bytes = 0;        // dynamic LDS per workgroup
   int* d_lstart = nullptr;     // [n_mtiles * F + 1]
   uint32_t* d_lgrp = nullptr;  // [l_chunks * 4]  octet << 16 | dx
-  uint32_t* d_win = nullptr;   // [n_mtiles * (F + kLdsRows - 1)]  obase << 16 | ocnt
+  uint32_t* d_win = nullptr;   // [n_mtiles * (F + rows - 1)]  obase << 16 | ocnt
   void* d_la = nullptr;
   void* d_la_lo = nullptr;
+  int* d_order = nullptr;      // [n_mtiles] tiles by decreasing chunk count
 };
 
 struct Workspace {

@@ -462,7 +462,7 @@ __global__ __launch_bounds__(256) void band32(BandArgs A) {
 // --------------------------------------------------------------------------
 // LDS-staged band kernel (16-bit operands).
 //
-// A workgroup owns kLdsRows consecutive output rows (one per wave) x
+// A workgroup owns ROWS (4 or 8) consecutive output rows (one per wave) x
 // kLdsPos consecutive positions x one output tile of 16 rows.  Input rows
 // are streamed through LDS: padded input row iy0 + j is staged once (only the
 // octets the tile needs for the dy values j - r of its waves, one 16-pulse
@@ -476,123 +476,204 @@ constexpr int kStageBatch = 8;
 struct LdsArgs {
   const int* lstart;       // [n_mtiles * F + 1]
   const uint32_t* lgrp;    // [chunks * 4]: octet << 16 | dx  (octet 0xffff = padding group)
-  const uint32_t* win;     // [n_mtiles * (F + kLdsRows - 1)]: obase << 16 | ocnt
+  const uint32_t* win;     // [n_mtiles * (F + ROWS - 1)]: obase << 16 | ocnt
   const void* la;
   const void* la_lo;
   int f, yp, nyb, nxb, lds_elems;
+  int meta_off;  // byte offset of the per-tile window / list-bound table in LDS
+  const int* order;  // output tiles by decreasing work
 };
 
-template <int PREC, bool SPLIT, int MODE>
-__global__ __launch_bounds__(256) void band16_lds(BandArgs A, LdsArgs L) {
+template <int PREC, bool SPLIT, int MODE, int ROWS>
+__device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs& L) {
   using H = Half<PREC>;
   using E = typename H::E;
   using V = typename H::V;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   E* sh = (E*)smem_raw;
   E* sh_lo = sh + L.lds_elems;
-  const int nblocks = gridDim.x;
+  // per-tile row windows and chunk-list bounds, read once into LDS
+  uint32_t* s_win = (uint32_t*)(smem_raw + L.meta_off);
+  int* s_lstart = (int*)(s_win + (L.f + ROWS - 1));
+  // Block order.  Output tiles differ several-fold in work (bands crowd
+  // around the focal time), so (1) every XCD (blocks are dealt to the 8 XCDs
+  // round-robin) receives all tiles for its own share of position blocks,
+  // and (2) within an XCD the heaviest tiles are dispatched first so the
+  // light ones fill the tail (longest-processing-time order, L.order).
   const int b = blockIdx.x;
-  const int per = nblocks / 8;
-  int lin = b;
-  if (b < per * 8) lin = (b % 8) * per + b / 8;
-  const int xb = lin % L.nxb;
-  const int rest = lin / L.nxb;
-  const int yb = rest % L.nyb;
-  const int mtile = rest / L.nyb;
+  const int npos = L.nxb * L.nyb;
+  int mtile, pos;
+  if ((npos & 7) == 0) {
+    const int xcd = b & 7, k = b >> 3;
+    const int per_x = npos >> 3;
+    mtile = L.order[k / per_x];
+    pos = xcd * per_x + k % per_x;
+  } else {
+    mtile = L.order[b / npos];
+    pos = b % npos;
+  }
+  const int xb = pos % L.nxb;
+  const int yb = pos / L.nxb;
+  constexpr int NT = 64 * ROWS;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, n = lane & 15;
-  const int iy0 = yb * kLdsRows, ix0 = xb * kLdsPos;
+  const int iy0 = yb * ROWS, ix0 = xb * kLdsPos;
   const int iy = iy0 + wave;
   const bool row_ok = iy < A.ny;
   const int F = L.f;
   const int XW = kLdsPos + F - 1;
-  const int nwin = F + kLdsRows - 1;
+  const int nwin = F + ROWS - 1;
   const V* av = (const V*)L.la;
   const V* avlo = (const V*)L.la_lo;
   const E* q = (const E*)A.q;
   const E* qlo = (const E*)A.q_lo;
+  {
+    const int nw = L.f + ROWS - 1;
+    for (int i = (int)threadIdx.x; i < nw; i += NT) s_win[i] = L.win[mtile * nw + i];
+    for (int i = (int)threadIdx.x; i <= L.f; i += NT) s_lstart[i] = L.lstart[mtile * L.f + i];
+    __syncthreads();
+  }
   double ss = 0.0;
   const int nb_n = A.kp / 16;
   for (int pb = 0; pb < nb_n; ++pb) {
     f32x4 acc[kLdsPos];
     zero_acc(acc);
-    for (int j = 0; j < nwin; ++j) {
-      const uint32_t win = L.win[mtile * nwin + j];
-      const int ocnt = (int)(win & 0xffffu), obase = (int)(win >> 16);
-      const int yrow = iy0 + j;
-      if (ocnt == 0 || yrow >= L.yp) continue;  // uniform over the block
-      __syncthreads();  // the previous row's contractions are done with LDS
-      const size_t row_base = (size_t)yrow * A.xp * A.ps;
-      const int items = ocnt * XW * 16;
-      // batches of kStageBatch 16-byte loads per thread, all in flight before the LDS writes
-      for (int base = 0; base < items; base += 256 * kStageBatch) {
-        V tmp[kStageBatch];
-        V tmp_lo[SPLIT ? kStageBatch : 1];
+    // Software pipeline over staged rows: the first kStageBatch loads per
+    // thread of row j+1 are issued right after row j is committed to LDS, so
+    // their latency overlaps row j's contractions.  Thread t stages items
+    // t, t+NT, ...: item it = (octet oi, column xi, pulse nn) with
+    // it = (oi*XW + xi)*16 + nn, so nn = t%16 is fixed and (xi, oi) advance
+    // by NT/16 columns per step (at most one octet carry while XW >= NT/16;
+    // a wider step carries with a loop).
+    constexpr int NPRE = SPLIT ? kStageBatch / 2 : kStageBatch;
+    V pre[NPRE];
+    V pre_lo[SPLIT ? NPRE : 1];
+    const int t16 = (int)threadIdx.x >> 4;
+    const int tnn = (int)threadIdx.x & 15;
+    auto row_ok_at = [&](int jj, int& oc, int& ob) -> bool {
+      if (jj >= nwin) return false;
+      const uint32_t w = s_win[jj];
+      oc = (int)(w & 0xffffu);
+      ob = (int)(w >> 16);
+      return oc != 0 && iy0 + jj < L.yp;
+    };
+    // loads items [u0*NT, (u0+NPRE)*NT) of row jj into regs
+    auto load_batch = [&](int jj, int oc, int ob, int u0, V (&dst)[NPRE], V (&dst_lo)[SPLIT ? NPRE : 1]) {
+      const int items = oc * XW * 16;
+      const E* rowp = q + (size_t)(iy0 + jj) * A.xp * A.ps;
+      const E* rowp_lo = SPLIT ? qlo + (size_t)(iy0 + jj) * A.xp * A.ps : nullptr;
+      int r2 = u0 * (NT / 16) + t16;
+      int xi = r2 % XW, oi = r2 / XW;
+      const int ps = (int)A.ps;
+      int off = (ix0 + xi) * ps + ((ob + oi) * A.kp + pb * 16 + tnn) * 8;
 #pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-          const int it = base + u * 256 + (int)threadIdx.x;
-          if (it < items) {
-            const int nn = it & 15;
-            const int r2 = it >> 4;
-            const int xi = r2 % XW;
-            const int oi = r2 / XW;
-            const size_t so = row_base + (size_t)(ix0 + xi) * A.ps +
-                              ((size_t)(obase + oi) * A.kp + pb * 16 + nn) * 8;
-            tmp[u] = *(const V*)(q + so);
-            if constexpr (SPLIT) tmp_lo[u] = *(const V*)(qlo + so);
-          }
+      for (int u = 0; u < NPRE; ++u) {
+        if ((u0 + u) * NT + (int)threadIdx.x < items) {
+          dst[u] = *(const V*)(rowp + off);
+          if constexpr (SPLIT) dst_lo[u] = *(const V*)(rowp_lo + off);
         }
-#pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-          const int it = base + u * 256 + (int)threadIdx.x;
-          if (it < items) {
-            *(V*)(sh + it * 8) = tmp[u];
-            if constexpr (SPLIT) *(V*)(sh_lo + it * 8) = tmp_lo[u];
-          }
+        xi += NT / 16;
+        off += (NT / 16) * ps;
+        while (xi >= XW) {
+          xi -= XW;
+          off += -XW * ps + A.kp * 8;
         }
       }
+    };
+    auto store_batch = [&](int oc, int u0, const V (&src)[NPRE], const V (&src_lo)[SPLIT ? NPRE : 1]) {
+      const int items = oc * XW * 16;
+#pragma unroll
+      for (int u = 0; u < NPRE; ++u) {
+        const int it = (u0 + u) * NT + (int)threadIdx.x;
+        if (it < items) {
+          *(V*)(sh + it * 8) = src[u];
+          if constexpr (SPLIT) *(V*)(sh_lo + it * 8) = src_lo[u];
+        }
+      }
+    };
+    int ocnt_n = 0, obase_n = 0;
+    bool ok_n = row_ok_at(0, ocnt_n, obase_n);
+    if (ok_n) load_batch(0, ocnt_n, obase_n, 0, pre, pre_lo);
+    for (int j = 0; j < nwin; ++j) {
+      const bool ok = ok_n;
+      const int ocnt = ocnt_n, obase = obase_n;
+      if (!ok) {  // uniform over the block
+        ok_n = row_ok_at(j + 1, ocnt_n, obase_n);
+        if (ok_n) load_batch(j + 1, ocnt_n, obase_n, 0, pre, pre_lo);
+        continue;
+      }
+      __syncthreads();  // the previous row's contractions are done with LDS
+      store_batch(ocnt, 0, pre, pre_lo);
+      const int items = ocnt * XW * 16;
+      // items beyond the prefetched part: batches with all loads in flight
+      for (int u0 = NPRE; u0 * NT < items; u0 += NPRE) {
+        V tmp[NPRE];
+        V tmp_lo[SPLIT ? NPRE : 1];
+        load_batch(j, ocnt, obase, u0, tmp, tmp_lo);
+        store_batch(ocnt, u0, tmp, tmp_lo);
+      }
       __syncthreads();
+      ok_n = row_ok_at(j + 1, ocnt_n, obase_n);
+      if (ok_n) load_batch(j + 1, ocnt_n, obase_n, 0, pre, pre_lo);
       const int dy = j - wave;
       if (row_ok && dy >= 0 && dy < F) {
-        const int c0 = L.lstart[mtile * F + dy], c1 = L.lstart[mtile * F + dy + 1];
-        // the next chunk's group word and band block are loaded while this one runs
-        uint32_t gr_n = 0;
-        V a_n{}, alo_n{};
-        if (c0 < c1) {
-          gr_n = L.lgrp[c0 * 4 + g];
-          a_n = av[(size_t)c0 * kWaveLanes + lane];
-          if constexpr (SPLIT) alo_n = avlo[(size_t)c0 * kWaveLanes + lane];
-        }
-        for (int c = c0; c < c1; ++c) {
-          const uint32_t gr = gr_n;
-          const V a = a_n;
-          const V alo = alo_n;
-          if (c + 1 < c1) {
-            gr_n = L.lgrp[(c + 1) * 4 + g];
-            a_n = av[(size_t)(c + 1) * kWaveLanes + lane];
-            if constexpr (SPLIT) alo_n = avlo[(size_t)(c + 1) * kWaveLanes + lane];
-          }
+        const int c0 = s_lstart[dy], c1 = s_lstart[dy + 1];
+        // two chunk buffers, each reloaded right after its chunk's products
+        // are issued, so a chunk's group word and band block travel from L2
+        // while the other buffer's chunk runs (no register copies between
+        // iterations: a copy would force a wait on the newest load)
+        uint32_t gr0 = 0, gr1 = 0;
+        V a0{}, a1{}, alo0{}, alo1{};
+        auto fetch = [&](int cc, uint32_t& grx, V& ax, V& alox) {
+          grx = L.lgrp[cc * 4 + g];
+          ax = av[(size_t)cc * kWaveLanes + lane];
+          if constexpr (SPLIT) alox = avlo[(size_t)cc * kWaveLanes + lane];
+        };
+        auto run = [&](uint32_t gr, const V& a, const V& alo) {
           const int dx = (int)(gr & 0xffffu);
           const int o = (int)(gr >> 16);
           const int oo = (o == 0xffff) ? 0 : o - obase;
           const int bofs = ((oo * XW + dx) * 16 + n) * 8;
-          constexpr int kHalf = kLdsPos / 2;
+          if constexpr (!SPLIT) {
+            V bv[kLdsPos];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            V bv[kHalf];
+            for (int p = 0; p < kLdsPos; ++p) bv[p] = *(const V*)(sh + bofs + p * 128);
 #pragma unroll
-            for (int p = 0; p < kHalf; ++p) bv[p] = *(const V*)(sh + bofs + (h * kHalf + p) * 128);
+            for (int p = 0; p < kLdsPos; ++p) acc[p] = H::mma(a, bv[p], acc[p]);
+            // keep 8 LDS reads ahead of the matrix-core instructions
+            __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
 #pragma unroll
-            for (int p = 0; p < kHalf; ++p) {
-              acc[h * kHalf + p] = H::mma(a, bv[p], acc[h * kHalf + p]);
-              if constexpr (SPLIT) {
-                const V blo = *(const V*)(sh_lo + bofs + (h * kHalf + p) * 128);
-                acc[h * kHalf + p] = H::mma(a, blo, acc[h * kHalf + p]);
-                acc[h * kHalf + p] = H::mma(alo, bv[p], acc[h * kHalf + p]);
-              }
+            for (int i = 0; i < kLdsPos - 8; ++i) {
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+              __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+          } else {
+#pragma unroll
+            for (int p = 0; p < kLdsPos; ++p) {
+              const V bv = *(const V*)(sh + bofs + p * 128);
+              const V blo = *(const V*)(sh_lo + bofs + p * 128);
+              acc[p] = H::mma(a, bv, acc[p]);
+              acc[p] = H::mma(a, blo, acc[p]);
+              acc[p] = H::mma(alo, bv, acc[p]);
             }
           }
+        };
+        if (c0 < c1) {
+          // in-loop fetches are unconditional (index clamped to the last chunk)
+          // so the loop body has no branches and each wait covers only the
+          // buffer about to be used
+          fetch(c0, gr0, a0, alo0);
+          fetch(min(c0 + 1, c1 - 1), gr1, a1, alo1);
+          int c = c0;
+          for (; c + 1 < c1; c += 2) {
+            run(gr0, a0, alo0);
+            fetch(min(c + 2, c1 - 1), gr0, a0, alo0);
+            run(gr1, a1, alo1);
+            fetch(min(c + 3, c1 - 1), gr1, a1, alo1);
+          }
+          if (c < c1) run(gr0, a0, alo0);
         }
       }
     }
@@ -600,8 +681,22 @@ __global__ __launch_bounds__(256) void band16_lds(BandArgs A, LdsArgs L) {
   }
   if constexpr (MODE == 1) {
     ss = wave_sum(ss);
-    if (lane == 0) A.partial[(size_t)b * kLdsRows + wave] = ss;
+    if (lane == 0) A.partial[(size_t)b * ROWS + wave] = ss;
   }
+}
+
+// H and the residual form run two waves per SIMD (their LDS tile allows two
+// or three workgroups per CU); the S^T epilogue of H^T needs more registers
+// and its wider staged window allows one workgroup per CU anyway.
+template <int PREC, bool SPLIT, int MODE, int ROWS>
+__global__ __launch_bounds__(64 * ROWS) __attribute__((amdgpu_waves_per_eu(2))) void band16_lds(
+    BandArgs A, LdsArgs L) {
+  band16_lds_body<PREC, SPLIT, MODE, ROWS>(A, L);
+}
+
+template <int PREC, bool SPLIT, int ROWS>
+__global__ __launch_bounds__(64 * ROWS) void band16_lds_adj(BandArgs A, LdsArgs L) {
+  band16_lds_body<PREC, SPLIT, 2, ROWS>(A, L);
 }
 
 // --------------------------------------------------------------------------
@@ -676,7 +771,7 @@ static bool use_lds(const psoam_plan* P, int mode) {
 static size_t band_blocks(const psoam_plan* P, int mode) {
   const BandTable& T = (mode == 2) ? P->adj : P->fwd;
   if (use_lds(P, mode)) {
-    const size_t nyb = (P->g.ny + kLdsRows - 1) / kLdsRows;
+    const size_t nyb = (P->g.ny + T.rows - 1) / T.rows;
     const size_t nxb = (P->g.nx + kLdsPos - 1) / kLdsPos;
     return (size_t)T.n_mtiles * nyb * nxb;
   }
@@ -686,7 +781,8 @@ static size_t band_blocks(const psoam_plan* P, int mode) {
 }
 
 size_t band_partials(const psoam_plan* P, int mode) {
-  return band_blocks(P, mode) * (use_lds(P, mode) ? kLdsRows : kWavesPerBlock);
+  const BandTable& T = (mode == 2) ? P->adj : P->fwd;
+  return band_blocks(P, mode) * (use_lds(P, mode) ? T.rows : kWavesPerBlock);
 }
 
 template <int MODE>
@@ -694,24 +790,38 @@ static hipError_t launch_band_lds(const psoam_plan* P, const BandTable& T, BandA
                                   dim3 grid, hipStream_t s) {
   LdsArgs L;
   L.lstart = T.d_lstart;
+  L.order = T.d_order;
   L.lgrp = T.d_lgrp;
   L.win = T.d_win;
   L.la = T.d_la;
   L.la_lo = T.d_la_lo;
   L.f = P->F;
   L.yp = P->Yp;
-  L.nyb = (P->g.ny + kLdsRows - 1) / kLdsRows;
+  L.nyb = (P->g.ny + T.rows - 1) / T.rows;
   L.nxb = (P->g.nx + kLdsPos - 1) / kLdsPos;
   const bool split = P->prec == PSOAM_BF16_SPLIT || P->prec == PSOAM_FP16_SPLIT;
   L.lds_elems = (int)(T.lds_bytes / sizeof(uint16_t) / (split ? 2 : 1));
-  const size_t lds = T.lds_bytes;
+  L.meta_off = (int)((T.lds_bytes + 15) / 16 * 16);
+  const size_t lds = L.meta_off + sizeof(uint32_t) * (2 * P->F + T.rows + 1);
+#define PSOAM_LDS_R(PR, SP, R)                                                              \
+  {                                                                                         \
+    if constexpr (MODE == 2) {                                                              \
+      auto kern = band16_lds_adj<PR, SP, R>;                                                \
+      if (lds > 64 * 1024)                                                                  \
+        (void)hipFuncSetAttribute((const void*)kern,                                        \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
+      hipLaunchKernelGGL(kern, grid, dim3(64 * R), lds, s, A, L);                           \
+    } else {                                                                                \
+      auto kern = band16_lds<PR, SP, MODE, R>;                                              \
+      if (lds > 64 * 1024)                                                                  \
+        (void)hipFuncSetAttribute((const void*)kern,                                        \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
+      hipLaunchKernelGGL(kern, grid, dim3(64 * R), lds, s, A, L);                           \
+    }                                                                                       \
+  }
 #define PSOAM_LDS(PR, SP)                                                                   \
   {                                                                                         \
-    auto kern = band16_lds<PR, SP, MODE>;                                                   \
-    if (lds > 64 * 1024)                                                                    \
-      (void)hipFuncSetAttribute((const void*)kern,                                          \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);      \
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, A, L);                                \
+    if (T.rows == 8) PSOAM_LDS_R(PR, SP, 8) else PSOAM_LDS_R(PR, SP, 4)                     \
     break;                                                                                  \
   }
   switch (P->prec) {
@@ -723,6 +833,7 @@ static hipError_t launch_band_lds(const psoam_plan* P, const BandTable& T, BandA
       return hipErrorInvalidValue;
   }
 #undef PSOAM_LDS
+#undef PSOAM_LDS_R
   return hipGetLastError();
 }
 

@@ -235,32 +235,57 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
     }
   const int l_chunks = lstart[(size_t)n_mt * F];
   T.l_chunks = l_chunks;
-  const int nwin = F + kLdsRows - 1;
-  std::vector<uint32_t> win((size_t)n_mt * nwin, 0);
-  int max_oct = 0;
-  for (int tile = 0; tile < n_mt; ++tile)
-    for (int j = 0; j < nwin; ++j) {
-      int lo = 1 << 30, hi = -1;
-      for (int r = 0; r < kLdsRows; ++r) {
-        const int dy = j - r;
-        if (dy < 0 || dy >= F) continue;
-        const size_t key = (size_t)tile * F + dy;
-        if (hi_l[key] < 0) continue;
-        lo = std::min(lo, lo_l[key]);
-        hi = std::max(hi, hi_l[key]);
+  // staged row windows for a workgroup of `rows` output rows (waves): the
+  // union of the octet ranges of the dy values j - r, r < rows
+  auto windows = [&](int rows, std::vector<uint32_t>& win, int& max_oct) {
+    const int nwin = F + rows - 1;
+    win.assign((size_t)n_mt * nwin, 0);
+    max_oct = 0;
+    for (int tile = 0; tile < n_mt; ++tile)
+      for (int j = 0; j < nwin; ++j) {
+        int lo = 1 << 30, hi = -1;
+        for (int r = 0; r < rows; ++r) {
+          const int dy = j - r;
+          if (dy < 0 || dy >= F) continue;
+          const size_t key = (size_t)tile * F + dy;
+          if (hi_l[key] < 0) continue;
+          lo = std::min(lo, lo_l[key]);
+          hi = std::max(hi, hi_l[key]);
+        }
+        if (hi >= 0) {
+          const int cnt = hi - lo + 1;
+          max_oct = std::max(max_oct, cnt);
+          win[(size_t)tile * nwin + j] = ((uint32_t)lo << 16) | (uint32_t)cnt;
+        }
       }
-      if (hi >= 0) {
-        const int cnt = hi - lo + 1;
-        max_oct = std::max(max_oct, cnt);
-        win[(size_t)tile * nwin + j] = ((uint32_t)lo << 16) | (uint32_t)cnt;
-      }
-    }
-  T.max_oct = max_oct;
+  };
   const int XW = kLdsPos + F - 1;
-  T.lds_bytes = (size_t)max_oct * XW * 16 * 8 * sizeof(uint16_t) * (split ? 2 : 1);
+  auto lds_of = [&](int rows, int max_oct) {
+    return (size_t)max_oct * XW * 16 * 8 * sizeof(uint16_t) * (split ? 2 : 1) +
+           sizeof(uint32_t) * (2 * F + rows + 1) + 16;
+  };
+  std::vector<uint32_t> win4, win8;
+  int mo4 = 0, mo8 = 0;
+  windows(4, win4, mo4);
+  windows(8, win8, mo8);
+  const size_t lds4 = lds_of(4, mo4), lds8 = lds_of(8, mo8);
+  // four rows per workgroup (measured faster than eight for both directions
+  // at the 31-wide footprint: eight rows widen the staged window); eight
+  // only when four does not fit
+  int rows = 4;
+  if (lds4 > (size_t)kLdsMaxBytes && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
+  // PSOAM_LDS_ROWS=4 or 8 overrides the choice when it fits (tests cover both)
+  if (const char* fr = std::getenv("PSOAM_LDS_ROWS")) {
+    if (fr[0] == '8' && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
+    if (fr[0] == '4' && lds4 <= (size_t)kLdsMaxBytes) rows = 4;
+  }
+  std::vector<uint32_t>& win = rows == 8 ? win8 : win4;
+  T.rows = rows;
+  T.max_oct = rows == 8 ? mo8 : mo4;
+  T.lds_bytes = (size_t)T.max_oct * XW * 16 * 8 * sizeof(uint16_t) * (split ? 2 : 1);
   // PSOAM_BAND_GLOBAL=1 keeps the plan on the global-operand kernel (tests cover both)
   const char* force_global = std::getenv("PSOAM_BAND_GLOBAL");
-  T.lds_ok = n_l < 0xffff && F < 0xffff && T.lds_bytes <= (size_t)kLdsMaxBytes &&
+  T.lds_ok = n_l < 0xffff && F < 0xffff && (rows == 8 ? lds8 : lds4) <= (size_t)kLdsMaxBytes &&
              !(force_global && force_global[0] == '1');
   if (!T.lds_ok) return PSOAM_OK;
   std::vector<uint32_t> lgrp((size_t)l_chunks * 4, 0);
@@ -284,6 +309,14 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   PSOAM_HIP(hipMalloc(&T.d_lgrp, sizeof(uint32_t) * std::max<size_t>(lgrp.size(), 4)));
   if (!lgrp.empty())
     PSOAM_HIP(hipMemcpy(T.d_lgrp, lgrp.data(), sizeof(uint32_t) * lgrp.size(), hipMemcpyHostToDevice));
+  {
+    std::vector<int> order(n_mt);
+    for (int i = 0; i < n_mt; ++i) order[i] = i;
+    auto work = [&](int t) { return lstart[(size_t)(t + 1) * F] - lstart[(size_t)t * F]; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+    PSOAM_HIP(hipMalloc(&T.d_order, sizeof(int) * n_mt));
+    PSOAM_HIP(hipMemcpy(T.d_order, order.data(), sizeof(int) * n_mt, hipMemcpyHostToDevice));
+  }
   PSOAM_HIP(hipMalloc(&T.d_win, sizeof(uint32_t) * win.size()));
   PSOAM_HIP(hipMemcpy(T.d_win, win.data(), sizeof(uint32_t) * win.size(), hipMemcpyHostToDevice));
   if (int rc = upload_vals(lvals, l_chunks, &T.d_la, &T.d_la_lo)) return rc;
@@ -292,7 +325,7 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
 
 static void free_table(BandTable& T) {
   void* ptrs[] = {T.d_start, T.d_off, T.d_a, T.d_a_lo, T.d_lstart, T.d_lgrp, T.d_win, T.d_la,
-                  T.d_la_lo};
+                  T.d_la_lo, T.d_order};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   T.d_start = nullptr;
@@ -302,6 +335,7 @@ static void free_table(BandTable& T) {
   T.d_lgrp = nullptr;
   T.d_win = nullptr;
   T.d_la = T.d_la_lo = nullptr;
+  T.d_order = nullptr;
 }
 
 void free_plan(psoam_plan* P) {

@@ -1,0 +1,74 @@
+"""Kernel micro-benchmark: repeated launches of the band contractions (and the
+TV dual step) on one synthetic workload, for profiling under rocprofv3.
+
+    python -m paper_2510_23739_amd.kbench --config C2 --prec bf16 --reps 5
+
+Prints one JSON line with the average time of each launch kind (HIP events on
+the stream the kernels run on).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--config", default="C2")
+    ap.add_argument("--crop", type=int, default=0, help="lateral crop (0 = full grid)")
+    ap.add_argument("--prec", default="bf16")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--what", default="fwd,adj,tv")
+    args = ap.parse_args()
+    import numpy as np
+    import torch
+
+    import paper_2510_23739_amd as pk
+    import synth
+
+    cfg = synth.CONFIGS[args.config]
+    if args.crop:
+        cfg = cfg.crop(args.crop, args.crop)
+    t0, taps = synth.sir_table(cfg.nz, cfg.f, cfg.nt)
+    phi = synth.phi_depth(cfg.nz)
+    sp = synth.species(cfg.n_species)
+    rng = np.random.default_rng(0)
+    c = torch.from_numpy(rng.random(cfg.c_shape, dtype=np.float32)).cuda()
+    plan = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=args.prec)
+    y = torch.empty(cfg.y_shape, dtype=torch.float32, device="cuda")
+    g = torch.empty(cfg.c_shape, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(args.reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.reps
+
+    out = {"config": cfg.name, "prec": args.prec, "stats": plan.stats()}
+    what = args.what.split(",")
+    if "fwd" in what:
+        plan.apply_A(c, y)
+        out["H_ms"] = timed(lambda: plan.band_only(0, y))
+    if "adj" in what:
+        plan.apply_A(c, y)
+        plan.apply_AT(y, g)
+        out["HT_ms"] = timed(lambda: plan.band_only(1, g))
+    if "tv" in what:
+        out["prox_tv_k20_ms"] = timed(lambda: plan.prox_tv(c, 0.01, 20, x=g))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -31,6 +31,12 @@ def lam_weights(aty_inf: float):
     return 5e-3 * aty_inf, 1e-2 * aty_inf
 
 
+def nan_buf(shape):
+    """Output buffer poisoned with NaN, so a call that writes nothing fails."""
+    import torch
+    return torch.full(tuple(shape), float("nan"), dtype=torch.float32, device="cuda")
+
+
 def say(msg: str) -> None:
     print(msg, flush=True)
 

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_common import lib_plan, oracle_S, ragged_cfg, say, torch_cuda
+from gpu_common import lib_plan, nan_buf, oracle_S, ragged_cfg, say, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -34,13 +34,13 @@ def test_apply_A_and_AT_C1(c1, prec):
     say(f"[parity] C1 apply_A/AT prec={prec}")
     plan = lib_plan(cfg, t0, taps, phi, sp, prec)
     c = torch.from_numpy(c_true).cuda()
-    y = plan.apply_A(c)
+    y = plan.apply_A(c, nan_buf(cfg.y_shape))
     y_ref = oracle.apply_A(c_true, S, t0, taps, cfg.nt)
     e = oracle.rel_err(y.cpu().numpy(), y_ref)
     say(f"   rel err A = {e:.3e}")
     assert e <= TOL_OP[prec]
     yr = np.random.default_rng(1).standard_normal(cfg.y_shape).astype(np.float32)
-    g = plan.apply_AT(torch.from_numpy(yr).cuda())
+    g = plan.apply_AT(torch.from_numpy(yr).cuda(), nan_buf(cfg.c_shape))
     g_ref = oracle.apply_AT(yr, S, t0, taps, cfg.nz)
     e = oracle.rel_err(g.cpu().numpy(), g_ref)
     say(f"   rel err AT = {e:.3e}")
@@ -49,25 +49,27 @@ def test_apply_A_and_AT_C1(c1, prec):
 
 @pytest.mark.parametrize("prec,kernel", [("fp32", "global"), ("bf16", "lds"), ("bf16_split", "lds"),
                                          ("fp16", "lds"), ("bf16", "global"),
-                                         ("bf16_split", "global")])
+                                         ("bf16_split", "global"), ("bf16", "lds8"),
+                                         ("fp16_split", "lds8")])
 def test_ragged_random_table(prec, kernel, monkeypatch):
     """Sizes off every tile boundary, per-voxel fluence with the fluence-
     dependent rate, asymmetric random band running off both ends; both the
     LDS-staged and the global-operand band kernels."""
     torch = torch_cuda()
     monkeypatch.setenv("PSOAM_BAND_GLOBAL", "1" if kernel == "global" else "0")
+    monkeypatch.setenv("PSOAM_LDS_ROWS", "8" if kernel == "lds8" else "4")
     cfg, t0, taps, phi, sp = ragged_cfg(3)
     say(f"[parity] ragged prec={prec}")
     S = oracle_S(cfg, phi, sp)
     plan = lib_plan(cfg, t0, taps, phi, sp, prec)
     rng = np.random.default_rng(4)
     c = rng.standard_normal(cfg.c_shape).astype(np.float32)
-    y = plan.apply_A(torch.from_numpy(c).cuda()).cpu().numpy()
+    y = plan.apply_A(torch.from_numpy(c).cuda(), nan_buf(cfg.y_shape)).cpu().numpy()
     e = oracle.rel_err(y, oracle.apply_A(c, S, t0, taps, cfg.nt))
     say(f"   rel err A = {e:.3e}")
     assert e <= TOL_OP[prec]
     yr = rng.standard_normal(cfg.y_shape).astype(np.float32)
-    g = plan.apply_AT(torch.from_numpy(yr).cuda()).cpu().numpy()
+    g = plan.apply_AT(torch.from_numpy(yr).cuda(), nan_buf(cfg.c_shape)).cpu().numpy()
     e = oracle.rel_err(g, oracle.apply_AT(yr, S, t0, taps, cfg.nz))
     say(f"   rel err AT = {e:.3e}")
     assert e <= TOL_OP[prec]
@@ -82,7 +84,7 @@ def test_point_source_fp32(c1):
     plan = lib_plan(cfg, t0, taps, phi, sp, "fp32")
     c = np.zeros(cfg.c_shape, np.float32)
     c[1, 3, 30, 9] = 1.0   # near a lateral border
-    y = plan.apply_A(torch.from_numpy(c).cuda()).cpu().numpy()
+    y = plan.apply_A(torch.from_numpy(c).cuda(), nan_buf(cfg.y_shape)).cpu().numpy()
     y_ref = oracle.apply_A(c, S, t0, taps, cfg.nt)
     assert oracle.rel_err(y, y_ref) <= 1e-6
     assert np.count_nonzero(y[:, 10:, :20]) == 0
@@ -96,8 +98,8 @@ def test_dot_product_identity(c1, prec):
     rng = np.random.default_rng(7)
     x = torch.from_numpy(rng.standard_normal(cfg.c_shape).astype(np.float32)).cuda()
     yv = torch.from_numpy(rng.standard_normal(cfg.y_shape).astype(np.float32)).cuda()
-    lhs = float((plan.apply_A(x).double() * yv.double()).sum())
-    rhs = float((x.double() * plan.apply_AT(yv).double()).sum())
+    lhs = float((plan.apply_A(x, nan_buf(cfg.y_shape)).double() * yv.double()).sum())
+    rhs = float((x.double() * plan.apply_AT(yv, nan_buf(cfg.c_shape)).double()).sum())
     scale = float(plan.apply_A(x).double().norm() * yv.double().norm())
     say(f"[parity] dot test {prec}: |lhs-rhs|/scale = {abs(lhs - rhs) / scale:.3e}")
     assert abs(lhs - rhs) <= (1e-6 if prec == "fp32" else 2e-3) * scale
@@ -110,9 +112,9 @@ def test_prox_l1_matches_closed_form():
     z[:5] = [0.25, -0.25, 0.0, 0.2500001, -0.2499999]
     th = np.float32(0.25)
     zt = torch.from_numpy(z).cuda()
-    x1 = pk.prox_l1(zt, float(th), nonneg=True).cpu().numpy()
+    x1 = pk.prox_l1(zt, float(th), nonneg=True, x=nan_buf(zt.shape)).cpu().numpy()
     np.testing.assert_array_equal(x1, np.maximum(z - th, np.float32(0)))
-    x2 = pk.prox_l1(zt, float(th), nonneg=False).cpu().numpy()
+    x2 = pk.prox_l1(zt, float(th), nonneg=False, x=nan_buf(zt.shape)).cpu().numpy()
     ref = np.sign(z) * np.maximum(np.abs(z) - th, np.float32(0))
     np.testing.assert_array_equal(x2, ref.astype(np.float32))
     # in place
@@ -126,7 +128,8 @@ def test_prox_tv_matches_oracle(c1, n_inner, theta, nonneg):
     cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
     plan = lib_plan(cfg, t0, taps, phi, sp, "fp32")
     z = (c_true + 0.2 * np.random.default_rng(5).standard_normal(cfg.c_shape)).astype(np.float32)
-    x = plan.prox_tv(torch.from_numpy(z).cuda(), theta, n_inner, nonneg=nonneg).cpu().numpy()
+    x = plan.prox_tv(torch.from_numpy(z).cuda(), theta, n_inner, nonneg=nonneg,
+                     x=nan_buf(cfg.c_shape)).cpu().numpy()
     ref = oracle.prox_tv(z, theta, n_inner, nonneg=nonneg)
     e = oracle.rel_err(x, ref)
     say(f"[parity] prox_tv K2={n_inner} theta={theta}: rel err {e:.3e}")
