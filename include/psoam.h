@@ -198,6 +198,8 @@ typedef struct {
   int64_t chunks[2];
   int64_t executed_macs[2];
   int64_t operand_bytes[2];  /* padded operand buffer of H (0) and H^T (1) */
+  int64_t lds_bytes[2];      /* LDS per workgroup of the staged kernel, 0 if not used */
+  int32_t lds_rows[2];       /* output rows per workgroup of the staged kernel */
 } psoam_plan_info;
 
 int psoam_plan_stats(const psoam_plan* plan, psoam_plan_info* info);

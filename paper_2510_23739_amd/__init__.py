@@ -101,7 +101,8 @@ class Plan:
         info = _lib.PlanInfo()
         check(load().psoam_plan_stats(self.handle, C.byref(info)))
         return {k: [int(getattr(info, k)[0]), int(getattr(info, k)[1])]
-                for k in ("useful_macs", "chunks", "executed_macs", "operand_bytes")}
+                for k in ("useful_macs", "chunks", "executed_macs", "operand_bytes", "lds_bytes",
+                          "lds_rows")}
 
     def band_only(self, direction: int, out, stream=None):
         """Launch only the band kernel (0: H -> y, 1: S^T H^T -> c) on the

@@ -37,7 +37,8 @@ class SolveStats(C.Structure):
 
 class PlanInfo(C.Structure):
     _fields_ = [("useful_macs", C.c_int64 * 2), ("chunks", C.c_int64 * 2),
-                ("executed_macs", C.c_int64 * 2), ("operand_bytes", C.c_int64 * 2)]
+                ("executed_macs", C.c_int64 * 2), ("operand_bytes", C.c_int64 * 2),
+                ("lds_bytes", C.c_int64 * 2), ("lds_rows", C.c_int32 * 2)]
 
 
 EXPORTS = {

@@ -385,6 +385,9 @@ int psoam_plan_stats(const psoam_plan* plan, psoam_plan_info* info) {
     info->useful_macs[d] = (int64_t)T[d]->useful_macs;
     info->chunks[d] = T[d]->n_chunks;
     info->executed_macs[d] = (int64_t)T[d]->n_chunks * tile;
+    const bool staged = half && T[d]->lds_ok;
+    info->lds_bytes[d] = staged ? (int64_t)T[d]->lds_bytes : 0;
+    info->lds_rows[d] = staged ? T[d]->rows : 0;
   }
   info->operand_bytes[0] = (int64_t)plan->bq_bytes;
   info->operand_bytes[1] = (int64_t)plan->rq_bytes;

@@ -269,10 +269,12 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   windows(4, win4, mo4);
   windows(8, win8, mo8);
   const size_t lds4 = lds_of(4, mo4), lds8 = lds_of(8, mo8);
-  // four rows per workgroup (measured faster than eight for both directions
-  // at the 31-wide footprint: eight rows widen the staged window); eight
-  // only when four does not fit
+  // Rows per workgroup: four while at least two such workgroups fit in one
+  // CU's LDS (eight waves per CU); when only one fits, eight rows keep two
+  // waves per SIMD resident (measured: H^T at 31 x 31 footprint 2.48 ms with
+  // eight rows vs 4.44 ms with four; H 2.55 ms with four vs 2.64 with eight)
   int rows = 4;
+  if (lds4 > (size_t)kLdsMaxBytes / 2 && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
   if (lds4 > (size_t)kLdsMaxBytes && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
   // PSOAM_LDS_ROWS=4 or 8 overrides the choice when it fits (tests cover both)
   if (const char* fr = std::getenv("PSOAM_LDS_ROWS")) {

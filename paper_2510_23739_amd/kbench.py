@@ -58,6 +58,14 @@ def main():
 
     out = {"config": cfg.name, "prec": args.prec, "stats": plan.stats()}
     what = args.what.split(",")
+    if "copy" in what:
+        # plain device copy of a known size: calibrates the HBM byte counters
+        n = 1 << 28  # 1 GiB of float32
+        xa = torch.ones(n, dtype=torch.float32, device="cuda")
+        xb = torch.empty_like(xa)
+        out["copy_bytes"] = 4 * n
+        out["copy_ms"] = timed(lambda: xb.copy_(xa))
+        del xa, xb
     if "fwd" in what:
         plan.apply_A(c, y)
         out["H_ms"] = timed(lambda: plan.band_only(0, y))
