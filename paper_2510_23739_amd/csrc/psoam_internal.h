@@ -31,6 +31,7 @@ constexpr int kWavesPerBlock = 4;    // consecutive output tiles of one position
 constexpr float kFp16Scale = 256.0f; // FP16 operands carry this power-of-two scale
 constexpr int kLdsPos = 16;          // staged kernel: positions per wave
 constexpr int kLdsMaxBytes = 160 * 1024;
+constexpr int kRunMax = 8;           // longest sliding run (chunks) of the staged kernel
 
 // Photo-switching coefficients in the form the kernels evaluate:
 //   S_v[k][s] = phi_v * (a[s] + b[s] * exp(-k * phi_v^gamma * inv_tau[s]))
@@ -66,13 +67,22 @@ struct BandTable {
   int l_chunks = 0;
   int max_oct = 0;             // widest staged octet window
   size_t lds_bytes = 0;        // dynamic LDS per workgroup
-  int* d_lstart = nullptr;     // [n_mtiles * F + 1]
-  uint32_t* d_lgrp = nullptr;  // [l_chunks * 4]  octet << 16 | dx
+  int* d_lstart = nullptr;     // [n_mtiles * F + 1] first run of each (tile, dy)
+  uint32_t* d_lgrp = nullptr;  // [n_runs * 4]  octet << 16 | dx at the run's first chunk
   uint32_t* d_win = nullptr;   // [n_mtiles * (F + rows - 1)]  obase << 16 | ocnt
   void* d_la = nullptr;
   void* d_la_lo = nullptr;
   int* d_order = nullptr;      // [n_mtiles] tiles by decreasing chunk count
+  int n_runs = 0;
+  int max_runs = 0;            // most runs of one output tile (LDS run table)
+  int* d_rinfo = nullptr;      // [n_runs * 2] run length, first chunk
 };
+
+// LDS bytes of the staged kernel's per-tile tables: row windows (F + rows - 1),
+// run bounds (F + 1), run records (4 group words + 2 ints each)
+inline size_t lds_meta_bytes(int F, int rows, int max_runs) {
+  return sizeof(uint32_t) * ((size_t)(F + rows - 1) + (F + 1) + 6 * (size_t)max_runs) + 16;
+}
 
 struct Workspace {
   size_t bytes = 0;

@@ -31,6 +31,10 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// word 3 of a raw buffer resource on CDNA (32-bit data format, no swizzle)
+constexpr int kBufWord3 = 0x00020000;
+// s_waitcnt operand: vmcnt(0), expcnt and lgkmcnt left at their maxima
+constexpr int kVmcnt0 = 0x0F70;
 
 template <int PREC>
 struct Half;
@@ -480,8 +484,11 @@ struct LdsArgs {
   const void* la;
   const void* la_lo;
   int f, yp, nyb, nxb, lds_elems;
-  int meta_off;  // byte offset of the per-tile window / list-bound table in LDS
+  int meta_off;  // byte offset of the per-tile window / run tables in LDS
   const int* order;  // output tiles by decreasing work
+  const int* rinfo;  // [runs][2]: length, first chunk
+  int max_runs;      // most runs of one tile
+  int la_bytes;      // bytes of la (and la_lo), including kRunMax zero chunks at the end
 };
 
 template <int PREC, bool SPLIT, int MODE, int ROWS>
@@ -492,9 +499,11 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   E* sh = (E*)smem_raw;
   E* sh_lo = sh + L.lds_elems;
-  // per-tile row windows and chunk-list bounds, read once into LDS
+  // per-tile row windows, run bounds and run records, read once into LDS
   uint32_t* s_win = (uint32_t*)(smem_raw + L.meta_off);
   int* s_lstart = (int*)(s_win + (L.f + ROWS - 1));
+  uint32_t* s_rgrp = (uint32_t*)(s_lstart + L.f + 1);      // [max_runs][4]
+  int* s_rinfo = (int*)(s_rgrp + 4 * L.max_runs);           // [max_runs][2]
   // Block order.  Output tiles differ several-fold in work (bands crowd
   // around the focal time), so (1) every XCD (blocks are dealt to the 8 XCDs
   // round-robin) receives all tiles for its own share of position blocks,
@@ -531,153 +540,141 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   {
     const int nw = L.f + ROWS - 1;
     for (int i = (int)threadIdx.x; i < nw; i += NT) s_win[i] = L.win[mtile * nw + i];
-    for (int i = (int)threadIdx.x; i <= L.f; i += NT) s_lstart[i] = L.lstart[mtile * L.f + i];
+    const int rt0 = L.lstart[mtile * L.f];
+    for (int i = (int)threadIdx.x; i <= L.f; i += NT) s_lstart[i] = L.lstart[mtile * L.f + i] - rt0;
+    const int nrun = L.lstart[(mtile + 1) * L.f] - rt0;
+    for (int i = (int)threadIdx.x; i < 4 * nrun; i += NT) s_rgrp[i] = L.lgrp[4 * rt0 + i];
+    for (int i = (int)threadIdx.x; i < 2 * nrun; i += NT) s_rinfo[i] = L.rinfo[2 * rt0 + i];
     __syncthreads();
   }
   double ss = 0.0;
   const int nb_n = A.kp / 16;
+  // Band blocks of the current run, in registers.  Each run loads the next
+  // run's blocks slot by slot as its own chunks finish with them, so the
+  // loads are in flight while the remaining chunks compute.
+  // Slot i of a run holds chunk (first chunk + i); slots past the run's
+  // length read the following chunks (or the zero chunks that end the table)
+  // and are not used.  Buffer loads share one offset register per run.
+  const int nrun = L.lstart[(mtile + 1) * L.f] - L.lstart[mtile * L.f];
+  const __amdgpu_buffer_rsrc_t rs_hi = __builtin_amdgcn_make_buffer_rsrc((void*)L.la, (short)0, L.la_bytes, kBufWord3);
+  const __amdgpu_buffer_rsrc_t rs_lo =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(SPLIT ? L.la_lo : L.la), (short)0, L.la_bytes, kBufWord3);
+  // cb is wave-uniform: the lane offset is the only vector address operand
+  const int vo = lane * (int)sizeof(V);
+  auto load_run = [&](int cb, V (&ab)[kRunMax], V (&al)[SPLIT ? kRunMax : 1], int i) {
+    const int so = (cb + i) * kWaveLanes * (int)sizeof(V);
+    ab[i] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs_hi, vo, so, 0));
+    if constexpr (SPLIT) al[i] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs_lo, vo, so, 0));
+  };
+  V ab[kRunMax];
+  V al[SPLIT ? kRunMax : 1];
+  if (row_ok && nrun > 0) {
+    const int cb0 = __builtin_amdgcn_readfirstlane(s_rinfo[1]);
+#pragma unroll
+    for (int i = 0; i < kRunMax; ++i) load_run(cb0, ab, al, i);
+  }
+  __builtin_amdgcn_s_waitcnt(kVmcnt0);
   for (int pb = 0; pb < nb_n; ++pb) {
     f32x4 acc[kLdsPos];
     zero_acc(acc);
-    // Software pipeline over staged rows: the first kStageBatch loads per
-    // thread of row j+1 are issued right after row j is committed to LDS, so
-    // their latency overlaps row j's contractions.  Thread t stages items
-    // t, t+NT, ...: item it = (octet oi, column xi, pulse nn) with
-    // it = (oi*XW + xi)*16 + nn, so nn = t%16 is fixed and (xi, oi) advance
-    // by NT/16 columns per step (at most one octet carry while XW >= NT/16;
-    // a wider step carries with a loop).
+    // Staging: thread t loads items t, t+NT, ... of the row, where item
+    // it = (oi*XW + xi)*16 + nn is one 16-byte octet of pulse nn at column xi
+    // of octet oi; nn = t%16 is fixed and (xi, oi) advance by NT/16 columns
+    // per step.  kStageBatch loads are in flight before their LDS writes.
     constexpr int NPRE = SPLIT ? kStageBatch / 2 : kStageBatch;
-    V pre[NPRE];
-    V pre_lo[SPLIT ? NPRE : 1];
     const int t16 = (int)threadIdx.x >> 4;
     const int tnn = (int)threadIdx.x & 15;
-    auto row_ok_at = [&](int jj, int& oc, int& ob) -> bool {
-      if (jj >= nwin) return false;
-      const uint32_t w = s_win[jj];
-      oc = (int)(w & 0xffffu);
-      ob = (int)(w >> 16);
-      return oc != 0 && iy0 + jj < L.yp;
-    };
-    // loads items [u0*NT, (u0+NPRE)*NT) of row jj into regs
-    auto load_batch = [&](int jj, int oc, int ob, int u0, V (&dst)[NPRE], V (&dst_lo)[SPLIT ? NPRE : 1]) {
-      const int items = oc * XW * 16;
-      const E* rowp = q + (size_t)(iy0 + jj) * A.xp * A.ps;
-      const E* rowp_lo = SPLIT ? qlo + (size_t)(iy0 + jj) * A.xp * A.ps : nullptr;
-      int r2 = u0 * (NT / 16) + t16;
-      int xi = r2 % XW, oi = r2 / XW;
-      const int ps = (int)A.ps;
-      int off = (ix0 + xi) * ps + ((ob + oi) * A.kp + pb * 16 + tnn) * 8;
-#pragma unroll
-      for (int u = 0; u < NPRE; ++u) {
-        if ((u0 + u) * NT + (int)threadIdx.x < items) {
-          dst[u] = *(const V*)(rowp + off);
-          if constexpr (SPLIT) dst_lo[u] = *(const V*)(rowp_lo + off);
-        }
-        xi += NT / 16;
-        off += (NT / 16) * ps;
-        while (xi >= XW) {
-          xi -= XW;
-          off += -XW * ps + A.kp * 8;
-        }
-      }
-    };
-    auto store_batch = [&](int oc, int u0, const V (&src)[NPRE], const V (&src_lo)[SPLIT ? NPRE : 1]) {
-      const int items = oc * XW * 16;
-#pragma unroll
-      for (int u = 0; u < NPRE; ++u) {
-        const int it = (u0 + u) * NT + (int)threadIdx.x;
-        if (it < items) {
-          *(V*)(sh + it * 8) = src[u];
-          if constexpr (SPLIT) *(V*)(sh_lo + it * 8) = src_lo[u];
-        }
-      }
-    };
-    int ocnt_n = 0, obase_n = 0;
-    bool ok_n = row_ok_at(0, ocnt_n, obase_n);
-    if (ok_n) load_batch(0, ocnt_n, obase_n, 0, pre, pre_lo);
     for (int j = 0; j < nwin; ++j) {
-      const bool ok = ok_n;
-      const int ocnt = ocnt_n, obase = obase_n;
-      if (!ok) {  // uniform over the block
-        ok_n = row_ok_at(j + 1, ocnt_n, obase_n);
-        if (ok_n) load_batch(j + 1, ocnt_n, obase_n, 0, pre, pre_lo);
-        continue;
-      }
+      const uint32_t wj = s_win[j];
+      const int ocnt = (int)(wj & 0xffffu), obase = (int)(wj >> 16);
+      if (ocnt == 0 || iy0 + j >= L.yp) continue;  // uniform over the block
       __syncthreads();  // the previous row's contractions are done with LDS
-      store_batch(ocnt, 0, pre, pre_lo);
       const int items = ocnt * XW * 16;
-      // items beyond the prefetched part: batches with all loads in flight
-      for (int u0 = NPRE; u0 * NT < items; u0 += NPRE) {
+      const E* rowp = q + (size_t)(iy0 + j) * A.xp * A.ps;
+      const E* rowp_lo = SPLIT ? qlo + (size_t)(iy0 + j) * A.xp * A.ps : nullptr;
+      const int ps = (int)A.ps;
+      for (int u0 = 0; u0 * NT < items; u0 += NPRE) {
         V tmp[NPRE];
         V tmp_lo[SPLIT ? NPRE : 1];
-        load_batch(j, ocnt, obase, u0, tmp, tmp_lo);
-        store_batch(ocnt, u0, tmp, tmp_lo);
+        int r2 = u0 * (NT / 16) + t16;
+        int xi = r2 % XW, oi = r2 / XW;
+        int off = (ix0 + xi) * ps + ((obase + oi) * A.kp + pb * 16 + tnn) * 8;
+#pragma unroll
+        for (int u = 0; u < NPRE; ++u) {
+          if ((u0 + u) * NT + (int)threadIdx.x < items) {
+            tmp[u] = *(const V*)(rowp + off);
+            if constexpr (SPLIT) tmp_lo[u] = *(const V*)(rowp_lo + off);
+          }
+          xi += NT / 16;
+          off += (NT / 16) * ps;
+          while (xi >= XW) {
+            xi -= XW;
+            off += -XW * ps + A.kp * 8;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < NPRE; ++u) {
+          const int it = (u0 + u) * NT + (int)threadIdx.x;
+          if (it < items) {
+            *(V*)(sh + it * 8) = tmp[u];
+            if constexpr (SPLIT) *(V*)(sh_lo + it * 8) = tmp_lo[u];
+          }
+        }
       }
       __syncthreads();
-      ok_n = row_ok_at(j + 1, ocnt_n, obase_n);
-      if (ok_n) load_batch(j + 1, ocnt_n, obase_n, 0, pre, pre_lo);
       const int dy = j - wave;
       if (row_ok && dy >= 0 && dy < F) {
-        const int c0 = s_lstart[dy], c1 = s_lstart[dy + 1];
-        // two chunk buffers, each reloaded right after its chunk's products
-        // are issued, so a chunk's group word and band block travel from L2
-        // while the other buffer's chunk runs (no register copies between
-        // iterations: a copy would force a wait on the newest load)
-        uint32_t gr0 = 0, gr1 = 0;
-        V a0{}, a1{}, alo0{}, alo1{};
-        auto fetch = [&](int cc, uint32_t& grx, V& ax, V& alox) {
-          grx = L.lgrp[cc * 4 + g];
-          ax = av[(size_t)cc * kWaveLanes + lane];
-          if constexpr (SPLIT) alox = avlo[(size_t)cc * kWaveLanes + lane];
-        };
-        auto run = [&](uint32_t gr, const V& a, const V& alo) {
-          const int dx = (int)(gr & 0xffffu);
-          const int o = (int)(gr >> 16);
-          const int oo = (o == 0xffff) ? 0 : o - obase;
-          const int bofs = ((oo * XW + dx) * 16 + n) * 8;
-          if constexpr (!SPLIT) {
-            V bv[kLdsPos];
+        // Runs of this (tile, dy).  Within a run the four groups keep their
+        // octet and step their offset by -1 per chunk, so position p's operand
+        // at chunk i is position p-1's at chunk i-1: a 16-fragment register
+        // window slides and one new column is read from LDS per chunk.
+        const int r0 = __builtin_amdgcn_readfirstlane(s_lstart[dy]);
+        const int r1 = __builtin_amdgcn_readfirstlane(s_lstart[dy + 1]);
+        for (int rr = r0; rr < r1; ++rr) {
+          const uint32_t gr = s_rgrp[4 * rr + g];
+          const int m = __builtin_amdgcn_readfirstlane(s_rinfo[2 * rr]);
+          const int d = (int)(gr & 0xffffu);
+          const int oo = (int)(gr >> 16) - obase;
+          const int base = ((oo * XW + d) * 16 + n) * 8;
+          // the run after this one (the first of the tile after the last: the
+          // band blocks do not depend on the pulse block)
+          const int nx = rr + 1 == nrun ? 0 : rr + 1;
+          const int cb2 = __builtin_amdgcn_readfirstlane(s_rinfo[2 * nx + 1]);
+          V R[kLdsPos];
+          V Rl[SPLIT ? kLdsPos : 1];
 #pragma unroll
-            for (int p = 0; p < kLdsPos; ++p) bv[p] = *(const V*)(sh + bofs + p * 128);
-#pragma unroll
-            for (int p = 0; p < kLdsPos; ++p) acc[p] = H::mma(a, bv[p], acc[p]);
-            // keep 8 LDS reads ahead of the matrix-core instructions
-            __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
-#pragma unroll
-            for (int i = 0; i < kLdsPos - 8; ++i) {
-              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-              __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            }
-            __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
-          } else {
-#pragma unroll
-            for (int p = 0; p < kLdsPos; ++p) {
-              const V bv = *(const V*)(sh + bofs + p * 128);
-              const V blo = *(const V*)(sh_lo + bofs + p * 128);
-              acc[p] = H::mma(a, bv, acc[p]);
-              acc[p] = H::mma(a, blo, acc[p]);
-              acc[p] = H::mma(alo, bv, acc[p]);
-            }
+          for (int p = 0; p < kLdsPos; ++p) {
+            R[p] = *(const V*)(sh + base + p * 128);
+            if constexpr (SPLIT) Rl[p] = *(const V*)(sh_lo + base + p * 128);
           }
-        };
-        if (c0 < c1) {
-          // in-loop fetches are unconditional (index clamped to the last chunk)
-          // so the loop body has no branches and each wait covers only the
-          // buffer about to be used
-          fetch(c0, gr0, a0, alo0);
-          fetch(min(c0 + 1, c1 - 1), gr1, a1, alo1);
-          int c = c0;
-          for (; c + 1 < c1; c += 2) {
-            run(gr0, a0, alo0);
-            fetch(min(c + 2, c1 - 1), gr0, a0, alo0);
-            run(gr1, a1, alo1);
-            fetch(min(c + 3, c1 - 1), gr1, a1, alo1);
+#pragma unroll
+          for (int i = 0; i < kRunMax; ++i) {
+            if (i < m) {
+              if (i > 0) {
+                R[(kLdsPos - i) & (kLdsPos - 1)] = *(const V*)(sh + base - i * 128);
+                if constexpr (SPLIT) Rl[(kLdsPos - i) & (kLdsPos - 1)] = *(const V*)(sh_lo + base - i * 128);
+              }
+#pragma unroll
+              for (int p = 0; p < kLdsPos; ++p) {
+                const int w = (p - i) & (kLdsPos - 1);
+                acc[p] = H::mma(ab[i], R[w], acc[p]);
+                if constexpr (SPLIT) {
+                  acc[p] = H::mma(ab[i], Rl[w], acc[p]);
+                  acc[p] = H::mma(al[i], R[w], acc[p]);
+                }
+              }
+            }
+            // slot i is free: load the next run's block i into it
+            load_run(cb2, ab, al, i);
           }
-          if (c < c1) run(gr0, a0, alo0);
         }
       }
     }
     if (row_ok) epi_block<MODE, kLdsPos, PREC, SPLIT>(A, acc, mtile, iy, ix0, pb * 16, pb == 0, ss);
+    // Retire the epilogue's stores here: with stores and loads both in
+    // flight the memory counter no longer orders the band-block loads, and
+    // every chunk of the run loop would wait for all of them.
+    __builtin_amdgcn_s_waitcnt(kVmcnt0);
   }
   if constexpr (MODE == 1) {
     ss = wave_sum(ss);
@@ -791,10 +788,13 @@ static hipError_t launch_band_lds(const psoam_plan* P, const BandTable& T, BandA
   LdsArgs L;
   L.lstart = T.d_lstart;
   L.order = T.d_order;
+  L.rinfo = T.d_rinfo;
+  L.max_runs = T.max_runs;
   L.lgrp = T.d_lgrp;
   L.win = T.d_win;
   L.la = T.d_la;
   L.la_lo = T.d_la_lo;
+  L.la_bytes = (int)((size_t)(T.l_chunks + kRunMax) * kWaveLanes * 8 * sizeof(uint16_t));
   L.f = P->F;
   L.yp = P->Yp;
   L.nyb = (P->g.ny + T.rows - 1) / T.rows;
@@ -802,7 +802,7 @@ static hipError_t launch_band_lds(const psoam_plan* P, const BandTable& T, BandA
   const bool split = P->prec == PSOAM_BF16_SPLIT || P->prec == PSOAM_FP16_SPLIT;
   L.lds_elems = (int)(T.lds_bytes / sizeof(uint16_t) / (split ? 2 : 1));
   L.meta_off = (int)((T.lds_bytes + 15) / 16 * 16);
-  const size_t lds = L.meta_off + sizeof(uint32_t) * (2 * P->F + T.rows + 1);
+  const size_t lds = L.meta_off + lds_meta_bytes(P->F, T.rows, T.max_runs);
 #define PSOAM_LDS_R(PR, SP, R)                                                              \
   {                                                                                         \
     if constexpr (MODE == 2) {                                                              \

@@ -145,9 +145,11 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
       }
     }
   };
+  // `pad` zero chunks follow the table (read, unused, by the staged kernel's
+  // fixed-width run loads)
   auto upload_vals = [&](const std::vector<float>& vals, int n_chunks, void** hi_out,
-                         void** lo_out) -> int {
-    const size_t nc = n_chunks > 0 ? (size_t)n_chunks : 1;
+                         void** lo_out, int pad) -> int {
+    const size_t nc = (n_chunks > 0 ? (size_t)n_chunks : 1) + (size_t)pad;
     if (!half) {
       PSOAM_HIP(hipMalloc(hi_out, sizeof(float) * 64 * nc));
       if (n_chunks)
@@ -165,10 +167,12 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
       }
     }
     PSOAM_HIP(hipMalloc(hi_out, sizeof(uint16_t) * 512 * nc));
+    PSOAM_HIP(hipMemset(*hi_out, 0, sizeof(uint16_t) * 512 * nc));
     if (n_chunks)
       PSOAM_HIP(hipMemcpy(*hi_out, hi.data(), sizeof(uint16_t) * 512 * n_chunks, hipMemcpyHostToDevice));
     if (split) {
       PSOAM_HIP(hipMalloc(lo_out, sizeof(uint16_t) * 512 * nc));
+      PSOAM_HIP(hipMemset(*lo_out, 0, sizeof(uint16_t) * 512 * nc));
       if (n_chunks)
         PSOAM_HIP(hipMemcpy(*lo_out, lo.data(), sizeof(uint16_t) * 512 * n_chunks, hipMemcpyHostToDevice));
     }
@@ -209,32 +213,87 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
     const size_t nc = n_chunks > 0 ? (size_t)n_chunks : 1;
     PSOAM_HIP(hipMalloc(&T.d_off, sizeof(int) * 4 * nc));
     if (n_chunks) PSOAM_HIP(hipMemcpy(T.d_off, off.data(), sizeof(int) * 4 * n_chunks, hipMemcpyHostToDevice));
-    if (int rc = upload_vals(vals, n_chunks, &T.d_a, &T.d_a_lo)) return rc;
+    if (int rc = upload_vals(vals, n_chunks, &T.d_a, &T.d_a_lo, 0)) return rc;
   }
   if (!half) return PSOAM_OK;
 
-  // ---- packing 2: per (tile, dy) for the LDS-staged kernel
-  std::vector<int> lstart((size_t)n_mt * F + 1, 0);
-  std::vector<Group> lgroups;
+  // ---- packing 2: runs per (tile, dy) for the LDS-staged kernel.
+  // A run holds m consecutive chunks whose 4 groups keep their octet while
+  // their offset steps dx_g, dx_g - 1, ..., dx_g - m + 1: the operand of
+  // position p at chunk i is then the one of position p - 1 at chunk i - 1,
+  // so the kernel slides a register window and reads one new column per
+  // chunk.  The marked (dx, octet) pairs of each octet are split into
+  // pieces of at most kRunMax consecutive dx, grouped four per run (longest
+  // first); a lane shorter than the run is placed so that its idle chunks
+  // still address columns inside [0, F) (with zero band values).
+  const int run_max = std::max(1, std::min(kRunMax, (F + 1) / 2));
+  struct Piece { int l, lo, len; };
+  std::vector<int> rstart((size_t)n_mt * F + 1, 0);
+  std::vector<uint32_t> rgrp;   // 4 per run: octet << 16 | dx at the run's first chunk
+  std::vector<int> rlen, rcb;   // run length, first chunk index
+  std::vector<Group> lgroups;   // 4 per chunk (active groups; jy < 0 for idle lanes)
   std::vector<int> lo_l((size_t)n_mt * F, 1 << 30), hi_l((size_t)n_mt * F, -1);
+  int l_chunks = 0;
+  std::vector<Piece> pieces;
   for (int tile = 0; tile < n_mt; ++tile)
     for (int jy = 0; jy < F; ++jy) {
       const size_t key = (size_t)tile * F + jy;
-      size_t cnt = 0;
-      for (int jx = 0; jx < F; ++jx)
-        for (int l = 0; l < n_l; ++l)
-          if (mark[((size_t)tile * n_off + (size_t)jy * F + jx) * n_l + l]) {
-            lgroups.push_back({jy, jx, l});
-            ++cnt;
-            lo_l[key] = std::min(lo_l[key], l);
-            hi_l[key] = std::max(hi_l[key], l);
+      pieces.clear();
+      for (int l = 0; l < n_l; ++l) {
+        int jx = 0;
+        while (jx < F) {
+          if (!mark[((size_t)tile * n_off + (size_t)jy * F + jx) * n_l + l]) { ++jx; continue; }
+          int e = jx;
+          while (e + 1 < F && mark[((size_t)tile * n_off + (size_t)jy * F + e + 1) * n_l + l]) ++e;
+          for (int lo = jx; lo <= e; lo += run_max) pieces.push_back({l, lo, std::min(run_max, e - lo + 1)});
+          lo_l[key] = std::min(lo_l[key], l);
+          hi_l[key] = std::max(hi_l[key], l);
+          jx = e + 1;
+        }
+      }
+      std::stable_sort(pieces.begin(), pieces.end(),
+                       [](const Piece& x, const Piece& y) { return x.len > y.len; });
+      for (size_t i = 0; i < pieces.size(); i += 4) {
+        const int m = pieces[i].len;
+        rlen.push_back(m);
+        rcb.push_back(l_chunks);
+        int dstart[4], lane_l[4], first[4], len[4];
+        for (int gi = 0; gi < 4; ++gi) {
+          if (i + gi < pieces.size()) {
+            const Piece& pc = pieces[i + gi];
+            lane_l[gi] = pc.l;
+            len[gi] = pc.len;
+            if (pc.lo + m - 1 <= F - 1) {        // piece at the end of the run
+              dstart[gi] = pc.lo + m - 1;
+              first[gi] = m - pc.len;
+            } else {                             // piece at the start
+              dstart[gi] = pc.lo + pc.len - 1;
+              first[gi] = 0;
+              if (dstart[gi] - (m - 1) < 0) return fail(PSOAM_EINVAL, "plan: run placement");
+            }
+          } else {                               // idle lane: zero band, valid columns
+            lane_l[gi] = pieces[i].l;
+            len[gi] = 0;
+            dstart[gi] = m - 1;
+            first[gi] = 0;
           }
-      const size_t nch = (cnt + 3) / 4;
-      for (size_t i = cnt; i < nch * 4; ++i) lgroups.push_back({-1, -1, -1});
-      lstart[key + 1] = lstart[key] + (int)nch;
+          rgrp.push_back(((uint32_t)lane_l[gi] << 16) | (uint32_t)dstart[gi]);
+        }
+        for (int c = 0; c < m; ++c) {
+          for (int gi = 0; gi < 4; ++gi) {
+            const bool on = c >= first[gi] && c < first[gi] + len[gi];
+            lgroups.push_back(on ? Group{jy, dstart[gi] - c, lane_l[gi]} : Group{-1, -1, -1});
+          }
+          ++l_chunks;
+        }
+      }
+      rstart[key + 1] = (int)rlen.size();
     }
-  const int l_chunks = lstart[(size_t)n_mt * F];
   T.l_chunks = l_chunks;
+  T.n_runs = (int)rlen.size();
+  T.max_runs = 0;
+  for (int tile = 0; tile < n_mt; ++tile)
+    T.max_runs = std::max(T.max_runs, rstart[(size_t)(tile + 1) * F] - rstart[(size_t)tile * F]);
   // staged row windows for a workgroup of `rows` output rows (waves): the
   // union of the octet ranges of the dy values j - r, r < rows
   auto windows = [&](int rows, std::vector<uint32_t>& win, int& max_oct) {
@@ -262,7 +321,7 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   const int XW = kLdsPos + F - 1;
   auto lds_of = [&](int rows, int max_oct) {
     return (size_t)max_oct * XW * 16 * 8 * sizeof(uint16_t) * (split ? 2 : 1) +
-           sizeof(uint32_t) * (2 * F + rows + 1) + 16;
+           lds_meta_bytes(F, rows, T.max_runs) + 16;
   };
   std::vector<uint32_t> win4, win8;
   int mo4 = 0, mo8 = 0;
@@ -290,44 +349,56 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   T.lds_ok = n_l < 0xffff && F < 0xffff && (rows == 8 ? lds8 : lds4) <= (size_t)kLdsMaxBytes &&
              !(force_global && force_global[0] == '1');
   if (!T.lds_ok) return PSOAM_OK;
-  std::vector<uint32_t> lgrp((size_t)l_chunks * 4, 0);
   std::vector<float> lvals((size_t)l_chunks * 64 * gw, 0.0f);
-  for (int tile = 0; tile < n_mt; ++tile)
-    for (int jy = 0; jy < F; ++jy) {
-      const size_t key = (size_t)tile * F + jy;
-      for (int c = lstart[key]; c < lstart[key + 1]; ++c)
-        for (int gi = 0; gi < 4; ++gi) {
-          const Group& G = lgroups[(size_t)c * 4 + gi];
-          if (G.jy < 0) {
-            lgrp[(size_t)c * 4 + gi] = 0xffffu << 16;
-            continue;
-          }
-          lgrp[(size_t)c * 4 + gi] = ((uint32_t)G.l << 16) | (uint32_t)G.jx;
-          fill(lvals, c, gi, G, tile);
-        }
+  {
+    // chunk -> tile for the band fill
+    std::vector<int> chunk_tile(l_chunks, 0);
+    for (int tile = 0; tile < n_mt; ++tile)
+      for (int jy = 0; jy < F; ++jy) {
+        const size_t key = (size_t)tile * F + jy;
+        for (int r = rstart[key]; r < rstart[key + 1]; ++r)
+          for (int c = rcb[r]; c < rcb[r] + rlen[r]; ++c) chunk_tile[c] = tile;
+      }
+    for (int c = 0; c < l_chunks; ++c)
+      for (int gi = 0; gi < 4; ++gi) {
+        const Group& G = lgroups[(size_t)c * 4 + gi];
+        if (G.jy >= 0) fill(lvals, c, gi, G, chunk_tile[c]);
+      }
+  }
+  const size_t nr = std::max<size_t>(rlen.size(), 1);
+  PSOAM_HIP(hipMalloc(&T.d_lstart, sizeof(int) * rstart.size()));
+  PSOAM_HIP(hipMemcpy(T.d_lstart, rstart.data(), sizeof(int) * rstart.size(), hipMemcpyHostToDevice));
+  PSOAM_HIP(hipMalloc(&T.d_lgrp, sizeof(uint32_t) * 4 * nr));
+  if (!rgrp.empty())
+    PSOAM_HIP(hipMemcpy(T.d_lgrp, rgrp.data(), sizeof(uint32_t) * rgrp.size(), hipMemcpyHostToDevice));
+  {
+    std::vector<int> rinfo(2 * nr, 0);  // (length, first chunk) per run
+    for (size_t r = 0; r < rlen.size(); ++r) {
+      rinfo[2 * r] = rlen[r];
+      rinfo[2 * r + 1] = rcb[r];
     }
-  PSOAM_HIP(hipMalloc(&T.d_lstart, sizeof(int) * lstart.size()));
-  PSOAM_HIP(hipMemcpy(T.d_lstart, lstart.data(), sizeof(int) * lstart.size(), hipMemcpyHostToDevice));
-  PSOAM_HIP(hipMalloc(&T.d_lgrp, sizeof(uint32_t) * std::max<size_t>(lgrp.size(), 4)));
-  if (!lgrp.empty())
-    PSOAM_HIP(hipMemcpy(T.d_lgrp, lgrp.data(), sizeof(uint32_t) * lgrp.size(), hipMemcpyHostToDevice));
+    PSOAM_HIP(hipMalloc(&T.d_rinfo, sizeof(int) * rinfo.size()));
+    PSOAM_HIP(hipMemcpy(T.d_rinfo, rinfo.data(), sizeof(int) * rinfo.size(), hipMemcpyHostToDevice));
+  }
   {
     std::vector<int> order(n_mt);
     for (int i = 0; i < n_mt; ++i) order[i] = i;
-    auto work = [&](int t) { return lstart[(size_t)(t + 1) * F] - lstart[(size_t)t * F]; };
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+    std::vector<long> work(n_mt, 0);
+    for (int t = 0; t < n_mt; ++t)
+      for (int r = rstart[(size_t)t * F]; r < rstart[(size_t)(t + 1) * F]; ++r) work[t] += rlen[r];
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
     PSOAM_HIP(hipMalloc(&T.d_order, sizeof(int) * n_mt));
     PSOAM_HIP(hipMemcpy(T.d_order, order.data(), sizeof(int) * n_mt, hipMemcpyHostToDevice));
   }
   PSOAM_HIP(hipMalloc(&T.d_win, sizeof(uint32_t) * win.size()));
   PSOAM_HIP(hipMemcpy(T.d_win, win.data(), sizeof(uint32_t) * win.size(), hipMemcpyHostToDevice));
-  if (int rc = upload_vals(lvals, l_chunks, &T.d_la, &T.d_la_lo)) return rc;
+  if (int rc = upload_vals(lvals, l_chunks, &T.d_la, &T.d_la_lo, kRunMax)) return rc;
   return PSOAM_OK;
 }
 
 static void free_table(BandTable& T) {
   void* ptrs[] = {T.d_start, T.d_off, T.d_a, T.d_a_lo, T.d_lstart, T.d_lgrp, T.d_win, T.d_la,
-                  T.d_la_lo, T.d_order};
+                  T.d_la_lo, T.d_order, T.d_rinfo};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   T.d_start = nullptr;
@@ -338,6 +409,7 @@ static void free_table(BandTable& T) {
   T.d_win = nullptr;
   T.d_la = T.d_la_lo = nullptr;
   T.d_order = nullptr;
+  T.d_rinfo = nullptr;
 }
 
 void free_plan(psoam_plan* P) {
