@@ -335,33 +335,72 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
       }
     }
   } else {
-    // c[s][iy][ix][z] (+)= sum_k S[k][s] bh[k][z]: reduce over the 16 pulse lanes
+    // c[s][iy][ix][z] (+)= sum_k S[k][s] bh[k][z].  The sum over the 16 pulse
+    // lanes is a reduce-scatter: each butterfly stage halves the positions a
+    // lane keeps, so lane n ends with position n >> (4 - log2 NP) (the low
+    // lanes of a pair add once more when NP < 16) and writes its own column.
+    static_assert(NP == 8 || NP == 16, "positions per wave");
+    constexpr int kSh = NP == 16 ? 0 : 1;
     const int nz = A.nz;
+    const int pme = n >> kSh;
+    const int ixm = ix0 + pme;
+    const bool writer = (n & ((1 << kSh) - 1)) == 0 && ixm < A.nx;
+    const bool kok = k < A.nk;
+    for (int s = 0; s < A.sw.ns; ++s) {
+      float x[NP][4];
+      if (A.stab) {
+        // depth-only switching table: one coefficient per (z, pulse)
+        float cz[4];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int ix = ix0 + p;
-      const int ixc = ix < A.nx ? ix : A.nx - 1;
-      const size_t col = ((size_t)iy * A.nx + ixc) * nz;
-      for (int s = 0; s < A.sw.ns; ++s) {
-        float v4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (k < A.nk) {
+        for (int j = 0; j < 4; ++j) {
+          const int z = row0 + j;
+          cz[j] = (kok && z < nz) ? A.stab[((size_t)z * A.kp + k) * A.sw.ns + s] * A.inv_scale : 0.0f;
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) x[p][j] = cz[j] * acc[p][j];
+      } else {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const int ix = ix0 + p;
+          const int ixc = ix < A.nx ? ix : A.nx - 1;
+          const size_t col = ((size_t)iy * A.nx + ixc) * nz;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int z = row0 + j;
-            if (z < nz)
-              v4[j] = coef_at(A.sw, A.phi, A.stab, A.kp, col, z, k, s) * (acc[p][j] * A.inv_scale);
+            x[p][j] = (kok && z < nz) ? scoef(A.sw, A.phi[col + z], k, s) * (acc[p][j] * A.inv_scale) : 0.0f;
           }
         }
+      }
+      // reduce-scatter over lane bits 3, 2, ...: the upper half of the lanes
+      // keeps the upper half of the positions
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+      for (int h = NP / 2, mask = 8; h >= 1; h >>= 1, mask >>= 1) {
+        const bool up = (n & mask) != 0;
 #pragma unroll
-          for (int m = 8; m >= 1; m >>= 1) v4[j] += __shfl_xor(v4[j], m, 64);
-        }
-        if (n == 0 && ix < A.nx) {
-          float* co = A.out + ((size_t)s * A.ny * A.nx) * nz + col + row0;
+        for (int q = 0; q < h; ++q)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float send = up ? x[q][j] : x[q + h][j];
+            const float keep = up ? x[q + h][j] : x[q][j];
+            x[q][j] = keep + __shfl_xor(send, mask, 64);
+          }
+      }
+      if constexpr (kSh == 1) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[0][j] += __shfl_xor(x[0][j], 1, 64);
+      }
+      if (writer) {
+        float* co = A.out + ((size_t)s * A.ny * A.nx + (size_t)iy * A.nx + ixm) * nz + row0;
+        if ((nz & 3) == 0 && row0 + 3 < nz) {
+          f32x4 v = {x[0][0], x[0][1], x[0][2], x[0][3]};
+          if (!first) v += *(const f32x4*)co;
+          *(f32x4*)co = v;
+        } else {
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            if (row0 + j < nz) co[j] = first ? v4[j] : co[j] + v4[j];
+            if (row0 + j < nz) co[j] = first ? x[0][j] : co[j] + x[0][j];
         }
       }
     }
@@ -475,7 +514,7 @@ __global__ __launch_bounds__(256) void band32(BandArgs A) {
 // (tile, dy); each group names (octet, dx), so the operand of position p is
 // the staged column p + dx.
 // --------------------------------------------------------------------------
-constexpr int kStageBatch = 8;
+constexpr int kStageBatch = 16;
 
 struct LdsArgs {
   const int* lstart;       // [n_mtiles * F + 1]
@@ -590,9 +629,16 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
       if (ocnt == 0 || iy0 + j >= L.yp) continue;  // uniform over the block
       __syncthreads();  // the previous row's contractions are done with LDS
       const int items = ocnt * XW * 16;
-      const E* rowp = q + (size_t)(iy0 + j) * A.xp * A.ps;
-      const E* rowp_lo = SPLIT ? qlo + (size_t)(iy0 + j) * A.xp * A.ps : nullptr;
+      // Buffer loads from this staged row: all issued unconditionally (an
+      // item past the window still lies inside the padded row, and its value
+      // is never written to LDS), so one wait covers the batch.
       const int ps = (int)A.ps;
+      const int row_bytes = A.xp * ps * (int)sizeof(E);
+      const int dwrap = -XW * ps + A.kp * 8;
+      const __amdgpu_buffer_rsrc_t rq_hi = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(q + (size_t)(iy0 + j) * A.xp * A.ps), (short)0, row_bytes, kBufWord3);
+      const __amdgpu_buffer_rsrc_t rq_lo = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)((SPLIT ? qlo : q) + (size_t)(iy0 + j) * A.xp * A.ps), (short)0, row_bytes, kBufWord3);
       for (int u0 = 0; u0 * NT < items; u0 += NPRE) {
         V tmp[NPRE];
         V tmp_lo[SPLIT ? NPRE : 1];
@@ -601,15 +647,20 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
         int off = (ix0 + xi) * ps + ((obase + oi) * A.kp + pb * 16 + tnn) * 8;
 #pragma unroll
         for (int u = 0; u < NPRE; ++u) {
-          if ((u0 + u) * NT + (int)threadIdx.x < items) {
-            tmp[u] = *(const V*)(rowp + off);
-            if constexpr (SPLIT) tmp_lo[u] = *(const V*)(rowp_lo + off);
-          }
+          const int ob = off * (int)sizeof(E);
+          tmp[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rq_hi, ob, 0, 0));
+          if constexpr (SPLIT) tmp_lo[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rq_lo, ob, 0, 0));
+          // advance by NT/16 columns; XW >= 16 and NT/16 <= 32, so at most
+          // two wraps into the next octet (selects, no branches)
           xi += NT / 16;
           off += (NT / 16) * ps;
-          while (xi >= XW) {
-            xi -= XW;
-            off += -XW * ps + A.kp * 8;
+          const bool w1 = xi >= XW;
+          xi = w1 ? xi - XW : xi;
+          off = w1 ? off + dwrap : off;
+          if constexpr (NT / 16 > 16) {
+            const bool w2 = xi >= XW;
+            xi = w2 ? xi - XW : xi;
+            off = w2 ? off + dwrap : off;
           }
         }
 #pragma unroll
