@@ -31,7 +31,7 @@ constexpr int kWavesPerBlock = 4;    // consecutive output tiles of one position
 constexpr float kFp16Scale = 256.0f; // FP16 operands carry this power-of-two scale
 constexpr int kLdsPos = 16;          // staged kernel: positions per wave
 constexpr int kLdsMaxBytes = 160 * 1024;
-constexpr int kRunMax = 8;           // longest sliding run (chunks) of the staged kernel
+constexpr int kRunMax = 4;           // longest sliding run (chunks) of the staged kernel
 
 // Photo-switching coefficients in the form the kernels evaluate:
 //   S_v[k][s] = phi_v * (a[s] + b[s] * exp(-k * phi_v^gamma * inv_tau[s]))

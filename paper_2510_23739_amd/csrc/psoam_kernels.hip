@@ -663,6 +663,9 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
             off = w2 ? off + dwrap : off;
           }
         }
+        // all of the batch has landed (the writes below are conditional, and
+        // a load left pending on a skipped path would stall the run loop)
+        __builtin_amdgcn_s_waitcnt(kVmcnt0);
 #pragma unroll
         for (int u = 0; u < NPRE; ++u) {
           const int it = (u0 + u) * NT + (int)threadIdx.x;
@@ -737,7 +740,7 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
 // or three workgroups per CU); the S^T epilogue of H^T needs more registers
 // and its wider staged window allows one workgroup per CU anyway.
 template <int PREC, bool SPLIT, int MODE, int ROWS>
-__global__ __launch_bounds__(64 * ROWS) __attribute__((amdgpu_waves_per_eu(2))) void band16_lds(
+__global__ __launch_bounds__(64 * ROWS) __attribute__((amdgpu_waves_per_eu(MODE == 0 && !SPLIT ? 3 : 2))) void band16_lds(
     BandArgs A, LdsArgs L) {
   band16_lds_body<PREC, SPLIT, MODE, ROWS>(A, L);
 }
