@@ -537,7 +537,6 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   using V = typename H::V;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   E* sh = (E*)smem_raw;
-  E* sh_lo = sh + L.lds_elems;
   // per-tile row windows, run bounds and run records, read once into LDS
   uint32_t* s_win = (uint32_t*)(smem_raw + L.meta_off);
   int* s_lstart = (int*)(s_win + (L.f + ROWS - 1));
@@ -620,9 +619,12 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
     // it = (oi*XW + xi)*16 + nn is one 16-byte octet of pulse nn at column xi
     // of octet oi; nn = t%16 is fixed and (xi, oi) advance by NT/16 columns
     // per step.  kStageBatch loads are in flight before their LDS writes.
-    constexpr int NPRE = SPLIT ? kStageBatch / 2 : kStageBatch;
+    // The split forms stage the high and the low operand rows in two passes
+    // over the window (the same LDS tile): pass 0 adds hi(H) hi(q) +
+    // lo(H) hi(q), pass 1 adds hi(H) lo(q).
     const int t16 = (int)threadIdx.x >> 4;
     const int tnn = (int)threadIdx.x & 15;
+    for (int pass = 0; pass < (SPLIT ? 2 : 1); ++pass)
     for (int j = 0; j < nwin; ++j) {
       const uint32_t wj = s_win[j];
       const int ocnt = (int)(wj & 0xffffu), obase = (int)(wj >> 16);
@@ -635,21 +637,18 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
       const int ps = (int)A.ps;
       const int row_bytes = A.xp * ps * (int)sizeof(E);
       const int dwrap = -XW * ps + A.kp * 8;
-      const __amdgpu_buffer_rsrc_t rq_hi = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)(q + (size_t)(iy0 + j) * A.xp * A.ps), (short)0, row_bytes, kBufWord3);
-      const __amdgpu_buffer_rsrc_t rq_lo = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)((SPLIT ? qlo : q) + (size_t)(iy0 + j) * A.xp * A.ps), (short)0, row_bytes, kBufWord3);
+      const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)((pass ? qlo : q) + (size_t)(iy0 + j) * A.xp * A.ps), (short)0, row_bytes, kBufWord3);
+      constexpr int NPRE = kStageBatch;
       for (int u0 = 0; u0 * NT < items; u0 += NPRE) {
         V tmp[NPRE];
-        V tmp_lo[SPLIT ? NPRE : 1];
         int r2 = u0 * (NT / 16) + t16;
         int xi = r2 % XW, oi = r2 / XW;
         int off = (ix0 + xi) * ps + ((obase + oi) * A.kp + pb * 16 + tnn) * 8;
 #pragma unroll
         for (int u = 0; u < NPRE; ++u) {
           const int ob = off * (int)sizeof(E);
-          tmp[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rq_hi, ob, 0, 0));
-          if constexpr (SPLIT) tmp_lo[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rq_lo, ob, 0, 0));
+          tmp[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rq, ob, 0, 0));
           // advance by NT/16 columns; XW >= 16 and NT/16 <= 32, so at most
           // two wraps into the next octet (selects, no branches)
           xi += NT / 16;
@@ -669,10 +668,7 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
 #pragma unroll
         for (int u = 0; u < NPRE; ++u) {
           const int it = (u0 + u) * NT + (int)threadIdx.x;
-          if (it < items) {
-            *(V*)(sh + it * 8) = tmp[u];
-            if constexpr (SPLIT) *(V*)(sh_lo + it * 8) = tmp_lo[u];
-          }
+          if (it < items) *(V*)(sh + it * 8) = tmp[u];
         }
       }
       __syncthreads();
@@ -695,27 +691,22 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
           const int nx = rr + 1 == nrun ? 0 : rr + 1;
           const int cb2 = __builtin_amdgcn_readfirstlane(s_rinfo[2 * nx + 1]);
           V R[kLdsPos];
-          V Rl[SPLIT ? kLdsPos : 1];
 #pragma unroll
-          for (int p = 0; p < kLdsPos; ++p) {
-            R[p] = *(const V*)(sh + base + p * 128);
-            if constexpr (SPLIT) Rl[p] = *(const V*)(sh_lo + base + p * 128);
-          }
+          for (int p = 0; p < kLdsPos; ++p) R[p] = *(const V*)(sh + base + p * 128);
 #pragma unroll
           for (int i = 0; i < kRunMax; ++i) {
             if (i < m) {
-              if (i > 0) {
-                R[(kLdsPos - i) & (kLdsPos - 1)] = *(const V*)(sh + base - i * 128);
-                if constexpr (SPLIT) Rl[(kLdsPos - i) & (kLdsPos - 1)] = *(const V*)(sh_lo + base - i * 128);
-              }
+              if (i > 0) R[(kLdsPos - i) & (kLdsPos - 1)] = *(const V*)(sh + base - i * 128);
+              if (SPLIT && pass == 0) {
 #pragma unroll
-              for (int p = 0; p < kLdsPos; ++p) {
-                const int w = (p - i) & (kLdsPos - 1);
-                acc[p] = H::mma(ab[i], R[w], acc[p]);
-                if constexpr (SPLIT) {
-                  acc[p] = H::mma(ab[i], Rl[w], acc[p]);
+                for (int p = 0; p < kLdsPos; ++p) {
+                  const int w = (p - i) & (kLdsPos - 1);
+                  acc[p] = H::mma(ab[i], R[w], acc[p]);
                   acc[p] = H::mma(al[i], R[w], acc[p]);
                 }
+              } else {
+#pragma unroll
+                for (int p = 0; p < kLdsPos; ++p) acc[p] = H::mma(ab[i], R[(p - i) & (kLdsPos - 1)], acc[p]);
               }
             }
             // slot i is free: load the next run's block i into it
@@ -853,8 +844,7 @@ static hipError_t launch_band_lds(const psoam_plan* P, const BandTable& T, BandA
   L.yp = P->Yp;
   L.nyb = (P->g.ny + T.rows - 1) / T.rows;
   L.nxb = (P->g.nx + kLdsPos - 1) / kLdsPos;
-  const bool split = P->prec == PSOAM_BF16_SPLIT || P->prec == PSOAM_FP16_SPLIT;
-  L.lds_elems = (int)(T.lds_bytes / sizeof(uint16_t) / (split ? 2 : 1));
+  L.lds_elems = (int)(T.lds_bytes / sizeof(uint16_t));
   L.meta_off = (int)((T.lds_bytes + 15) / 16 * 16);
   const size_t lds = L.meta_off + lds_meta_bytes(P->F, T.rows, T.max_runs);
 #define PSOAM_LDS_R(PR, SP, R)                                                              \

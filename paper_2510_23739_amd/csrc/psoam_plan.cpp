@@ -320,7 +320,7 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   };
   const int XW = kLdsPos + F - 1;
   auto lds_of = [&](int rows, int max_oct) {
-    return (size_t)max_oct * XW * 16 * 8 * sizeof(uint16_t) * (split ? 2 : 1) +
+    return (size_t)max_oct * XW * 16 * 8 * sizeof(uint16_t) +
            lds_meta_bytes(F, rows, T.max_runs) + 16;
   };
   std::vector<uint32_t> win4, win8;
@@ -343,7 +343,7 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   std::vector<uint32_t>& win = rows == 8 ? win8 : win4;
   T.rows = rows;
   T.max_oct = rows == 8 ? mo8 : mo4;
-  T.lds_bytes = (size_t)T.max_oct * XW * 16 * 8 * sizeof(uint16_t) * (split ? 2 : 1);
+  T.lds_bytes = (size_t)T.max_oct * XW * 16 * 8 * sizeof(uint16_t);
   // PSOAM_BAND_GLOBAL=1 keeps the plan on the global-operand kernel (tests cover both)
   const char* force_global = std::getenv("PSOAM_BAND_GLOBAL");
   T.lds_ok = n_l < 0xffff && F < 0xffff && (rows == 8 ? lds8 : lds4) <= (size_t)kLdsMaxBytes &&
