@@ -191,8 +191,10 @@ int psoam_solve_batch(int32_t n, const psoam_plan* const* plans, const float* co
 /* Work figures of a plan's band contraction, per position and per pulse:
  * useful_macs = nonzero band entries h[z][jdy][jdx][t] with t in [0, Nt)
  * (the algorithmic multiply-adds of one A-scan of one pulse);
- * chunks = packed matrix-core tiles; executed_macs = chunks times the
- * tile size (16 x 32 for 16-bit, 16 x 4 for FP32).  dir 0: H, dir 1: H^T. */
+ * chunks = packed matrix-core tiles of the kernel the plan launches (the
+ * run-packed tiles when the LDS-staged kernel is used); executed_macs =
+ * chunks times the tile size (16 x 32 for 16-bit, 16 x 4 for FP32).
+ * dir 0: H, dir 1: H^T. */
 typedef struct {
   int64_t useful_macs[2];
   int64_t chunks[2];

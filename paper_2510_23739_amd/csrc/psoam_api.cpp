@@ -383,9 +383,9 @@ int psoam_plan_stats(const psoam_plan* plan, psoam_plan_info* info) {
   const BandTable* T[2] = {&plan->fwd, &plan->adj};
   for (int d = 0; d < 2; ++d) {
     info->useful_macs[d] = (int64_t)T[d]->useful_macs;
-    info->chunks[d] = T[d]->n_chunks;
-    info->executed_macs[d] = (int64_t)T[d]->n_chunks * tile;
     const bool staged = half && T[d]->lds_ok;
+    info->chunks[d] = staged ? T[d]->l_chunks : T[d]->n_chunks;
+    info->executed_macs[d] = (int64_t)info->chunks[d] * tile;
     info->lds_bytes[d] = staged ? (int64_t)T[d]->lds_bytes : 0;
     info->lds_rows[d] = staged ? T[d]->rows : 0;
   }

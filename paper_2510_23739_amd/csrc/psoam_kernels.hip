@@ -731,7 +731,7 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
 // or three workgroups per CU); the S^T epilogue of H^T needs more registers
 // and its wider staged window allows one workgroup per CU anyway.
 template <int PREC, bool SPLIT, int MODE, int ROWS>
-__global__ __launch_bounds__(64 * ROWS) __attribute__((amdgpu_waves_per_eu(MODE == 0 && !SPLIT ? 3 : 2))) void band16_lds(
+__global__ __launch_bounds__(64 * ROWS) __attribute__((amdgpu_waves_per_eu(!SPLIT ? 3 : 2))) void band16_lds(
     BandArgs A, LdsArgs L) {
   band16_lds_body<PREC, SPLIT, MODE, ROWS>(A, L);
 }
