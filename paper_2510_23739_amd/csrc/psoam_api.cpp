@@ -89,6 +89,7 @@ int tv_prox_core(const psoam_plan* P, float* x, const float* z, float theta, int
                  int mode, float th1, float* const u[3], float* w, const float* u_start,
                  bool literal, const float** u_last, hipStream_t s) {
   const float inv_mu = (float)inv_mu_tv(P->g);
+  (void)w;  // the fused dual step keeps w on chip; the workspace slot stays in the layout
   if (u_last) *u_last = nullptr;
   if (n_inner <= 0 || theta == 0.0f) {
     PSOAM_HIP(launch_tv_final(P, x, z, nullptr, mode, th1, s));
@@ -100,11 +101,6 @@ int tv_prox_core(const psoam_plan* P, float* x, const float* z, float theta, int
   int slot = 0;
   for (int j = 0; j < n_inner; ++j) {
     // eta_j = u_j + beta_{j-1} (u_j - u_{j-1})
-    const float* wz = z;
-    if (cur) {
-      PSOAM_HIP(launch_tv_w(P, w, z, cur, prev, (float)beta_prev, s));
-      wz = w;
-    }
     float* nxt = u[slot];
     if (nxt == cur || nxt == prev) {
       slot = (slot + 1) % 3;
@@ -114,7 +110,7 @@ int tv_prox_core(const psoam_plan* P, float* x, const float* z, float theta, int
         nxt = u[slot];
       }
     }
-    PSOAM_HIP(launch_tv_u(P, nxt, cur, prev, (float)beta_prev, wz, inv_mu, theta, s));
+    PSOAM_HIP(launch_tv_step(P, nxt, z, cur, prev, (float)beta_prev, inv_mu, theta, s));
     slot = (slot + 1) % 3;
     double beta;
     momentum_step(t, beta, literal);

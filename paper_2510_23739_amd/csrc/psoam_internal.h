@@ -146,11 +146,9 @@ hipError_t launch_prox_l1(float* x, const float* z, int64_t n, float thresh, int
 // one inner step of the TV dual iteration:
 //   w = z - grad^T eta ; u_next = clip(eta + inv_mu * grad w, -theta, theta),
 //   eta = u_cur + beta (u_cur - u_prev)  (u_cur == null: eta = 0; u_prev == null: eta = u_cur)
-hipError_t launch_tv_w(const psoam_plan* P, float* w, const float* z, const float* u_cur,
-                       const float* u_prev, float beta, hipStream_t s);
-hipError_t launch_tv_u(const psoam_plan* P, float* u_next, const float* u_cur,
-                       const float* u_prev, float beta, const float* w, float inv_mu,
-                       float theta, hipStream_t s);
+hipError_t launch_tv_step(const psoam_plan* P, float* u_next, const float* z, const float* u_cur,
+                          const float* u_prev, float beta, float inv_mu, float theta,
+                          hipStream_t s);
 // x = z - grad^T u (u may be null: x = z); then mode 0: as is, 1: max(x,0), 2: max(x - t1, 0)
 hipError_t launch_tv_final(const psoam_plan* P, float* x, const float* z, const float* u,
                            int mode, float thresh1, hipStream_t s);

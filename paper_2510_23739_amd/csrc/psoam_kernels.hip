@@ -149,35 +149,73 @@ __global__ __launch_bounds__(256) void switch_fwd32(const float* __restrict__ c,
   bq[((size_t)(y + r) * xp + (x + r)) * ps + (size_t)z * kp + k] = b;
 }
 
-// y[k][y][x][t] -> 16-bit octet operand of H^T at the padded position.
+// y[k][y][x][t] -> 16-bit octet operand of H^T at the padded position,
+// rq[pos][t/8][k][8].  One block per position, in chunks of 16 pulses x 16
+// octets transposed through LDS: a thread reads 8 consecutive samples of one
+// pulse (16 threads cover 512 contiguous bytes of a pulse row) and, after the
+// barrier, writes the 16-byte octet of (octet t/16, pulse t%16), so 16
+// consecutive threads write 256 contiguous bytes.
 template <int PREC, bool SPLIT>
 __global__ __launch_bounds__(256) void pack_r16(const float* __restrict__ yin,
                                                 typename Half<PREC>::E* __restrict__ rq,
                                                 typename Half<PREC>::E* __restrict__ rq_lo,
                                                 int nk, int ny, int nx, int nt, int to_n,
-                                                int kp, int xp, int r, size_t ps) {
+                                                int kp, int xp, int r, size_t ps, int vec4) {
   using H = Half<PREC>;
-  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t total = (size_t)ny * nx * to_n * kp;
-  if (tid >= total) return;
-  const int k = (int)(tid % kp);
-  size_t rest = tid / kp;
-  const int to = (int)(rest % to_n);
-  rest /= to_n;
-  const int x = (int)(rest % nx);
-  const int y = (int)(rest / nx);
-  typename H::V hi, lo;
-  const float* src = yin + (((size_t)k * ny + y) * nx + x) * nt;
+  using V = typename H::V;
+  __shared__ V t_hi[256];
+  __shared__ V t_lo[SPLIT ? 256 : 1];
+  const int pos = blockIdx.x;
+  const int y = pos / nx, x = pos % nx;
+  const size_t o_pos = ((size_t)(y + r) * xp + (x + r)) * ps;
+  const int tid = threadIdx.x;
+  const int a = tid >> 4, c = tid & 15;
+  for (int kc = 0; kc < kp; kc += 16) {
+    for (int oc = 0; oc < to_n; oc += 16) {
+      // read: pulse kc + a, octet oc + c
+      {
+        const int k = kc + a, to = oc + c;
+        V hi, lo;
+        if (k < nk && to < to_n) {
+          const float* src = yin + (((size_t)k * ny + y) * nx + x) * nt + (size_t)to * 8;
+          float v[8];
+          if (vec4 && to * 8 + 7 < nt) {
+            const f32x4 v0 = *(const f32x4*)src, v1 = *(const f32x4*)(src + 4);
+            v[0] = v0[0]; v[1] = v0[1]; v[2] = v0[2]; v[3] = v0[3];
+            v[4] = v1[0]; v[5] = v1[1]; v[6] = v1[2]; v[7] = v1[3];
+          } else {
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int t = to * 8 + j;
-    const float v = (k < nk && t < nt) ? src[t] * H::scale : 0.0f;
-    hi[j] = (typename H::E)v;
-    lo[j] = (typename H::E)(v - (float)hi[j]);
+            for (int j = 0; j < 8; ++j) v[j] = to * 8 + j < nt ? src[j] : 0.0f;
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float w = v[j] * H::scale;
+            hi[j] = (typename H::E)w;
+            lo[j] = (typename H::E)(w - (float)hi[j]);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            hi[j] = (typename H::E)0.0f;
+            lo[j] = (typename H::E)0.0f;
+          }
+        }
+        t_hi[c * 16 + a] = hi;
+        if constexpr (SPLIT) t_lo[c * 16 + a] = lo;
+      }
+      __syncthreads();
+      // write: octet oc + a, pulse kc + c
+      {
+        const int to = oc + a, k = kc + c;
+        if (to < to_n) {
+          const size_t o = o_pos + ((size_t)to * kp + k) * 8;
+          *(V*)(rq + o) = t_hi[a * 16 + c];
+          if constexpr (SPLIT) *(V*)(rq_lo + o) = t_lo[a * 16 + c];
+        }
+      }
+      __syncthreads();
+    }
   }
-  const size_t o = ((size_t)(y + r) * xp + (x + r)) * ps + ((size_t)to * kp + k) * 8;
-  *(typename H::V*)(rq + o) = hi;
-  if constexpr (SPLIT) *(typename H::V*)(rq_lo + o) = lo;
 }
 
 // y[k][pos][t] -> rq[pos][t][k] (FP32), transposed through LDS, one block per position.
@@ -780,6 +818,8 @@ hipError_t launch_switch_fwd(const psoam_plan* P, const float* c, hipStream_t s)
 
 hipError_t launch_pack_r(const psoam_plan* P, const float* y, hipStream_t s) {
   const auto& g = P->g;
+  // 16-byte loads of the A-scans when every octet starts 16-byte aligned
+  const int vec4 = ((uintptr_t)y & 15) == 0 && (g.nt & 3) == 0;
   switch (P->prec) {
     case PSOAM_FP32:
       hipLaunchKernelGGL(pack_r32, dim3(g.ny * g.nx), dim3(256), 0, s, y, (float*)P->d_rq,
@@ -788,10 +828,10 @@ hipError_t launch_pack_r(const psoam_plan* P, const float* y, hipStream_t s) {
 #define PSOAM_PK16(PR, SP)                                                                  \
   {                                                                                         \
     using E = Half<PR>::E;                                                                  \
-    const size_t n = (size_t)g.ny * g.nx * (P->Lt / 8) * P->Kp;                            \
-    hipLaunchKernelGGL((pack_r16<PR, SP>), dim3(blocks_for(n)), dim3(256), 0, s, y,         \
+    const size_t n = (size_t)g.ny * g.nx;                                                   \
+    hipLaunchKernelGGL((pack_r16<PR, SP>), dim3((unsigned)n), dim3(256), 0, s, y,           \
                        (E*)P->d_rq, (E*)P->d_rq_lo, g.n_pulses, g.ny, g.nx, g.nt, P->Lt / 8, \
-                       P->Kp, P->Xp, P->R, P->ps_r);                                        \
+                       P->Kp, P->Xp, P->R, P->ps_r, vec4);                                  \
     break;                                                                                  \
   }
     case PSOAM_BF16: PSOAM_PK16(PSOAM_BF16, false)
@@ -1033,41 +1073,129 @@ __device__ __forceinline__ float gradT_at(const float* __restrict__ uc, const fl
   return acc;
 }
 
-__global__ __launch_bounds__(256) void tv_w_kernel(float* __restrict__ w,
-                                                   const float* __restrict__ z,
-                                                   const float* __restrict__ uc,
-                                                   const float* __restrict__ up, float beta,
-                                                   Grid3 G) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= G.sv) return;
-  const int iz = (int)(v % G.nz);
-  const int ix = (int)((v / G.nz) % G.nx);
-  const int iy = (int)((v / ((int64_t)G.nz * G.nx)) % G.ny);
-  w[v] = z[v] - gradT_at(uc, up, beta, G, v, iy, ix, iz);
-}
+// One dual step of the TV prox, fused:
+//   eta = u_j + beta (u_j - u_{j-1}),  w = z - grad^T eta,
+//   u_{j+1} = clamp(eta + inv_mu grad w, -theta, theta)   (per component).
+// A block owns a TY x TX x TZ tile of one species volume.  eta is staged in
+// LDS per component over the tile, its forward halo and the one backward
+// plane that component's difference needs; w is formed on the tile plus the
+// forward halo; the new duals are written for the tile.  Global traffic is
+// about u_j, u_{j-1} (3 components each), z in and u_{j+1} out per voxel.
+constexpr int kTvY = 4, kTvX = 8, kTvZ = 32;
+template <int Y, int X, int Z>
+struct Dims3 {
+  static constexpr int y = Y, x = X, z = Z;
+};
 
-__global__ __launch_bounds__(256) void tv_u_kernel(float* __restrict__ un,
-                                                   const float* __restrict__ uc,
-                                                   const float* __restrict__ up, float beta,
-                                                   const float* __restrict__ w, float inv_mu,
-                                                   float theta, Grid3 G) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= G.sv) return;
-  const int iz = (int)(v % G.nz);
-  const int ix = (int)((v / G.nz) % G.nx);
-  const int iy = (int)((v / ((int64_t)G.nz * G.nx)) % G.ny);
-  const float wv = w[v];
-  const int64_t sx = G.nz, sy = (int64_t)G.nx * G.nz;
-  const float gy = (iy < G.ny - 1) ? w[v + sy] - wv : 0.0f;
-  const float gx = (ix < G.nx - 1) ? w[v + sx] - wv : 0.0f;
-  const float gz = (iz < G.nz - 1) ? w[v + 1] - wv : 0.0f;
-  const float* uc1 = uc ? uc + G.sv : nullptr;
-  const float* up1 = up ? up + G.sv : nullptr;
-  const float* uc2 = uc ? uc + 2 * G.sv : nullptr;
-  const float* up2 = up ? up + 2 * G.sv : nullptr;
-  un[v] = fminf(fmaxf(eta_at(uc, up, beta, v) + inv_mu * gy, -theta), theta);
-  un[G.sv + v] = fminf(fmaxf(eta_at(uc1, up1, beta, v) + inv_mu * gx, -theta), theta);
-  un[2 * G.sv + v] = fminf(fmaxf(eta_at(uc2, up2, beta, v) + inv_mu * gz, -theta), theta);
+__global__ __launch_bounds__(256) void tv_step_kernel(float* __restrict__ un,
+                                                      const float* __restrict__ zin,
+                                                      const float* __restrict__ uc,
+                                                      const float* __restrict__ up, float beta,
+                                                      float inv_mu, float theta, Grid3 G) {
+  constexpr int EY = kTvY + 1, EX = kTvX + 1, EZ = kTvZ + 1;  // w region (tile + forward halo)
+  __shared__ float s_ey[(EY + 1) * EX * EZ];  // eta_y, y from y0 - 1
+  __shared__ float s_ex[EY * (EX + 1) * EZ];  // eta_x, x from x0 - 1
+  __shared__ float s_ez[EY * EX * (EZ + 1)];  // eta_z, z from z0 - 1
+  __shared__ float s_w[EY * EX * EZ];
+  const int nzb = (G.nz + kTvZ - 1) / kTvZ, nxb = (G.nx + kTvX - 1) / kTvX;
+  const int nyb = (G.ny + kTvY - 1) / kTvY;
+  int bb = blockIdx.x;
+  const int zb = bb % nzb;
+  bb /= nzb;
+  const int xb = bb % nxb;
+  bb /= nxb;
+  const int yb = bb % nyb;
+  const int sp = bb / nyb;
+  const int y0 = yb * kTvY, x0 = xb * kTvX, z0 = zb * kTvZ;
+  const int64_t vol = (int64_t)G.ny * G.nx * G.nz;
+  const int64_t sbase = (int64_t)sp * vol;
+  const int tid = threadIdx.x;
+  // eta of component d on a region of NY_ x NX_ x NZ_ points from (gy0, gx0, gz0)
+  // into LDS: all of a thread's loads are issued before any is used
+  auto stage = [&](float* dst, int d, auto dims, int gy0, int gx0, int gz0) {
+    constexpr int NY_ = decltype(dims)::y, NX_ = decltype(dims)::x, NZ_ = decltype(dims)::z;
+    constexpr int CNT = NY_ * NX_ * NZ_;
+    constexpr int IT = (CNT + 255) / 256;
+    const float* c = uc ? uc + d * G.sv : nullptr;
+    const float* pr = up ? up + d * G.sv : nullptr;
+    float a[IT], b[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = tid + it * 256;
+      const int lz = i % NZ_, r = i / NZ_;
+      const int lx = r % NX_, ly = r / NX_;
+      const int gy = gy0 + ly, gx = gx0 + lx, gz = gz0 + lz;
+      a[it] = 0.0f;
+      b[it] = 0.0f;
+      if (c && i < CNT && gy >= 0 && gy < G.ny && gx >= 0 && gx < G.nx && gz >= 0 && gz < G.nz) {
+        const int64_t v = sbase + ((int64_t)gy * G.nx + gx) * G.nz + gz;
+        a[it] = c[v];
+        if (pr) b[it] = pr[v];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = tid + it * 256;
+      if (i < CNT) dst[i] = pr ? a[it] + beta * (a[it] - b[it]) : a[it];
+    }
+  };
+  stage(s_ey, 0, Dims3<EY + 1, EX, EZ>{}, y0 - 1, x0, z0);
+  stage(s_ex, 1, Dims3<EY, EX + 1, EZ>{}, y0, x0 - 1, z0);
+  stage(s_ez, 2, Dims3<EY, EX, EZ + 1>{}, y0, x0, z0 - 1);
+  __syncthreads();
+  // w on the tile and its forward halo (the z loads first, then the sums)
+  constexpr int WIT = (EY * EX * EZ + 255) / 256;
+  float zv[WIT];
+#pragma unroll
+  for (int it = 0; it < WIT; ++it) {
+    const int i = tid + it * 256;
+    const int lz = i % EZ, r = i / EZ;
+    const int lx = r % EX, ly = r / EX;
+    const int gy = y0 + ly, gx = x0 + lx, gz = z0 + lz;
+    zv[it] = (i < EY * EX * EZ && gy < G.ny && gx < G.nx && gz < G.nz)
+                 ? zin[sbase + ((int64_t)gy * G.nx + gx) * G.nz + gz]
+                 : 0.0f;
+  }
+#pragma unroll
+  for (int it = 0; it < WIT; ++it) {
+    const int i = tid + it * 256;
+    if (i >= EY * EX * EZ) break;
+    const int lz = i % EZ, r = i / EZ;
+    const int lx = r % EX, ly = r / EX;
+    const int gy = y0 + ly, gx = x0 + lx, gz = z0 + lz;
+    float wv = 0.0f;
+    if (gy < G.ny && gx < G.nx && gz < G.nz) {
+      float acc = 0.0f;
+      if (gy > 0) acc += s_ey[(ly * EX + lx) * EZ + lz];
+      if (gy < G.ny - 1) acc -= s_ey[((ly + 1) * EX + lx) * EZ + lz];
+      if (gx > 0) acc += s_ex[(ly * (EX + 1) + lx) * EZ + lz];
+      if (gx < G.nx - 1) acc -= s_ex[(ly * (EX + 1) + lx + 1) * EZ + lz];
+      if (gz > 0) acc += s_ez[(ly * EX + lx) * (EZ + 1) + lz];
+      if (gz < G.nz - 1) acc -= s_ez[(ly * EX + lx) * (EZ + 1) + lz + 1];
+      wv = zv[it] - acc;
+    }
+    s_w[i] = wv;
+  }
+  __syncthreads();
+  // new duals on the tile
+  for (int i = tid; i < kTvY * kTvX * kTvZ; i += 256) {
+    const int lz = i % kTvZ, r = i / kTvZ;
+    const int lx = r % kTvX, ly = r / kTvX;
+    const int gy = y0 + ly, gx = x0 + lx, gz = z0 + lz;
+    if (gy >= G.ny || gx >= G.nx || gz >= G.nz) continue;
+    const int wi = (ly * EX + lx) * EZ + lz;
+    const float wv = s_w[wi];
+    const float gyd = gy < G.ny - 1 ? s_w[wi + EX * EZ] - wv : 0.0f;
+    const float gxd = gx < G.nx - 1 ? s_w[wi + EZ] - wv : 0.0f;
+    const float gzd = gz < G.nz - 1 ? s_w[wi + 1] - wv : 0.0f;
+    const float ey = s_ey[((ly + 1) * EX + lx) * EZ + lz];
+    const float ex = s_ex[(ly * (EX + 1) + lx + 1) * EZ + lz];
+    const float ez = s_ez[(ly * EX + lx) * (EZ + 1) + lz + 1];
+    const int64_t v = sbase + ((int64_t)gy * G.nx + gx) * G.nz + gz;
+    un[v] = fminf(fmaxf(ey + inv_mu * gyd, -theta), theta);
+    un[G.sv + v] = fminf(fmaxf(ex + inv_mu * gxd, -theta), theta);
+    un[2 * G.sv + v] = fminf(fmaxf(ez + inv_mu * gzd, -theta), theta);
+  }
 }
 
 __global__ __launch_bounds__(256) void tv_final_kernel(float* __restrict__ x,
@@ -1094,20 +1222,15 @@ static Grid3 grid3(const psoam_plan* P) {
   return G;
 }
 
-hipError_t launch_tv_w(const psoam_plan* P, float* w, const float* z, const float* u_cur,
-                       const float* u_prev, float beta, hipStream_t s) {
+hipError_t launch_tv_step(const psoam_plan* P, float* u_next, const float* z, const float* u_cur,
+                          const float* u_prev, float beta, float inv_mu, float theta,
+                          hipStream_t s) {
   const Grid3 G = grid3(P);
-  hipLaunchKernelGGL(tv_w_kernel, dim3(blocks_for((size_t)G.sv)), dim3(256), 0, s, w, z, u_cur,
-                     u_prev, beta, G);
-  return hipGetLastError();
-}
-
-hipError_t launch_tv_u(const psoam_plan* P, float* u_next, const float* u_cur,
-                       const float* u_prev, float beta, const float* w, float inv_mu,
-                       float theta, hipStream_t s) {
-  const Grid3 G = grid3(P);
-  hipLaunchKernelGGL(tv_u_kernel, dim3(blocks_for((size_t)G.sv)), dim3(256), 0, s, u_next,
-                     u_cur, u_prev, beta, w, inv_mu, theta, G);
+  const size_t nb = (size_t)P->g.n_species * ((G.ny + kTvY - 1) / kTvY) *
+                    ((G.nx + kTvX - 1) / kTvX) * ((G.nz + kTvZ - 1) / kTvZ);
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(tv_step_kernel, dim3((unsigned)nb), dim3(256), 0, s, u_next, z, u_cur,
+                     u_prev, beta, inv_mu, theta, G);
   return hipGetLastError();
 }
 
