@@ -40,9 +40,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="bf16")
-    ap.add_argument("--compare", default="fp32", help="second precision reported beside ('' = none)")
+    ap.add_argument("--compare", default="fp16,bf16_split,fp16_split,fp32",
+                    help="other precisions reported beside, comma separated ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-crop", type=int, default=12, help="lateral crop side of the oracle sample")
+    ap.add_argument("--no-c1-oracle", action="store_true",
+                    help="skip the FP64 oracle solve at C1 used for each precision's rel err")
+    ap.add_argument("--cpu-crop", type=int, default=20, help="lateral crop side of the oracle sample")
     ap.add_argument("--kernel-reps", type=int, default=10)
     return ap.parse_args()
 
@@ -134,6 +137,61 @@ def run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam
                 solve_s=t_solve, c_full=c_full, lambda_max=st_full["lambda_max"], y=y)
 
 
+def c1_oracle_errors(torch, pk, precs):
+    """Relative error of c after the C1 solve (20 FISTA steps, 20 dual TV steps,
+    TV + l1 + nonnegativity) against the FP64 oracle's c on the same inputs and
+    the same step alpha1, for each precision."""
+    import oracle
+    import synth
+    cfg = synth.C1
+    c_true, t0, taps, phi, sp, n0, v0 = synth.inputs(cfg)
+    S = oracle.switching_matrix(np.asarray(phi, np.float64), sp.a, sp.b, sp.tau, sp.gamma,
+                                cfg.n_pulses)
+    A = lambda v: oracle.apply_A(v, S, t0, taps, cfg.nt)
+    AT = lambda w: oracle.apply_AT(w, S, t0, taps, cfg.nz)
+    y = A(c_true.astype(np.float64))
+    p = (y + synth.noise_sigma(float(np.sqrt(np.mean(y ** 2)))) * n0).astype(np.float32)
+    aty = float(np.abs(AT(p.astype(np.float64))).max())
+    lam_tv, lam_l1 = 5e-3 * aty, 1e-2 * aty
+    ref = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec="fp32")
+    _, st = ref.solve(torch.from_numpy(p).cuda(), k1=0, n_power=30, v0=torch.from_numpy(v0).cuda())
+    alpha1 = st["alpha1"]
+    ref.close()
+    c_ref, _ = oracle.fista(p.astype(np.float64), A, AT, alpha1, lam_tv, lam_l1, cfg.k1, cfg.k2,
+                            shape_c=cfg.c_shape)
+    out = {}
+    for prec in precs:
+        plan = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=prec)
+        c, _ = plan.solve(torch.from_numpy(p).cuda(), lambda_tv=lam_tv, lambda_l1=lam_l1,
+                          k1=cfg.k1, k2=cfg.k2, alpha1=alpha1)
+        out[prec] = oracle.rel_err(c.cpu().numpy(), c_ref)
+        plan.close()
+    return out
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the H kernel from the committed counter summary,
+    valid only while the kernel and plan sources hash to what was profiled."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "band16_lds_H_C2_bf16_hbm.md")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    want = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            want[k.strip()] = v.strip().strip("`")
+    h = hashlib.sha1()
+    for f in ("psoam_kernels.hip", "psoam_plan.cpp", "psoam_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2510_23739_amd", "csrc", f), "rb").read())
+    if want.get("source_sha1") != h.hexdigest():
+        return None, "kernel sources changed since the counters were taken"
+    try:
+        return float(want["hbm_bytes_per_launch"]), path
+    except (KeyError, ValueError):
+        return None, "summary without hbm_bytes_per_launch"
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -167,26 +225,54 @@ def main():
     log(f"[bench] alpha1 {alpha1:.4e}; timing {args.prec}")
     res = run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1,
                    args.prec, args.steps, args.warmup, args.kernel_reps)
-    cmp = None
-    if args.compare:
-        log(f"[bench] timing {args.compare}")
-        cmp = run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1,
-                       args.compare, max(2, args.steps // 4), 1, max(2, args.kernel_reps // 4))
-    # accuracy of the timed precision's operator vs the FP64 oracle on sampled A-scans
+    others = [q for q in args.compare.split(",") if q and q != args.prec]
+    runs = {args.prec: res}
+    for q in others:
+        log(f"[bench] timing {q}")
+        slow = q == "fp32"
+        runs[q] = run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1,
+                           q, max(2, args.steps // 4) if slow else args.steps, 1 if slow else args.warmup,
+                           max(2, args.kernel_reps // 4) if slow else args.kernel_reps)
+    # accuracy of each precision's operator vs the FP64 oracle on sampled A-scans
     import oracle
     S = oracle.switching_matrix(phi, sp.a, sp.b, sp.tau, sp.gamma, cfg.n_pulses)
     scans = [(5, 7), (64, 64), (127, 0), (90, 33)]
     y_s = oracle.apply_A_scans(c_true, S, t0, taps, cfg.nt, scans)
-    res["plan"].apply_A(torch.from_numpy(c_true).cuda(), res["y"])
-    y_g = np.stack([res["y"][:, iy, ix, :].cpu().numpy() for (iy, ix) in scans])
-    err_A = oracle.rel_err(y_g, y_s)
-    err_c_vs = None
-    if cmp is not None:
-        err_c_vs = float((res["c_full"] - cmp["c_full"]).double().norm() / cmp["c_full"].double().norm())
+    c_in = torch.from_numpy(c_true).cuda()
+    err_A = {}
+    for q, r in runs.items():
+        r["plan"].apply_A(c_in, r["y"])
+        y_g = np.stack([r["y"][:, iy, ix, :].cpu().numpy() for (iy, ix) in scans])
+        err_A[q] = oracle.rel_err(y_g, y_s)
+    c1_err = {}
+    if not args.no_c1_oracle:
+        log("[bench] C1 solves vs the FP64 oracle")
+        c1_err = c1_oracle_errors(torch, pk, list(runs))
     info = res["info"]
     alg_flops = 2.0 * info["useful_macs"][0] * cfg.n_pulses * cfg.nx * cfg.ny
     peak = PEAK_TFLOPS[args.prec]
     achieved = alg_flops / (res["t_H"] * 1e-3) / 1e12
+    traffic, traffic_src = profiled_traffic()
+    fp32 = runs.get("fp32")
+
+    def err_vs_fp32(r):
+        if fp32 is None or r is fp32:
+            return None
+        return float((r["c_full"] - fp32["c_full"]).double().norm() / fp32["c_full"].double().norm())
+
+    per_prec = {}
+    for q, r in runs.items():
+        per_prec[q] = {
+            "ms_per_step": r["step_s"] * 1e3, "applies_per_s_in_solver": 1.0 / r["step_s"],
+            "apply_A_ms": r["t_A"], "apply_AT_ms": r["t_AT"],
+            "isolated_applies_per_s": 1e3 / (r["t_A"] + r["t_AT"]),
+            "H_kernel_ms": r["t_H"], "HT_kernel_ms": r["t_HT"],
+            "H_alg_frac_of_peak": alg_flops / (r["t_H"] * 1e-3) / 1e12 / PEAK_TFLOPS[q],
+            "fista_s_to_tol": r["solve_s"], "fista_iterations": cfg.k1,
+            "rel_err_A_vs_oracle_sampled": err_A[q],
+            "rel_err_c_vs_fp32_C2": err_vs_fp32(r),
+            "rel_err_c_vs_oracle_C1": c1_err.get(q),
+        }
     out = {
         "metric": METRIC,
         "value": 1.0 / res["step_s"],
@@ -205,26 +291,15 @@ def main():
                    "nx": cfg.nx, "ny": cfg.ny, "nz": cfg.nz, "species": cfg.n_species,
                    "pulses": cfg.n_pulses, "nt": cfg.nt, "footprint": cfg.f, "k2": cfg.k2},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
                      "kernel": f"band contraction H ({args.prec}), algorithmic flops "
                                f"2*nnz*K*Nx*Ny = {alg_flops / 1e9:.1f} GFLOP per launch",
-                     "avg_ms": res["t_H"]},
+                     "avg_ms": res["t_H"], "traffic_source": traffic_src},
         "cpu_baseline": None,
-        "apply_A_ms": res["t_A"], "apply_AT_ms": res["t_AT"],
-        "isolated_applies_per_s": 1e3 / (res["t_A"] + res["t_AT"]),
-        "H_kernel_ms": res["t_H"], "HT_kernel_ms": res["t_HT"],
         "fista_s_to_tol": res["solve_s"], "fista_iterations": cfg.k1,
-        "rel_err_A_vs_oracle_sampled": err_A,
         "band_fill": info["useful_macs"][0] / max(1, info["executed_macs"][0]),
+        "precisions": per_prec,
     }
-    if cmp is not None:
-        out["compare"] = {
-            "dtype": args.compare, "ms_per_step": cmp["step_s"] * 1e3,
-            "applies_per_s": 1.0 / cmp["step_s"], "apply_A_ms": cmp["t_A"], "apply_AT_ms": cmp["t_AT"],
-            "H_kernel_ms": cmp["t_H"], "HT_kernel_ms": cmp["t_HT"], "fista_s_to_tol": cmp["solve_s"],
-            "H_frac_of_peak": alg_flops / (cmp["t_H"] * 1e-3) / 1e12 / PEAK_TFLOPS[args.compare],
-            "rel_err_c_vs_this": err_c_vs,
-        }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(cfg, t0, taps, phi, sp, args.cpu_crop, args.steps)
