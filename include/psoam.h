@@ -178,10 +178,22 @@ typedef struct {
 int psoam_solve(const psoam_plan* plan, const float* p, float* c, const psoam_solve_opts* o,
                 psoam_solve_stats* st, void* stream);
 
-/* n independent solves (plans of different shapes allowed) issued as one
- * batch: each outer step of every problem is launched as one grouped
- * launch per phase.  Arrays of length n; opts/st arrays too (st may be
- * NULL).  Same semantics per problem as psoam_solve. */
+/* n independent solves (plans of different shapes and pulse counts allowed)
+ * as one batch, the batched family of reconstructions of the same method
+ * (Alg. alg:prox-outer per problem).  Arrays of length n; opts/st arrays
+ * too (st may be NULL).  Same result per problem as psoam_solve.
+ * Execution: every problem runs on a stream of its own (default priority);
+ * the power iterations run concurrently, then pairs of outer iterations of
+ * all problems are captured into one HIP graph (one branch per problem, the
+ * FISTA step state kept on the device) and replayed; an odd last iteration
+ * runs uncaptured.  Problems whose options need host decisions inside the
+ * loop (eps1 > 0, eps2 > 0, a trace, warm_inner, k1 < 2), and every problem
+ * when a plan appears twice in the batch (plans own their operand buffers),
+ * are solved one after another on the caller's stream instead.  The call
+ * synchronises the streams it creates; results are ordered before later
+ * work on `stream`.  EINVAL: bad arguments (checked for all problems before
+ * any work); EHIP: stream, event or graph call failed; EDIVERGED as for
+ * psoam_solve. */
 int psoam_solve_batch(int32_t n, const psoam_plan* const* plans, const float* const* p,
                       float* const* c, const psoam_solve_opts* o, psoam_solve_stats* st,
                       void* stream);

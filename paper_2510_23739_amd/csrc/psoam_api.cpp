@@ -3,6 +3,7 @@
 // iteration of Alg. alg:prox-inner for the TV part).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -143,8 +144,7 @@ int objective_terms(psoam_plan* P, const float* c, const float* p, hipStream_t s
   return PSOAM_OK;
 }
 
-int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o,
-              psoam_solve_stats* st, hipStream_t s) {
+int check_opts(const float* p, const float* c, const psoam_solve_opts* o) {
   if (!p || !c || !o) return fail(PSOAM_EINVAL, "solve: NULL argument");
   if (o->k1 < 0 || o->k2 < 0 || !(o->lambda_tv >= 0.0) || !(o->lambda_l1 >= 0.0) ||
       !std::isfinite(o->lambda_tv) || !std::isfinite(o->lambda_l1) || !(o->eps1 >= 0.0) ||
@@ -152,46 +152,71 @@ int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o
     return fail(PSOAM_EINVAL, "solve: invalid options (negative or non-finite)");
   if (o->alpha1 <= 0.0 && o->n_power < 1)
     return fail(PSOAM_EINVAL, "solve: n_power must be >= 1 when alpha1 is not given");
+  return PSOAM_OK;
+}
+
+// power iteration on A^T A with FP64 norms, enqueued only: v <- v0/|v0|;
+// n_power times [w = A^T A v; lam = <v, w>; v = w/|w|]; lam in d_scalars[0]
+int enqueue_power(psoam_plan* P, SolveBufs& B, const psoam_solve_opts* o, hipStream_t s) {
+  const int64_t sv = (int64_t)P->c_elems();
+  float* v = B.zb;
+  float* w = B.g;
+  if (o->v0) {
+    PSOAM_HIP(hipMemcpyAsync(w, o->v0, sizeof(float) * sv, hipMemcpyDeviceToDevice, s));
+  } else {
+    PSOAM_HIP(launch_fill(w, 1.0f, sv, s));
+  }
+  PSOAM_HIP(launch_dot(w, w, sv, P->d_partial, P->d_scalars + 1, s));
+  PSOAM_HIP(launch_scale_by_rnorm(v, w, P->d_scalars + 1, sv, s));
+  for (int i = 0; i < o->n_power; ++i) {
+    PSOAM_HIP(launch_switch_fwd(P, v, s));
+    PSOAM_HIP(launch_band(P, 1, nullptr, nullptr, P->d_partial, s));
+    PSOAM_HIP(launch_band(P, 2, w, nullptr, nullptr, s));
+    PSOAM_HIP(launch_dot(v, w, sv, P->d_partial, P->d_scalars + 0, s));
+    PSOAM_HIP(launch_dot(w, w, sv, P->d_partial, P->d_scalars + 1, s));
+    PSOAM_HIP(launch_scale_by_rnorm(v, w, P->d_scalars + 1, sv, s));
+  }
+  return PSOAM_OK;
+}
+
+// reads the estimate (synchronises s) and sets alpha1 = 1 / (1.01 lam)
+int finish_power(psoam_plan* P, psoam_solve_stats& stats, psoam_solve_stats* st, double& alpha1,
+                 hipStream_t s) {
+  double hs[2];
+  if (int rc = copy_scalars(P, hs, 2, s)) return rc;
+  stats.lambda_max = hs[0];
+  if (!std::isfinite(hs[0]) || !(hs[0] > 0.0) || !std::isfinite(hs[1])) {
+    stats.status = PSOAM_EDIVERGED;
+    if (st) *st = stats;
+    return fail(PSOAM_EDIVERGED, "solve: power iteration gave a non-finite or non-positive estimate");
+  }
+  alpha1 = 1.0 / (1.01 * hs[0]);
+  return PSOAM_OK;
+}
+
+psoam_solve_stats fresh_stats() {
+  psoam_solve_stats stats;
+  stats.iterations = 0;
+  stats.status = PSOAM_OK;
+  stats.alpha1 = 0.0;
+  stats.lambda_max = 0.0;
+  stats.objective = std::numeric_limits<double>::quiet_NaN();
+  return stats;
+}
+
+int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o,
+              psoam_solve_stats* st, hipStream_t s) {
+  if (int rc = check_opts(p, c, o)) return rc;
   SolveBufs B;
   int rc = ensure_solve_ws(P, B);
   if (rc) return rc;
   const int64_t sv = (int64_t)P->c_elems();
   double hs[16];
-  psoam_solve_stats stats;
-  stats.iterations = 0;
-  stats.status = PSOAM_OK;
-  stats.lambda_max = 0.0;
-  stats.objective = std::numeric_limits<double>::quiet_NaN();
+  psoam_solve_stats stats = fresh_stats();
   double alpha1 = o->alpha1;
   if (alpha1 <= 0.0) {
-    // power iteration on A^T A with FP64 norms: v <- v0/|v0|; w = A^T A v;
-    // lam = <v, w>; v = w/|w|
-    float* v = B.zb;
-    float* w = B.g;
-    if (o->v0) {
-      PSOAM_HIP(hipMemcpyAsync(w, o->v0, sizeof(float) * sv, hipMemcpyDeviceToDevice, s));
-    } else {
-      PSOAM_HIP(launch_fill(w, 1.0f, sv, s));
-    }
-    PSOAM_HIP(launch_dot(w, w, sv, P->d_partial, P->d_scalars + 1, s));
-    PSOAM_HIP(launch_scale_by_rnorm(v, w, P->d_scalars + 1, sv, s));
-    for (int i = 0; i < o->n_power; ++i) {
-      PSOAM_HIP(launch_switch_fwd(P, v, s));
-      PSOAM_HIP(launch_band(P, 1, nullptr, nullptr, P->d_partial, s));
-      PSOAM_HIP(launch_band(P, 2, w, nullptr, nullptr, s));
-      PSOAM_HIP(launch_dot(v, w, sv, P->d_partial, P->d_scalars + 0, s));
-      PSOAM_HIP(launch_dot(w, w, sv, P->d_partial, P->d_scalars + 1, s));
-      PSOAM_HIP(launch_scale_by_rnorm(v, w, P->d_scalars + 1, sv, s));
-    }
-    rc = copy_scalars(P, hs, 2, s);
-    if (rc) return rc;
-    stats.lambda_max = hs[0];
-    if (!std::isfinite(hs[0]) || !(hs[0] > 0.0) || !std::isfinite(hs[1])) {
-      stats.status = PSOAM_EDIVERGED;
-      if (st) *st = stats;
-      return fail(PSOAM_EDIVERGED, "solve: power iteration gave a non-finite or non-positive estimate");
-    }
-    alpha1 = 1.0 / (1.01 * hs[0]);
+    if ((rc = enqueue_power(P, B, o, s))) return rc;
+    if ((rc = finish_power(P, stats, st, alpha1, s))) return rc;
   }
   stats.alpha1 = alpha1;
   const bool literal = o->literal_momentum != 0;
@@ -273,6 +298,162 @@ int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o
   if (!std::isfinite(hs[0])) stats.status = PSOAM_EDIVERGED;
   if (st) *st = stats;
   if (stats.status != PSOAM_OK) return fail(PSOAM_EDIVERGED, "solve: iterate became non-finite");
+  return PSOAM_OK;
+}
+
+// ---- batched solves (several plans, captured iterations) -------------------
+
+struct BatchItem {
+  psoam_plan* P;
+  const float* p;
+  float* c;
+  const psoam_solve_opts* o;
+  psoam_solve_stats* st;
+  psoam_solve_stats stats;
+  SolveBufs B;
+  double alpha1;
+  int remaining;
+};
+
+// One outer iteration with the step state t_k on the device (d_scalars[8])
+// and no host reads: the form solve_batch captures.  Same launches and the
+// same arithmetic as solve_one's loop without stopping tests.
+int enqueue_iteration(BatchItem& it, hipStream_t s) {
+  psoam_plan* P = it.P;
+  const int64_t sv = (int64_t)P->c_elems();
+  SolveBufs& B = it.B;
+  const psoam_solve_opts* o = it.o;
+  const bool literal = o->literal_momentum != 0;
+  const float th_tv = (float)(it.alpha1 * o->lambda_tv);
+  const float th_l1 = (float)(it.alpha1 * o->lambda_l1);
+  PSOAM_HIP(launch_switch_fwd(P, B.xi, s));
+  PSOAM_HIP(launch_band(P, 1, nullptr, it.p, P->d_partial, s));
+  PSOAM_HIP(launch_band(P, 2, B.g, nullptr, nullptr, s));
+  PSOAM_HIP(launch_axpby(B.zb, B.xi, B.g, 1.0f, (float)(-it.alpha1), sv, s));
+  float* uw[3] = {B.u[0], B.u[1], B.u[2]};
+  if (int rc = tv_prox_core(P, B.cnext, B.zb, th_tv, o->k2, 2, th_l1, uw, B.w, nullptr, literal,
+                            nullptr, s))
+    return rc;
+  PSOAM_HIP(launch_momentum_dev(B.xi, B.cnext, B.cprev, P->d_scalars + 8, literal ? 1 : 0, sv, s));
+  std::swap(B.cprev, B.cnext);  // cprev = c_{k+1}
+  return PSOAM_OK;
+}
+
+// Streams and events of one batch call, released on every exit path.
+struct BatchStreams {
+  std::vector<hipStream_t> ss;
+  std::vector<hipEvent_t> ev;
+  hipStream_t cs = nullptr;
+  hipEvent_t e_main = nullptr;
+  ~BatchStreams() {
+    for (hipStream_t x : ss)
+      if (x) (void)hipStreamDestroy(x);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e_main) (void)hipEventDestroy(e_main);
+  }
+};
+
+// Problems on their own streams (default priority): the power iterations run
+// concurrently; then pairs of outer iterations of every active problem are
+// captured into one graph (one branch per problem) and replayed — a pair
+// brings the c_k / c_{k+1} buffers back to their roles, so one graph serves
+// every replay; a final odd iteration runs eagerly.
+int solve_batch_graph(std::vector<BatchItem>& items, hipStream_t caller) {
+  const int n = (int)items.size();
+  BatchStreams bs;
+  bs.ss.assign(n, nullptr);
+  bs.ev.assign(n, nullptr);
+  for (int i = 0; i < n; ++i) {
+    PSOAM_HIP(hipStreamCreateWithFlags(&bs.ss[i], hipStreamNonBlocking));
+    PSOAM_HIP(hipEventCreateWithFlags(&bs.ev[i], hipEventDisableTiming));
+  }
+  PSOAM_HIP(hipStreamCreateWithFlags(&bs.cs, hipStreamNonBlocking));
+  PSOAM_HIP(hipEventCreateWithFlags(&bs.e_main, hipEventDisableTiming));
+  PSOAM_HIP(hipEventRecord(bs.e_main, caller));
+  for (int i = 0; i < n; ++i) PSOAM_HIP(hipStreamWaitEvent(bs.ss[i], bs.e_main, 0));
+  // phase 1: step sizes
+  for (int i = 0; i < n; ++i) {
+    BatchItem& it = items[i];
+    it.alpha1 = it.o->alpha1;
+    if (it.alpha1 <= 0.0)
+      if (int rc = enqueue_power(it.P, it.B, it.o, bs.ss[i])) return rc;
+  }
+  for (int i = 0; i < n; ++i) {
+    BatchItem& it = items[i];
+    if (it.o->alpha1 <= 0.0)
+      if (int rc = finish_power(it.P, it.stats, it.st, it.alpha1, bs.ss[i])) return rc;
+    it.stats.alpha1 = it.alpha1;
+    const int64_t sv = (int64_t)it.P->c_elems();
+    PSOAM_HIP(hipMemcpyAsync(it.B.cprev, it.c, sizeof(float) * sv, hipMemcpyDeviceToDevice, bs.ss[i]));
+    PSOAM_HIP(hipMemcpyAsync(it.B.xi, it.c, sizeof(float) * sv, hipMemcpyDeviceToDevice, bs.ss[i]));
+    PSOAM_HIP(launch_set_double(it.P->d_scalars + 8, 1.0, bs.ss[i]));
+    it.remaining = it.o->k1;
+    PSOAM_HIP(hipEventRecord(bs.ev[i], bs.ss[i]));
+    PSOAM_HIP(hipStreamWaitEvent(bs.cs, bs.ev[i], 0));
+  }
+  // phase 2: captured pairs of iterations
+  for (;;) {
+    int r = 1 << 30;
+    for (const BatchItem& it : items)
+      if (it.remaining >= 2) r = std::min(r, it.remaining / 2);
+    if (r == (1 << 30)) break;
+    hipGraph_t graph = nullptr;
+    PSOAM_HIP(hipStreamBeginCapture(bs.cs, hipStreamCaptureModeRelaxed));
+    int rc = PSOAM_OK;
+    hipError_t he = hipEventRecord(bs.e_main, bs.cs);
+    for (int i = 0; i < n && rc == PSOAM_OK && he == hipSuccess; ++i) {
+      BatchItem& it = items[i];
+      if (it.remaining < 2) continue;
+      he = hipStreamWaitEvent(bs.ss[i], bs.e_main, 0);
+      if (he == hipSuccess) rc = enqueue_iteration(it, bs.ss[i]);
+      if (rc == PSOAM_OK && he == hipSuccess) rc = enqueue_iteration(it, bs.ss[i]);
+      if (rc == PSOAM_OK && he == hipSuccess) he = hipEventRecord(bs.ev[i], bs.ss[i]);
+      if (rc == PSOAM_OK && he == hipSuccess) he = hipStreamWaitEvent(bs.cs, bs.ev[i], 0);
+    }
+    const hipError_t he_end = hipStreamEndCapture(bs.cs, &graph);
+    if (rc != PSOAM_OK || he != hipSuccess || he_end != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (rc != PSOAM_OK) return rc;
+      return fail(PSOAM_EHIP, std::string("solve_batch: graph capture: ") +
+                                  hipGetErrorString(he != hipSuccess ? he : he_end));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t hi = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (hi != hipSuccess) return fail(PSOAM_EHIP, std::string("solve_batch: graph instantiate: ") + hipGetErrorString(hi));
+    hipError_t hl = hipSuccess;
+    for (int k = 0; k < r && hl == hipSuccess; ++k) hl = hipGraphLaunch(exec, bs.cs);
+    (void)hipGraphExecDestroy(exec);
+    if (hl != hipSuccess) return fail(PSOAM_EHIP, std::string("solve_batch: graph launch: ") + hipGetErrorString(hl));
+    for (BatchItem& it : items)
+      if (it.remaining >= 2) it.remaining -= 2 * r;
+  }
+  // odd last iterations, results, join the caller's stream
+  PSOAM_HIP(hipEventRecord(bs.e_main, bs.cs));
+  for (int i = 0; i < n; ++i) {
+    BatchItem& it = items[i];
+    PSOAM_HIP(hipStreamWaitEvent(bs.ss[i], bs.e_main, 0));
+    if (it.remaining == 1)
+      if (int rc = enqueue_iteration(it, bs.ss[i])) return rc;
+    it.stats.iterations = it.o->k1;
+    const int64_t sv = (int64_t)it.P->c_elems();
+    PSOAM_HIP(hipMemcpyAsync(it.c, it.B.cprev, sizeof(float) * sv, hipMemcpyDeviceToDevice, bs.ss[i]));
+    PSOAM_HIP(launch_dot(it.c, it.c, sv, it.P->d_partial, it.P->d_scalars + 0, bs.ss[i]));
+  }
+  int status = PSOAM_OK;
+  for (int i = 0; i < n; ++i) {
+    BatchItem& it = items[i];
+    double h;
+    if (int rc = copy_scalars(it.P, &h, 1, bs.ss[i])) return rc;
+    if (!std::isfinite(h)) it.stats.status = PSOAM_EDIVERGED;
+    if (it.st) *it.st = it.stats;
+    if (it.stats.status != PSOAM_OK) status = PSOAM_EDIVERGED;
+    PSOAM_HIP(hipEventRecord(bs.ev[i], bs.ss[i]));
+    PSOAM_HIP(hipStreamWaitEvent(caller, bs.ev[i], 0));
+  }
+  if (status != PSOAM_OK) return fail(PSOAM_EDIVERGED, "solve_batch: an iterate became non-finite");
   return PSOAM_OK;
 }
 
@@ -362,14 +543,44 @@ int psoam_solve_batch(int32_t n, const psoam_plan* const* plans, const float* co
                       float* const* c, const psoam_solve_opts* o, psoam_solve_stats* st,
                       void* stream) {
   if (n < 0) return fail(PSOAM_EINVAL, "solve_batch: n < 0");
-  if (n > 0 && (!plans || !p || !c || !o)) return fail(PSOAM_EINVAL, "solve_batch: NULL argument");
+  if (n == 0) return PSOAM_OK;
+  if (!plans || !p || !c || !o) return fail(PSOAM_EINVAL, "solve_batch: NULL argument");
   for (int i = 0; i < n; ++i) {
     if (!plans[i]) return fail(PSOAM_EINVAL, "solve_batch: NULL plan");
-    const int rc = solve_one(const_cast<psoam_plan*>(plans[i]), p[i], c[i], &o[i],
-                             st ? &st[i] : nullptr, S(stream));
-    if (rc) return rc;
+    if (int rc = check_opts(p[i], c[i], &o[i])) return rc;
   }
-  return PSOAM_OK;
+  // Captured iterations need distinct plans (each owns its operand buffers and
+  // scalars) and no host decisions inside the loop; other problems are solved
+  // one after another on the caller's stream.
+  bool distinct = true;
+  for (int i = 0; i < n && distinct; ++i)
+    for (int j = 0; j < i; ++j)
+      if (plans[i] == plans[j]) distinct = false;
+  std::vector<BatchItem> items;
+  for (int i = 0; i < n; ++i) {
+    const psoam_solve_opts* oi = &o[i];
+    const bool graphable = distinct && oi->eps1 == 0.0 && oi->eps2 == 0.0 && !oi->trace &&
+                           !oi->warm_inner && oi->k1 >= 2;
+    if (!graphable) {
+      const int rc = solve_one(const_cast<psoam_plan*>(plans[i]), p[i], c[i], oi,
+                               st ? &st[i] : nullptr, S(stream));
+      if (rc) return rc;
+      continue;
+    }
+    BatchItem it;
+    it.P = const_cast<psoam_plan*>(plans[i]);
+    it.p = p[i];
+    it.c = c[i];
+    it.o = oi;
+    it.st = st ? &st[i] : nullptr;
+    it.stats = fresh_stats();
+    it.alpha1 = 0.0;
+    it.remaining = 0;
+    if (int rc = ensure_solve_ws(it.P, it.B)) return rc;
+    items.push_back(it);
+  }
+  if (items.empty()) return PSOAM_OK;
+  return solve_batch_graph(items, S(stream));
 }
 
 int psoam_plan_stats(const psoam_plan* plan, psoam_plan_info* info) {

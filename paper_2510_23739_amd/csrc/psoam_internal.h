@@ -171,5 +171,10 @@ hipError_t launch_fill(float* x, float v, int64_t n, hipStream_t s);
 hipError_t launch_momentum(float* xi, const float* c_next, const float* c_prev, float beta,
                            int64_t n, double* partial, hipStream_t s);
 size_t reduce_blocks(int64_t n);
+// xi = c_next + beta (c_next - c_prev) with beta from the device step state
+// tst[0] = t_k, which is then advanced to t_{k+1} (captured iterations)
+hipError_t launch_momentum_dev(float* xi, const float* c_next, const float* c_prev, double* tst,
+                               int literal, int64_t n, hipStream_t s);
+hipError_t launch_set_double(double* p, double v, hipStream_t s);
 
 }  // namespace psoam

@@ -1407,4 +1407,45 @@ hipError_t launch_momentum(float* xi, const float* c_next, const float* c_prev, 
   return hipGetLastError();
 }
 
+// Momentum with the FISTA step state on the device (for captured iterations,
+// whose kernel arguments are fixed): t_k is read from tst[0], the weight is
+// formed in FP64 exactly as the host does (Beck-Teboulle (t-1)/t', or the
+// printed (t-1)/(t+1)), and xi = c_{k+1} + beta (c_{k+1} - c_k).
+__global__ __launch_bounds__(256) void momentum_dev_kernel(float* __restrict__ xi,
+                                                           const float* __restrict__ cn,
+                                                           const float* __restrict__ cp,
+                                                           const double* __restrict__ tst,
+                                                           int literal, int64_t n) {
+  const double t = tst[0];
+  const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+  const float beta = (float)(literal ? (t - 1.0) / (t + 1.0) : (t - 1.0) / tn);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float a = cn[i];
+    xi[i] = a + beta * (a - cp[i]);
+  }
+}
+
+// t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, one thread, after the momentum kernel
+__global__ void advance_t_kernel(double* tst) {
+  const double t = tst[0];
+  tst[0] = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+}
+
+__global__ void set_double_kernel(double* p, double v) { p[0] = v; }
+
+hipError_t launch_momentum_dev(float* xi, const float* c_next, const float* c_prev, double* tst,
+                               int literal, int64_t n, hipStream_t s) {
+  const size_t nb = reduce_blocks(n);
+  hipLaunchKernelGGL(momentum_dev_kernel, dim3((unsigned)nb), dim3(256), 0, s, xi, c_next, c_prev,
+                     (const double*)tst, literal, n);
+  hipLaunchKernelGGL(advance_t_kernel, dim3(1), dim3(1), 0, s, tst);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_double(double* p, double v, hipStream_t s) {
+  hipLaunchKernelGGL(set_double_kernel, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+
 }  // namespace psoam
