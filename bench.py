@@ -47,6 +47,8 @@ def parse():
                     help="skip the FP64 oracle solve at C1 used for each precision's rel err")
     ap.add_argument("--cpu-crop", type=int, default=20, help="lateral crop side of the oracle sample")
     ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--no-scales", action="store_true",
+                    help="skip the 256x256x96 / 320x320x128 applies and the 16-problem batch")
     return ap.parse_args()
 
 
@@ -192,6 +194,76 @@ def profiled_traffic():
         return None, "summary without hbm_bytes_per_launch"
 
 
+def scale_runs(torch, pk):
+    """Isolated A / A^T applies at 256x256x96 (BF16, FP16, BF16 split, FP32)
+    and 320x320x128 (BF16, FP32), and the 16 uneven problems of the batched
+    family solved as one batch vs one after another.  Timing inputs are
+    seeded uniform concentrations (operator cost does not depend on values;
+    parity at these sizes is in the GPU tests)."""
+    import synth
+    out = {}
+    for cfg, precs in ((synth.C3, ("bf16", "fp16", "bf16_split", "fp32")),
+                       (synth.C5, ("bf16", "fp32"))):
+        t0, taps = synth.sir_table(cfg.nz, cfg.f, cfg.nt)
+        phi = synth.phi_depth(cfg.nz)
+        sp = synth.species(cfg.n_species)
+        c = torch.from_numpy(np.random.default_rng(cfg.seed).random(cfg.c_shape, dtype=np.float32)).cuda()
+        y = torch.empty(cfg.y_shape, dtype=torch.float32, device="cuda")
+        g = torch.empty(cfg.c_shape, dtype=torch.float32, device="cuda")
+        rows = {}
+        for prec in precs:
+            log(f"[bench] {cfg.name} {prec}")
+            plan = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=prec)
+            info = plan.stats()
+            reps = 2 if prec == "fp32" else 5
+            t_A = time_events(torch, lambda: plan.apply_A(c, y), reps)
+            t_AT = time_events(torch, lambda: plan.apply_AT(y, g), reps)
+            plan.apply_A(c, y)
+            t_H = time_events(torch, lambda: plan.band_only(0, y), reps)
+            alg = 2.0 * info["useful_macs"][0] * cfg.n_pulses * cfg.nx * cfg.ny
+            rows[prec] = {"apply_A_ms": t_A, "apply_AT_ms": t_AT,
+                          "isolated_applies_per_s": 1e3 / (t_A + t_AT), "H_kernel_ms": t_H,
+                          "H_alg_frac_of_peak": alg / (t_H * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
+                          "staged_rows": info["lds_rows"]}
+            plan.close()
+            torch.cuda.empty_cache()
+        out[f"{cfg.nx}x{cfg.ny}x{cfg.nz} S{cfg.n_species} K{cfg.n_pulses} Nt{cfg.nt} F{cfg.f}"] = rows
+        del c, y, g
+        torch.cuda.empty_cache()
+    # batched family: 16 instances, BF16, 10 outer iterations each (K2 20),
+    # step from a 10-step power iteration, batch vs one-by-one
+    log("[bench] batched family")
+    plans, ps, opts = [], [], []
+    for i in range(16):
+        cfg = synth.c4_instance(i)
+        t0, taps = synth.sir_table(cfg.nz, cfg.f, cfg.nt)
+        plan = pk.Plan.from_config(cfg, synth.phi_depth(cfg.nz), synth.species(cfg.n_species), t0,
+                                   taps, prec="bf16")
+        rng = np.random.default_rng(cfg.seed)
+        ps.append(torch.from_numpy(rng.standard_normal(cfg.y_shape, dtype=np.float32)).cuda())
+        plans.append(plan)
+        opts.append(dict(lambda_tv=1e-3, lambda_l1=1e-3, k1=10, k2=20, n_power=10))
+    cs = [torch.zeros(pl.c_shape, dtype=torch.float32, device="cuda") for pl in plans]
+    pk.solve_batch(plans, ps, cs, opts)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    pk.solve_batch(plans, ps, cs, opts)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    t = time.perf_counter()
+    for pl, p_, c_, o in zip(plans, ps, cs, opts):
+        c_.zero_()
+        pl.solve(p_, c=c_, lambda_tv=o["lambda_tv"], lambda_l1=o["lambda_l1"], k1=o["k1"], k2=o["k2"],
+                 n_power=o["n_power"])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    out["batched_16_uneven_bf16_k1_10"] = {"batch_s": t_batch, "one_by_one_s": t_seq,
+                                           "speedup": t_seq / t_batch}
+    for pl in plans:
+        pl.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -300,6 +372,10 @@ def main():
         "band_fill": info["useful_macs"][0] / max(1, info["executed_macs"][0]),
         "precisions": per_prec,
     }
+    if not args.no_scales:
+        del runs, res, fp32
+        torch.cuda.empty_cache()
+        out["scales"] = scale_runs(torch, pk)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(cfg, t0, taps, phi, sp, args.cpu_crop, args.steps)
