@@ -32,6 +32,7 @@ __all__ = [
     "apply_H", "apply_HT", "apply_A", "apply_AT", "dense_A",
     "apply_A_scans", "apply_AT_columns",
     "grad", "grad_T", "tv", "tv_step_constant", "prox_l1", "prox_tv", "prox_w",
+    "switching_norm2", "r3_dual_steps", "prox_r3",
     "power_iteration", "objective", "fista", "fista_momentum", "rel_err",
 ]
 
@@ -362,6 +363,76 @@ def prox_w(z: np.ndarray, theta_tv: float, theta_l1: float, n_inner: int,
 
 
 # ----------------------------------------------------------------------------
+# the full one-step regulariser R3 with its TV(S c) term  (eq. reg-tv-l1-one;
+# the stacked operator L = [L1; L2; L3] and Alg. alg:prox-inner on its dual)
+# ----------------------------------------------------------------------------
+def switching_norm2(S: np.ndarray) -> float:
+    """max over voxels of the squared spectral norm of S_v ([K][S] blocks)."""
+    S = np.asarray(S, dtype=np.float64)
+    return float(np.max(np.linalg.norm(S, ord=2, axis=(-2, -1)) ** 2))
+
+
+def r3_dual_steps(shape_v: Sequence[int], S: np.ndarray, theta_tv: float, theta_tvs: float,
+                  theta_l1: float) -> Tuple[float, float, float]:
+    """Per-block dual steps of the stacked prox.  With L = [l1 grad; l2 grad S;
+    l3 I] and the duals rescaled block by block (u_b = l_b u'_b, so the
+    projection radius alpha_1 of Alg. alg:prox-inner becomes theta_b =
+    alpha_1 l_b), the step alpha_2 = 1/eig_max(L^T L) multiplies block b by
+    l_b^2, i.e. theta_b^2 / (sum_b' theta_b'^2 m_b').  eig_max(L^T L) is
+    replaced by the upper bound sum_b l_b^2 m_b with m_1 = eig_max(grad^T grad)
+    (closed form), m_2 = m_1 * max_v |S_v|^2 (|grad S x| <= |grad| |S x|) and
+    m_3 = 1: the eigenvalues of a sum of symmetric PSD matrices are at most the
+    sum of their largest ones, so the step stays at or below 1/eig_max."""
+    mu = tv_step_constant(shape_v)
+    bsum = theta_tv ** 2 * mu + theta_tvs ** 2 * mu * switching_norm2(S) + theta_l1 ** 2
+    if bsum == 0.0:
+        return 0.0, 0.0, 0.0
+    return theta_tv ** 2 / bsum, theta_tvs ** 2 / bsum, theta_l1 ** 2 / bsum
+
+
+def prox_r3(z: np.ndarray, S: np.ndarray, theta_tv: float, theta_tvs: float, theta_l1: float,
+            n_inner: int, literal_momentum: bool = False, return_dual: bool = False):
+    """Proximal map of theta_tv TV(x) + theta_tvs sum_k TV((S x)^k) +
+    theta_l1 |x|_1 + indicator(x >= 0) by the paper's dual iteration on the
+    stacked operator (Alg. alg:prox-inner, eq. prox-dual, L of eq.
+    reg-tv-l1-one's text: TV of c, TV of S c, l1):
+        w = z - (grad^T e1 + S^T grad^T e2 + e3)
+        u1' = clip(e1 + s1 grad w, theta_tv)
+        u2' = clip(e2 + s2 grad (S w), theta_tvs)
+        u3' = clip(e3 + s3 w, theta_l1)
+        e_b = u_b' + beta (u_b' - u_b)
+    from zero duals, exactly n_inner steps (steps s_b from r3_dual_steps),
+    then x = max(z - (grad^T u1 + S^T grad^T u2 + u3), 0).
+    The iteration projects the duals onto their boxes only and clamps at the
+    end, as printed; it converges to the clamp of the prox of the regulariser
+    without the sign constraint, which equals the prox with it when
+    theta_tvs = 0 or S does not mix species, and differs otherwise.
+    z: [S][Ny][Nx][Nz]; S: [Nz][K][S] or [Ny][Nx][Nz][K][S]."""
+    z = np.asarray(z, dtype=np.float64)
+    s1, s2, s3 = r3_dual_steps(z.shape[-3:], S, theta_tv, theta_tvs, theta_l1)
+    n_k = S.shape[-2]
+    u1 = np.zeros((3,) + z.shape)
+    u2 = np.zeros((3, n_k) + z.shape[1:])
+    u3 = np.zeros(z.shape)
+    e1, e2, e3 = u1.copy(), u2.copy(), u3.copy()
+    t = 1.0
+
+    def lt(a1, a2, a3):
+        return grad_T(a1) + apply_ST(grad_T(a2), S) + a3
+
+    for _ in range(n_inner):
+        w = z - lt(e1, e2, e3)
+        n1 = np.clip(e1 + s1 * grad(w), -theta_tv, theta_tv)
+        n2 = np.clip(e2 + s2 * grad(apply_S(w, S)), -theta_tvs, theta_tvs)
+        n3 = np.clip(e3 + s3 * w, -theta_l1, theta_l1)
+        t, beta = fista_momentum(t, literal_momentum)
+        e1, e2, e3 = n1 + beta * (n1 - u1), n2 + beta * (n2 - u2), n3 + beta * (n3 - u3)
+        u1, u2, u3 = n1, n2, n3
+    x = np.maximum(z - lt(u1, u2, u3), 0.0)
+    return (x, (u1, u2, u3)) if return_dual else x
+
+
+# ----------------------------------------------------------------------------
 # solver  (Alg. alg:prox-outer; eq. one-step)
 # ----------------------------------------------------------------------------
 def power_iteration(A: Callable, AT: Callable, v0: np.ndarray, n_iter: int) -> float:
@@ -378,17 +449,22 @@ def power_iteration(A: Callable, AT: Callable, v0: np.ndarray, n_iter: int) -> f
     return lam
 
 
-def objective(c, p, A: Callable, lam_tv: float, lam_l1: float) -> float:
-    """F(c) = 1/2 |A c - p|^2 + lam_tv TV(c) + lam_l1 |c|_1 (eq. one-step with
-    R3 without its TV(Sc) term; c is assumed nonnegative)."""
+def objective(c, p, A: Callable, lam_tv: float, lam_l1: float, lam_tvs: float = 0.0,
+              S: Optional[np.ndarray] = None) -> float:
+    """F(c) = 1/2 |A c - p|^2 + lam_tv TV(c) + lam_l1 |c|_1 + lam_tvs TV(S c)
+    (eq. one-step with R3 of eq. reg-tv-l1-one; c is assumed nonnegative)."""
     r = A(c) - p
-    return 0.5 * float(np.vdot(r, r)) + lam_tv * tv(c) + lam_l1 * float(np.abs(c).sum())
+    f = 0.5 * float(np.vdot(r, r)) + lam_tv * tv(c) + lam_l1 * float(np.abs(c).sum())
+    if lam_tvs > 0.0:
+        f += lam_tvs * tv(apply_S(c, S))
+    return f
 
 
 def fista(p, A: Callable, AT: Callable, alpha1: float, lam_tv: float, lam_l1: float,
           k1: int, k2: int, c_init=None, eps1: float = 0.0, eps2: float = 0.0,
           literal_momentum: bool = False, momentum: bool = True,
-          trace: Optional[list] = None, shape_c=None):
+          trace: Optional[list] = None, shape_c=None, lam_tvs: float = 0.0,
+          S: Optional[np.ndarray] = None):
     """Proximal gradient with FISTA momentum (Alg. alg:prox-outer):
         c_{k+1} = prox_{alpha1 w}(xi_k - alpha1 A^T (A xi_k - p))
         t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2
@@ -398,6 +474,8 @@ def fista(p, A: Callable, AT: Callable, alpha1: float, lam_tv: float, lam_l1: fl
     checked from the third iteration on; a zero eps disables its test).
     The gradient is formed as A^T (A xi - p), equal to the printed
     A^T A xi - A^T p.  momentum=False gives plain proximal gradient (ISTA).
+    With lam_tvs > 0 (the TV(S c) term, S given) the prox is the stacked dual
+    iteration prox_r3; otherwise the exact composition prox_w.
     Returns (c_final, iterations)."""
     if c_init is None:
         c = np.zeros(shape_c, dtype=np.float64)
@@ -409,7 +487,11 @@ def fista(p, A: Callable, AT: Callable, alpha1: float, lam_tv: float, lam_l1: fl
     it = 0
     for k in range(k1):
         g = AT(A(xi) - p)
-        c_next = prox_w(xi - alpha1 * g, alpha1 * lam_tv, alpha1 * lam_l1, k2, literal_momentum)
+        if lam_tvs > 0.0:
+            c_next = prox_r3(xi - alpha1 * g, S, alpha1 * lam_tv, alpha1 * lam_tvs,
+                             alpha1 * lam_l1, k2, literal_momentum)
+        else:
+            c_next = prox_w(xi - alpha1 * g, alpha1 * lam_tv, alpha1 * lam_l1, k2, literal_momentum)
         t, beta = fista_momentum(t, literal_momentum)
         if not momentum:
             beta = 0.0
@@ -418,7 +500,7 @@ def fista(p, A: Callable, AT: Callable, alpha1: float, lam_tv: float, lam_l1: fl
         stop = False
         f_now = None
         if eps1 > 0.0 or trace is not None:
-            f_now = objective(c_next, p, A, lam_tv, lam_l1)
+            f_now = objective(c_next, p, A, lam_tv, lam_l1, lam_tvs, S)
             if trace is not None:
                 trace.append(f_now)
         if k > 1:
