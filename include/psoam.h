@@ -140,6 +140,28 @@ size_t psoam_prox_tv_ws_bytes(const psoam_plan* plan);
 int psoam_prox_tv(const psoam_plan* plan, float* x, const float* z, float theta,
                   int32_t n_inner, int32_t nonneg, void* ws, void* stream);
 
+/* Bytes of workspace psoam_prox_r3 needs for this plan's grid and pulses. */
+size_t psoam_prox_r3_ws_bytes(const psoam_plan* plan);
+
+/* Proximal map of the full one-step regulariser (eq. reg-tv-l1-one):
+ *   theta_tv TV(x) + theta_tvs sum_k TV((S x)^k) + theta_l1 |x|_1, x >= 0,
+ * by n_inner steps of the paper's dual iteration on the stacked operator
+ * L = [grad; grad S; I] (Alg. alg:prox-inner, eq. prox-dual), duals rescaled
+ * per block so their boxes are theta_b, from zero duals:
+ *   w   = z - (grad^T e1 + S^T grad^T e2 + e3)
+ *   u1' = clip(e1 + s1 grad w), u2' = clip(e2 + s2 grad(S w)),
+ *   u3' = clip(e3 + s3 w),   e = u' + beta (u' - u)  (FISTA weights)
+ *   x   = max(z - (grad^T u1 + S^T grad^T u2 + u3), 0)
+ * with s_b = theta_b^2 / sum_b' theta_b'^2 m_b', m = {mu, mu max_v |S_v|^2,
+ * 1}, mu = eig_max(grad^T grad): the step 1/eig_max(L^T L) with eig_max
+ * replaced by that upper bound.  As printed, the duals are projected onto
+ * their boxes only and the sign constraint enters through the final clamp.
+ * x, z: device [S][Ny][Nx][Nz] float (may alias).  ws: device, at least
+ * psoam_prox_r3_ws_bytes(plan) bytes, 256-byte aligned.
+ * EINVAL: a threshold < 0 or not finite, n_inner < 0, null pointers. */
+int psoam_prox_r3(const psoam_plan* plan, float* x, const float* z, float theta_tv,
+                  float theta_tvs, float theta_l1, int32_t n_inner, void* ws, void* stream);
+
 /* Options of psoam_solve (Alg. alg:prox-outer and alg:prox-inner). */
 typedef struct {
   double lambda_tv;        /* weight of TV(c) (lambda_1 of eq. reg-tv-l1-one) */
@@ -154,6 +176,10 @@ typedef struct {
   int32_t warm_inner;      /* 0: cold dual start every outer step; 1: warm */
   const float* v0;         /* device [S][Ny][Nx][Nz] power start, or NULL (constant) */
   double* trace;           /* host, k1 doubles: F(c_{k+1}) per iteration, or NULL */
+  double lambda_tvs;       /* weight of sum_k TV((S c)^k) (lambda_3 of eq.
+                              reg-tv-l1-one); > 0 selects the full
+                              regulariser's prox (psoam_prox_r3; warm_inner
+                              does not apply to it) */
 } psoam_solve_opts;
 
 typedef struct {
@@ -164,11 +190,14 @@ typedef struct {
   double objective;        /* F(c) at exit if computed (trace or eps1), else NaN */
 } psoam_solve_stats;
 
-/* Solve eq. one-step without its TV(Sc) term:
+/* Solve eq. one-step:
  *   c = argmin_{c >= 0} 1/2 |A c - p|^2 + lambda_tv TV(c) + lambda_l1 |c|_1
+ *                       + lambda_tvs sum_k TV((S c)^k)
  * by Alg. alg:prox-outer: c_{k+1} = prox(xi_k - alpha1 A^T(A xi_k - p)),
- * xi_{k+1} = c_{k+1} + beta_k (c_{k+1} - c_k), the prox being the TV dual
- * iteration followed by max(. - alpha1 lambda_l1, 0).
+ * xi_{k+1} = c_{k+1} + beta_k (c_{k+1} - c_k).  With lambda_tvs = 0 the prox
+ * is the TV dual iteration followed by max(. - alpha1 lambda_l1, 0) (exact
+ * for that regulariser); with lambda_tvs > 0 it is psoam_prox_r3's stacked
+ * dual iteration at thresholds alpha1 * lambda.
  * p: device [K][Ny][Nx][Nt]; c: device [S][Ny][Nx][Nz], initial guess on
  * entry (zeros for the paper's start), result on exit.  st: host, may be
  * NULL.  Synchronises the stream when it needs host scalars (power

@@ -142,9 +142,24 @@ class Plan:
                                    1 if nonneg else 0, _ptr(ws), _stream(stream)))
         return x
 
+    def prox_r3(self, z, theta_tv: float, theta_tvs: float, theta_l1: float, n_inner: int,
+                x=None, ws=None, stream=None):
+        """Prox of the full regulariser (TV of c, TV of S c, l1, x >= 0)."""
+        torch = _torch()
+        _check_f32(z, self.c_shape, "z")
+        if x is None:
+            x = torch.empty_like(z)
+        nbytes = int(load().psoam_prox_r3_ws_bytes(self.handle))
+        if ws is None:
+            ws = torch.empty(nbytes // 4 + 64, dtype=torch.float32, device=z.device)
+        check(load().psoam_prox_r3(self.handle, _ptr(x), _ptr(z), float(theta_tv),
+                                   float(theta_tvs), float(theta_l1), int(n_inner), _ptr(ws),
+                                   _stream(stream)))
+        return x
+
     def solve(self, p, c=None, lambda_tv=0.0, lambda_l1=0.0, k1=100, k2=20, eps1=0.0, eps2=0.0,
               alpha1=0.0, n_power=30, literal_momentum=False, warm_inner=False, v0=None,
-              trace: bool = False, stream=None):
+              trace: bool = False, stream=None, lambda_tvs=0.0):
         """Returns (c, stats dict[, trace list])."""
         torch = _torch()
         _check_f32(p, self.y_shape, "p")
@@ -157,7 +172,8 @@ class Plan:
         o = _lib.SolveOpts(float(lambda_tv), float(lambda_l1), int(k1), int(k2), float(eps1),
                            float(eps2), float(alpha1), int(n_power), int(bool(literal_momentum)),
                            int(bool(warm_inner)), C.c_void_p(v0.data_ptr()) if v0 is not None else None,
-                           C.cast(tr, C.POINTER(C.c_double)) if tr is not None else None)
+                           C.cast(tr, C.POINTER(C.c_double)) if tr is not None else None,
+                           float(lambda_tvs))
         st = _lib.SolveStats()
         check(load().psoam_solve(self.handle, _ptr(p), _ptr(c), C.byref(o), C.byref(st),
                                  _stream(stream)))
@@ -180,7 +196,7 @@ def solve_batch(plans: Sequence[Plan], ps, cs, opts: Sequence[dict], stream=None
                                int(d.get("k1", 100)), int(d.get("k2", 20)),
                                float(d.get("eps1", 0.0)), float(d.get("eps2", 0.0)),
                                float(d.get("alpha1", 0.0)), int(d.get("n_power", 30)), 0, 0,
-                               None, None)
+                               None, None, float(d.get("lambda_tvs", 0.0)))
     st = (_lib.SolveStats * n)()
     check(load().psoam_solve_batch(n, hs, pp, cc, oo, st, _stream(stream)))
     return [dict(iterations=s.iterations, status=s.status, alpha1=s.alpha1,

@@ -27,7 +27,7 @@ class SolveOpts(C.Structure):
                 ("k1", C.c_int32), ("k2", C.c_int32),
                 ("eps1", C.c_double), ("eps2", C.c_double), ("alpha1", C.c_double),
                 ("n_power", C.c_int32), ("literal_momentum", C.c_int32), ("warm_inner", C.c_int32),
-                ("v0", C.c_void_p), ("trace", C.POINTER(C.c_double))]
+                ("v0", C.c_void_p), ("trace", C.POINTER(C.c_double)), ("lambda_tvs", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -52,6 +52,9 @@ EXPORTS = {
     "psoam_prox_l1": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_int32,
                                 C.c_void_p]),
     "psoam_prox_tv_ws_bytes": (C.c_size_t, [C.c_void_p]),
+    "psoam_prox_r3_ws_bytes": (C.c_size_t, [C.c_void_p]),
+    "psoam_prox_r3": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_float,
+                                C.c_float, C.c_int32, C.c_void_p, C.c_void_p]),
     "psoam_prox_tv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_int32,
                                 C.c_int32, C.c_void_p, C.c_void_p]),
     "psoam_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts),

@@ -124,6 +124,106 @@ int tv_prox_core(const psoam_plan* P, float* x, const float* z, float theta, int
   return PSOAM_OK;
 }
 
+double mu_tv(const psoam_geom& g) {
+  const int n[3] = {g.ny, g.nx, g.nz};
+  double mu = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double sn = std::sin(M_PI * (n[d] - 1) / (2.0 * n[d]));
+    mu += 4.0 * sn * sn;
+  }
+  return mu;
+}
+
+// floats of one set of duals of the full regulariser: u1 [3][S][V],
+// u2 [3][K][V], u3 [S][V], each 256-byte aligned
+size_t r3_set_floats(const psoam_plan* P) {
+  auto al = [](size_t n) { return (n + 63) / 64 * 64; };
+  const size_t sv = P->c_elems(), kv = (size_t)P->g.n_pulses * P->v_elems();
+  return al(3 * sv) + al(3 * kv) + al(sv);
+}
+
+struct R3Bufs {
+  float* u1[3];
+  float* u2[3];
+  float* u3[3];
+  float* w;
+};
+
+// three dual sets and w carved from a 256-byte aligned block
+R3Bufs r3_carve(const psoam_plan* P, void* base) {
+  auto al = [](size_t n) { return (n + 63) / 64 * 64; };
+  const size_t sv = P->c_elems(), kv = (size_t)P->g.n_pulses * P->v_elems();
+  float* p = (float*)base;
+  R3Bufs B;
+  for (int i = 0; i < 3; ++i) {
+    B.u1[i] = p;
+    p += al(3 * sv);
+    B.u2[i] = p;
+    p += al(3 * kv);
+    B.u3[i] = p;
+    p += al(sv);
+  }
+  B.w = p;
+  return B;
+}
+
+size_t r3_ws_bytes(const psoam_plan* P) {
+  return sizeof(float) * (3 * r3_set_floats(P) + (P->c_elems() + 63) / 64 * 64) + 256;
+}
+
+// x = prox of the full regulariser (TV of c, TV of S c, l1, then the final
+// clamp) by n_inner steps of the stacked dual iteration from zero duals;
+// th = {theta_tv, theta_tvs, theta_l1}.  Per-block steps theta_b^2 / sum_b'
+// theta_b'^2 m_b' with m = {mu, mu max_v |S_v|^2, 1} (an upper bound of
+// eig_max(L^T L)).
+int r3_prox_core(const psoam_plan* P, float* x, const float* z, const float th[3], int n_inner,
+                 const R3Bufs& B, bool literal, hipStream_t s) {
+  const double mu = mu_tv(P->g);
+  const double m[3] = {mu, mu * P->smax2, 1.0};
+  double bsum = 0.0;
+  for (int b = 0; b < 3; ++b) bsum += (double)th[b] * th[b] * m[b];
+  if (n_inner <= 0 || bsum == 0.0) {
+    PSOAM_HIP(launch_r3_w(P, x, z, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0f, 1, s));
+    return PSOAM_OK;
+  }
+  float step[3];
+  for (int b = 0; b < 3; ++b) step[b] = (float)((double)th[b] * th[b] / bsum);
+  double t = 1.0, beta_prev = 0.0;
+  int cur = -1, prev = -1;
+  for (int j = 0; j < n_inner; ++j) {
+    int nxt = 0;
+    while (nxt == cur || nxt == prev) ++nxt;
+    auto U1 = [&](int i) -> const float* { return i < 0 ? nullptr : B.u1[i]; };
+    auto U2 = [&](int i) -> const float* { return i < 0 ? nullptr : B.u2[i]; };
+    auto U3 = [&](int i) -> const float* { return i < 0 ? nullptr : B.u3[i]; };
+    PSOAM_HIP(launch_r3_w(P, B.w, z, U1(cur), U1(prev), U2(cur), U2(prev), U3(cur), U3(prev),
+                          (float)beta_prev, 0, s));
+    PSOAM_HIP(launch_r3_u(P, B.u1[nxt], B.u2[nxt], B.u3[nxt], B.w, U1(cur), U1(prev), U2(cur),
+                          U2(prev), U3(cur), U3(prev), (float)beta_prev, step, th, s));
+    double beta;
+    momentum_step(t, beta, literal);
+    beta_prev = beta;
+    prev = cur;
+    cur = nxt;
+  }
+  PSOAM_HIP(launch_r3_w(P, x, z, B.u1[cur], nullptr, B.u2[cur], nullptr, B.u3[cur], nullptr, 0.0f,
+                        1, s));
+  return PSOAM_OK;
+}
+
+int ensure_r3_ws(psoam_plan* P, R3Bufs& B) {
+  const size_t need = r3_ws_bytes(P);
+  if (P->r3_ws.bytes < need) {
+    if (P->r3_ws.base) PSOAM_HIP(hipFree(P->r3_ws.base));
+    P->r3_ws.base = nullptr;
+    P->r3_ws.bytes = 0;
+    PSOAM_HIP(hipMalloc(&P->r3_ws.base, need));
+    P->r3_ws.bytes = need;
+  }
+  B = r3_carve(P, (void*)(((uintptr_t)P->r3_ws.base + 255) & ~(uintptr_t)255));
+  return PSOAM_OK;
+}
+
 int check_plan(const psoam_plan* P) {
   if (!P) return fail(PSOAM_EINVAL, "plan is NULL");
   return PSOAM_OK;
@@ -136,11 +236,12 @@ int copy_scalars(const psoam_plan* P, double* host, int n, hipStream_t s) {
 }
 
 // data term 1/2 |A c - p|^2 + TV + l1 sums of c into d_scalars[4..6]
-int objective_terms(psoam_plan* P, const float* c, const float* p, hipStream_t s) {
+int objective_terms(psoam_plan* P, const float* c, const float* p, bool with_tvs, hipStream_t s) {
   PSOAM_HIP(launch_switch_fwd(P, c, s));
   PSOAM_HIP(launch_band(P, 1, nullptr, p, P->d_partial, s));
   PSOAM_HIP(launch_sum_partials(P->d_partial, band_partials(P, 1), P->d_scalars + 4, s));
   PSOAM_HIP(launch_tv_l1_sums(P, c, P->d_partial, P->d_scalars + 5, s));
+  if (with_tvs) PSOAM_HIP(launch_tvs_sum(P, c, P->d_partial, P->d_scalars + 7, s));
   return PSOAM_OK;
 }
 
@@ -152,6 +253,8 @@ int check_opts(const float* p, const float* c, const psoam_solve_opts* o) {
     return fail(PSOAM_EINVAL, "solve: invalid options (negative or non-finite)");
   if (o->alpha1 <= 0.0 && o->n_power < 1)
     return fail(PSOAM_EINVAL, "solve: n_power must be >= 1 when alpha1 is not given");
+  if (!(o->lambda_tvs >= 0.0) || !std::isfinite(o->lambda_tvs))
+    return fail(PSOAM_EINVAL, "solve: lambda_tvs must be finite and >= 0");
   return PSOAM_OK;
 }
 
@@ -225,6 +328,10 @@ int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o
   PSOAM_HIP(hipMemcpyAsync(B.cprev, c, sizeof(float) * sv, hipMemcpyDeviceToDevice, s));
   PSOAM_HIP(hipMemcpyAsync(B.xi, c, sizeof(float) * sv, hipMemcpyDeviceToDevice, s));
   const bool need_obj = o->eps1 > 0.0 || o->trace != nullptr;
+  const bool r3 = o->lambda_tvs > 0.0;
+  R3Bufs RB{};
+  if (r3 && (rc = ensure_r3_ws(P, RB))) return rc;
+  const float th3[3] = {th_tv, (float)(alpha1 * o->lambda_tvs), th_l1};
   double t = 1.0, f_prev = 0.0;
   bool have_f = false;
   const float* u_warm = nullptr;
@@ -235,10 +342,14 @@ int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o
     PSOAM_HIP(launch_band(P, 1, nullptr, p, P->d_partial, s));
     PSOAM_HIP(launch_band(P, 2, B.g, nullptr, nullptr, s));
     PSOAM_HIP(launch_axpby(B.zb, B.xi, B.g, 1.0f, (float)(-alpha1), sv, s));
-    // prox: TV dual iteration, then max(. - alpha1 lambda_l1, 0)
+    // prox: TV dual iteration, then max(. - alpha1 lambda_l1, 0); with the
+    // TV(S c) term the stacked dual iteration of the full regulariser
     const float* u_last = nullptr;
-    rc = tv_prox_core(P, B.cnext, B.zb, th_tv, o->k2, 2, th_l1, uw, B.w,
-                      o->warm_inner ? u_warm : nullptr, literal, &u_last, s);
+    if (r3)
+      rc = r3_prox_core(P, B.cnext, B.zb, th3, o->k2, RB, literal, s);
+    else
+      rc = tv_prox_core(P, B.cnext, B.zb, th_tv, o->k2, 2, th_l1, uw, B.w,
+                        o->warm_inner ? u_warm : nullptr, literal, &u_last, s);
     if (rc) return rc;
     if (o->warm_inner && u_last) {
       // keep the last dual iterate out of the next call's rotation
@@ -263,14 +374,15 @@ int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o
     bool stop = false;
     if (need_obj || o->eps2 > 0.0) {
       if (need_obj) {
-        rc = objective_terms(P, B.cprev, p, s);
+        rc = objective_terms(P, B.cprev, p, r3, s);
         if (rc) return rc;
       }
-      rc = copy_scalars(P, hs, 7, s);
+      rc = copy_scalars(P, hs, 8, s);
       if (rc) return rc;
       double f_now = 0.0;
       if (need_obj) {
         f_now = 0.5 * hs[4] + o->lambda_tv * hs[5] + o->lambda_l1 * hs[6];
+        if (r3) f_now += o->lambda_tvs * hs[7];
         if (!std::isfinite(f_now)) {
           stats.status = PSOAM_EDIVERGED;
           break;
@@ -311,6 +423,7 @@ struct BatchItem {
   psoam_solve_stats* st;
   psoam_solve_stats stats;
   SolveBufs B;
+  R3Bufs RB;
   double alpha1;
   int remaining;
 };
@@ -331,9 +444,13 @@ int enqueue_iteration(BatchItem& it, hipStream_t s) {
   PSOAM_HIP(launch_band(P, 2, B.g, nullptr, nullptr, s));
   PSOAM_HIP(launch_axpby(B.zb, B.xi, B.g, 1.0f, (float)(-it.alpha1), sv, s));
   float* uw[3] = {B.u[0], B.u[1], B.u[2]};
-  if (int rc = tv_prox_core(P, B.cnext, B.zb, th_tv, o->k2, 2, th_l1, uw, B.w, nullptr, literal,
-                            nullptr, s))
+  if (o->lambda_tvs > 0.0) {
+    const float th3[3] = {th_tv, (float)(it.alpha1 * o->lambda_tvs), th_l1};
+    if (int rc = r3_prox_core(P, B.cnext, B.zb, th3, o->k2, it.RB, literal, s)) return rc;
+  } else if (int rc = tv_prox_core(P, B.cnext, B.zb, th_tv, o->k2, 2, th_l1, uw, B.w, nullptr,
+                                   literal, nullptr, s)) {
     return rc;
+  }
   PSOAM_HIP(launch_momentum_dev(B.xi, B.cnext, B.cprev, P->d_scalars + 8, literal ? 1 : 0, sv, s));
   std::swap(B.cprev, B.cnext);  // cprev = c_{k+1}
   return PSOAM_OK;
@@ -533,6 +650,24 @@ int psoam_prox_tv(const psoam_plan* plan, float* x, const float* z, float theta,
                       nullptr, S(stream));
 }
 
+size_t psoam_prox_r3_ws_bytes(const psoam_plan* plan) {
+  if (!plan) return 0;
+  return r3_ws_bytes(plan);
+}
+
+int psoam_prox_r3(const psoam_plan* plan, float* x, const float* z, float theta_tv,
+                  float theta_tvs, float theta_l1, int32_t n_inner, void* ws, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!x || !z || !ws) return fail(PSOAM_EINVAL, "prox_r3: NULL argument");
+  const float th[3] = {theta_tv, theta_tvs, theta_l1};
+  for (float t : th)
+    if (!(t >= 0.0f) || !std::isfinite(t))
+      return fail(PSOAM_EINVAL, "prox_r3: thresholds must be finite and >= 0");
+  if (n_inner < 0) return fail(PSOAM_EINVAL, "prox_r3: n_inner < 0");
+  if (((uintptr_t)ws & 255) != 0) return fail(PSOAM_EINVAL, "prox_r3: ws must be 256-byte aligned");
+  return r3_prox_core(plan, x, z, th, n_inner, r3_carve(plan, ws), false, S(stream));
+}
+
 int psoam_solve(const psoam_plan* plan, const float* p, float* c, const psoam_solve_opts* o,
                 psoam_solve_stats* st, void* stream) {
   if (int rc = check_plan(plan)) return rc;
@@ -577,6 +712,9 @@ int psoam_solve_batch(int32_t n, const psoam_plan* const* plans, const float* co
     it.alpha1 = 0.0;
     it.remaining = 0;
     if (int rc = ensure_solve_ws(it.P, it.B)) return rc;
+    it.RB = R3Bufs{};
+    if (oi->lambda_tvs > 0.0)
+      if (int rc = ensure_r3_ws(it.P, it.RB)) return rc;
     items.push_back(it);
   }
   if (items.empty()) return PSOAM_OK;

@@ -115,6 +115,10 @@ struct psoam_plan {
   double* d_partial = nullptr;  // per-wave / per-block FP64 partial sums
   size_t n_partial = 0;
   double* d_scalars = nullptr;  // small FP64 results (reductions)
+  // duals of the full regulariser's prox (TV(S c) term), allocated on first use
+  psoam::Workspace r3_ws;
+  // max over voxels of the largest eigenvalue of S_v^T S_v (FP64, at creation)
+  double smax2 = 0.0;
   size_t y_elems() const { return (size_t)g.n_pulses * g.ny * g.nx * g.nt; }
   size_t c_elems() const { return (size_t)g.n_species * g.ny * g.nx * g.nz; }
   size_t v_elems() const { return (size_t)g.ny * g.nx * g.nz; }
@@ -176,5 +180,20 @@ size_t reduce_blocks(int64_t n);
 hipError_t launch_momentum_dev(float* xi, const float* c_next, const float* c_prev, double* tst,
                                int literal, int64_t n, hipStream_t s);
 hipError_t launch_set_double(double* p, double v, hipStream_t s);
+// full regulariser with the TV(S c) term (stacked dual iteration):
+//   w = z - (grad^T eta1 + S^T grad^T eta2 + eta3)   [clamp_out: max(., 0)]
+//   u1' = clip(eta1 + step0 grad w), u2' = clip(eta2 + step1 grad S w),
+//   u3' = clip(eta3 + step2 w)  at radii theta[0..2]
+// duals u1 [3][S][V], u2 [3][K][V], u3 [S][V]; eta from (current, previous)
+hipError_t launch_r3_w(const psoam_plan* P, float* out, const float* z, const float* u1c,
+                       const float* u1p, const float* u2c, const float* u2p, const float* u3c,
+                       const float* u3p, float beta, int clamp_out, hipStream_t s);
+hipError_t launch_r3_u(const psoam_plan* P, float* n1, float* n2, float* n3, const float* w,
+                       const float* u1c, const float* u1p, const float* u2c, const float* u2p,
+                       const float* u3c, const float* u3p, float beta, const float step[3],
+                       const float theta[3], hipStream_t s);
+// sum over pulses of the anisotropic TV of (S c)^k into out[0] (FP64)
+hipError_t launch_tvs_sum(const psoam_plan* P, const float* c, double* partial, double* out,
+                          hipStream_t s);
 
 }  // namespace psoam

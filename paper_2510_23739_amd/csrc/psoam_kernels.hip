@@ -1359,6 +1359,194 @@ hipError_t launch_tv_l1_sums(const psoam_plan* P, const float* c, double* partia
   return hipGetLastError();
 }
 
+// ---- full regulariser with the TV(S c) term: stacked dual iteration -------
+// Duals: u1 [3][S][V] (differences of c), u2 [3][K][V] (differences of each
+// pulse image S c), u3 [S][V] (the l1 block); eta = u_c + beta (u_c - u_p),
+// with u_c == null meaning eta = 0 and u_p == null meaning eta = u_c.
+__device__ __forceinline__ float eta3(const float* __restrict__ uc, const float* __restrict__ up,
+                                      float beta, int64_t i) {
+  if (!uc) return 0.0f;
+  const float a = uc[i];
+  return up ? a + beta * (a - up[i]) : a;
+}
+
+// w = z - (grad^T eta1 + S^T grad^T eta2 + eta3); with clamp_out the
+// algorithm's output max(., 0) instead.  One thread per voxel position, all
+// species.
+__global__ __launch_bounds__(256) void r3_w_kernel(
+    float* __restrict__ out, const float* __restrict__ z, const float* __restrict__ u1c,
+    const float* __restrict__ u1p, const float* __restrict__ u2c, const float* __restrict__ u2p,
+    const float* __restrict__ u3c, const float* __restrict__ u3p, float beta, SwitchParams sw,
+    const float* __restrict__ phi, const float* __restrict__ stab, int kp, Grid3 G, int clamp_out) {
+  const int64_t vol = (int64_t)G.ny * G.nx * G.nz;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= vol) return;
+  const int iz = (int)(v % G.nz);
+  const int ix = (int)((v / G.nz) % G.nx);
+  const int iy = (int)(v / ((int64_t)G.nz * G.nx));
+  const int idx[3] = {iy, ix, iz};
+  const int nd[3] = {G.ny, G.nx, G.nz};
+  const int64_t st[3] = {(int64_t)G.nx * G.nz, G.nz, 1};
+  const size_t col = (size_t)v - iz;
+  const int ns = sw.ns, nk = sw.nk;
+  float acc[kMaxSpecies];
+#pragma unroll
+  for (int s = 0; s < kMaxSpecies; ++s) acc[s] = 0.0f;
+  // S^T grad^T eta2, pulse by pulse
+  for (int k = 0; k < nk; ++k) {
+    float gt = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t base = ((int64_t)d * nk + k) * vol;
+      if (idx[d] > 0) gt += eta3(u2c, u2p, beta, base + v - st[d]);
+      if (idx[d] < nd[d] - 1) gt -= eta3(u2c, u2p, beta, base + v);
+    }
+    for (int s = 0; s < ns; ++s) acc[s] += coef_at(sw, phi, stab, kp, col, iz, k, s) * gt;
+  }
+  for (int s = 0; s < ns; ++s) {
+    float gt = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t base = ((int64_t)d * ns + s) * vol;
+      if (idx[d] > 0) gt += eta3(u1c, u1p, beta, base + v - st[d]);
+      if (idx[d] < nd[d] - 1) gt -= eta3(u1c, u1p, beta, base + v);
+    }
+    const int64_t i = (int64_t)s * vol + v;
+    const float r = z[i] - (gt + acc[s] + eta3(u3c, u3p, beta, i));
+    out[i] = clamp_out ? fmaxf(r, 0.0f) : r;
+  }
+}
+
+// u1' = clip(eta1 + s1 grad w), u2' = clip(eta2 + s2 grad (S w)),
+// u3' = clip(eta3 + s3 w), each at its own radius; one thread per voxel
+// position (forward differences, zero at the last index of each axis).
+__global__ __launch_bounds__(256) void r3_u_kernel(
+    float* __restrict__ n1, float* __restrict__ n2, float* __restrict__ n3,
+    const float* __restrict__ w, const float* __restrict__ u1c, const float* __restrict__ u1p,
+    const float* __restrict__ u2c, const float* __restrict__ u2p, const float* __restrict__ u3c,
+    const float* __restrict__ u3p, float beta, float s1, float s2, float s3, float th1, float th2,
+    float th3, SwitchParams sw, const float* __restrict__ phi, const float* __restrict__ stab,
+    int kp, Grid3 G) {
+  const int64_t vol = (int64_t)G.ny * G.nx * G.nz;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= vol) return;
+  const int iz = (int)(v % G.nz);
+  const int ix = (int)((v / G.nz) % G.nx);
+  const int iy = (int)(v / ((int64_t)G.nz * G.nx));
+  const bool fwd[3] = {iy < G.ny - 1, ix < G.nx - 1, iz < G.nz - 1};
+  const int64_t st[3] = {(int64_t)G.nx * G.nz, G.nz, 1};
+  const int ns = sw.ns, nk = sw.nk;
+  // w at v and at its three forward neighbours
+  float wv[4][kMaxSpecies];
+  for (int s = 0; s < ns; ++s) {
+    const int64_t i = (int64_t)s * vol + v;
+    wv[0][s] = w[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) wv[d + 1][s] = fwd[d] ? w[i + st[d]] : 0.0f;
+  }
+  for (int s = 0; s < ns; ++s) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t i = ((int64_t)d * ns + s) * vol + v;
+      const float g = fwd[d] ? wv[d + 1][s] - wv[0][s] : 0.0f;
+      n1[i] = fminf(fmaxf(eta3(u1c, u1p, beta, i) + s1 * g, -th1), th1);
+    }
+    const int64_t i = (int64_t)s * vol + v;
+    n3[i] = fminf(fmaxf(eta3(u3c, u3p, beta, i) + s3 * wv[0][s], -th3), th3);
+  }
+  // neighbour columns for the per-voxel switching coefficients
+  const size_t col0 = (size_t)v - iz;
+  const size_t colq[3] = {col0 + (size_t)st[0], col0 + (size_t)st[1], col0};
+  const int zq[3] = {iz, iz, iz + 1};
+  for (int k = 0; k < nk; ++k) {
+    float sw0 = 0.0f;
+    for (int s = 0; s < ns; ++s) sw0 += coef_at(sw, phi, stab, kp, col0, iz, k, s) * wv[0][s];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      float g = 0.0f;
+      if (fwd[d]) {
+        float swd = 0.0f;
+        for (int s = 0; s < ns; ++s)
+          swd += coef_at(sw, phi, stab, kp, colq[d], zq[d], k, s) * wv[d + 1][s];
+        g = swd - sw0;
+      }
+      const int64_t i = ((int64_t)d * nk + k) * vol + v;
+      n2[i] = fminf(fmaxf(eta3(u2c, u2p, beta, i) + s2 * g, -th2), th2);
+    }
+  }
+}
+
+// sum over pulses and positions of |differences of S c| (TV of S c), FP64
+// partial sums per block
+__global__ __launch_bounds__(256) void tvs_kernel(const float* __restrict__ c, SwitchParams sw,
+                                                  const float* __restrict__ phi,
+                                                  const float* __restrict__ stab, int kp, Grid3 G,
+                                                  double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int64_t vol = (int64_t)G.ny * G.nx * G.nz;
+  const int64_t st[3] = {(int64_t)G.nx * G.nz, G.nz, 1};
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < vol; v += stride) {
+    const int iz = (int)(v % G.nz);
+    const int ix = (int)((v / G.nz) % G.nx);
+    const int iy = (int)(v / ((int64_t)G.nz * G.nx));
+    const bool fwd[3] = {iy < G.ny - 1, ix < G.nx - 1, iz < G.nz - 1};
+    const size_t col0 = (size_t)v - iz;
+    const size_t colq[3] = {col0 + (size_t)st[0], col0 + (size_t)st[1], col0};
+    const int zq[3] = {iz, iz, iz + 1};
+    for (int k = 0; k < sw.nk; ++k) {
+      double b0 = 0.0;
+      for (int s = 0; s < sw.ns; ++s)
+        b0 += (double)coef_at(sw, phi, stab, kp, col0, iz, k, s) * (double)c[(int64_t)s * vol + v];
+      for (int d = 0; d < 3; ++d) {
+        if (!fwd[d]) continue;
+        double bd = 0.0;
+        for (int s = 0; s < sw.ns; ++s)
+          bd += (double)coef_at(sw, phi, stab, kp, colq[d], zq[d], k, s) *
+                (double)c[(int64_t)s * vol + v + st[d]];
+        acc += fabs(bd - b0);
+      }
+    }
+  }
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+hipError_t launch_r3_w(const psoam_plan* P, float* out, const float* z, const float* u1c,
+                       const float* u1p, const float* u2c, const float* u2p, const float* u3c,
+                       const float* u3p, float beta, int clamp_out, hipStream_t s) {
+  const Grid3 G = grid3(P);
+  const size_t vol = P->v_elems();
+  if (vol == 0) return hipSuccess;
+  hipLaunchKernelGGL(r3_w_kernel, dim3(blocks_for(vol)), dim3(256), 0, s, out, z, u1c, u1p, u2c,
+                     u2p, u3c, u3p, beta, P->sw, P->d_phi, P->d_stab, P->Kp, G, clamp_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_r3_u(const psoam_plan* P, float* n1, float* n2, float* n3, const float* w,
+                       const float* u1c, const float* u1p, const float* u2c, const float* u2p,
+                       const float* u3c, const float* u3p, float beta, const float step[3],
+                       const float theta[3], hipStream_t s) {
+  const Grid3 G = grid3(P);
+  const size_t vol = P->v_elems();
+  if (vol == 0) return hipSuccess;
+  hipLaunchKernelGGL(r3_u_kernel, dim3(blocks_for(vol)), dim3(256), 0, s, n1, n2, n3, w, u1c, u1p,
+                     u2c, u2p, u3c, u3p, beta, step[0], step[1], step[2], theta[0], theta[1],
+                     theta[2], P->sw, P->d_phi, P->d_stab, P->Kp, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_tvs_sum(const psoam_plan* P, const float* c, double* partial, double* out,
+                          hipStream_t s) {
+  const Grid3 G = grid3(P);
+  const size_t nb = reduce_blocks((int64_t)P->v_elems());
+  hipLaunchKernelGGL(tvs_kernel, dim3((unsigned)nb), dim3(256), 0, s, c, P->sw, P->d_phi,
+                     P->d_stab, P->Kp, G, partial);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void scale_rnorm_kernel(float* __restrict__ v,
                                                           const float* __restrict__ w,
                                                           const double* __restrict__ norm2,

@@ -412,6 +412,68 @@ static void free_table(BandTable& T) {
   T.d_rinfo = nullptr;
 }
 
+// Largest eigenvalue of a symmetric n x n matrix (n <= kMaxSpecies), cyclic
+// Jacobi rotations in FP64 until the off-diagonal part vanishes.
+static double sym_eig_max(double (&m)[kMaxSpecies][kMaxSpecies], int n) {
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += m[i][j] * m[i][j];
+        if (i != j) off += m[i][j] * m[i][j];
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        if (m[p][q] == 0.0) continue;
+        const double th = (m[q][q] - m[p][p]) / (2.0 * m[p][q]);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double a = m[k][p], b = m[k][q];
+          m[k][p] = c * a - sn * b;
+          m[k][q] = sn * a + c * b;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double a = m[p][k], b = m[q][k];
+          m[p][k] = c * a - sn * b;
+          m[q][k] = sn * a + c * b;
+        }
+      }
+  }
+  double e = m[0][0];
+  for (int i = 1; i < n; ++i) e = std::max(e, m[i][i]);
+  return e;
+}
+
+// max over the fluence values phi of eig_max(S^T S) for the switching block
+// S[k][s] = phi (a_s + b_s exp(-k phi^gamma / tau_s)) (FP64)
+static double switching_norm2(const psoam_geom& g, const psoam_species* sp, const float* phi,
+                              size_t nphi) {
+  const int ns = g.n_species, nk = g.n_pulses;
+  double best = 0.0;
+  std::vector<double> col((size_t)nk * ns);
+  float last = -1.0f;
+  for (size_t i = 0; i < nphi; ++i) {
+    if (phi[i] == last) continue;  // runs of equal fluence give the same block
+    last = phi[i];
+    const double ph = phi[i];
+    const double pg = sp->gamma == 0.0 ? 1.0 : std::pow(ph, sp->gamma);
+    for (int k = 0; k < nk; ++k)
+      for (int s = 0; s < ns; ++s)
+        col[(size_t)k * ns + s] = ph * (sp->a[s] + sp->b[s] * std::exp(-(double)k * pg / sp->tau[s]));
+    double m[kMaxSpecies][kMaxSpecies] = {};
+    for (int a = 0; a < ns; ++a)
+      for (int b = 0; b < ns; ++b) {
+        double acc = 0.0;
+        for (int k = 0; k < nk; ++k) acc += col[(size_t)k * ns + a] * col[(size_t)k * ns + b];
+        m[a][b] = acc;
+      }
+    best = std::max(best, sym_eig_max(m, ns));
+  }
+  return best;
+}
+
 void free_plan(psoam_plan* P) {
   if (!P) return;
   (void)hipSetDevice(P->device);
@@ -419,7 +481,7 @@ void free_plan(psoam_plan* P) {
   free_table(P->fwd);
   free_table(P->adj);
   void* bufs[] = {P->d_phi, P->d_stab, P->d_bq, P->d_bq_lo, P->d_rq, P->d_rq_lo,
-                  P->solve_ws.base, P->d_partial, P->d_scalars};
+                  P->solve_ws.base, P->r3_ws.base, P->d_partial, P->d_scalars};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete P;
@@ -497,6 +559,7 @@ int create_plan(const psoam_geom* gp, const psoam_species* sp, const float* phi,
     hipError_t _e = (call);                             \
     if (_e != hipSuccess) return bail(hip_fail(_e, #call)); \
   } while (0)
+  P->smax2 = switching_norm2(g, sp, phi, nphi);
   PLAN_HIP(hipMalloc(&P->d_phi, sizeof(float) * nphi));
   PLAN_HIP(hipMemcpy(P->d_phi, phi, sizeof(float) * nphi, hipMemcpyHostToDevice));
   if (!g.phi_per_voxel) {
