@@ -1393,6 +1393,7 @@ __global__ __launch_bounds__(256) void r3_w_kernel(
 #pragma unroll
   for (int s = 0; s < kMaxSpecies; ++s) acc[s] = 0.0f;
   // S^T grad^T eta2, pulse by pulse
+#pragma unroll 2
   for (int k = 0; k < nk; ++k) {
     float gt = 0.0f;
 #pragma unroll
@@ -1454,22 +1455,35 @@ __global__ __launch_bounds__(256) void r3_u_kernel(
     const int64_t i = (int64_t)s * vol + v;
     n3[i] = fminf(fmaxf(eta3(u3c, u3p, beta, i) + s3 * wv[0][s], -th3), th3);
   }
-  // neighbour columns for the per-voxel switching coefficients
+  // (S w)^k at v and its forward neighbours; with a per-depth table the y and
+  // x neighbours share v's coefficients and the z neighbour uses depth z + 1
   const size_t col0 = (size_t)v - iz;
   const size_t colq[3] = {col0 + (size_t)st[0], col0 + (size_t)st[1], col0};
   const int zq[3] = {iz, iz, iz + 1};
+  const int zn = fwd[2] ? iz + 1 : iz;
+#pragma unroll 2
   for (int k = 0; k < nk; ++k) {
-    float sw0 = 0.0f;
-    for (int s = 0; s < ns; ++s) sw0 += coef_at(sw, phi, stab, kp, col0, iz, k, s) * wv[0][s];
+    float sq[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (stab) {
+      for (int s = 0; s < ns; ++s) {
+        const float c0 = stab[((size_t)iz * kp + k) * ns + s];
+        const float c1 = stab[((size_t)zn * kp + k) * ns + s];
+        sq[0] += c0 * wv[0][s];
+        sq[1] += c0 * wv[1][s];
+        sq[2] += c0 * wv[2][s];
+        sq[3] += c1 * wv[3][s];
+      }
+    } else {
+      for (int s = 0; s < ns; ++s) {
+        sq[0] += scoef(sw, phi[col0 + iz], k, s) * wv[0][s];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (fwd[d]) sq[d + 1] += scoef(sw, phi[colq[d] + zq[d]], k, s) * wv[d + 1][s];
+      }
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      float g = 0.0f;
-      if (fwd[d]) {
-        float swd = 0.0f;
-        for (int s = 0; s < ns; ++s)
-          swd += coef_at(sw, phi, stab, kp, colq[d], zq[d], k, s) * wv[d + 1][s];
-        g = swd - sw0;
-      }
+      const float g = fwd[d] ? sq[d + 1] - sq[0] : 0.0f;
       const int64_t i = ((int64_t)d * nk + k) * vol + v;
       n2[i] = fminf(fmaxf(eta3(u2c, u2p, beta, i) + s2 * g, -th2), th2);
     }

@@ -75,6 +75,8 @@ def main():
         out["HT_ms"] = timed(lambda: plan.band_only(1, g))
     if "tv" in what:
         out["prox_tv_k20_ms"] = timed(lambda: plan.prox_tv(c, 0.01, 20, x=g))
+    if "r3" in what:
+        out["prox_r3_k20_ms"] = timed(lambda: plan.prox_r3(c, 0.01, 0.005, 0.01, 20, x=g))
     print(json.dumps(out), flush=True)
 
 
