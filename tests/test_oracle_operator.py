@@ -163,3 +163,29 @@ def test_power_iteration_matches_lapack():
     # identity operator: eigenvalue 1
     lam1 = oracle.power_iteration(lambda v: v, lambda v: v, v0, 3)
     assert lam1 == pytest.approx(1.0, rel=1e-14)
+
+
+@pytest.mark.parametrize("per_voxel", [True, False])
+def test_separable_switching_factorisation(per_voxel):
+    """With a fluence-independent rate (gamma = 0) the switching block is
+    S_v[k][s] = phi_v T[k][s], T[k][s] = a_s + b_s exp(-k / tau_s), so
+    A c = sum_s T[:, s] (x) H(phi c_s) and (A^T y)_s = phi H^T(sum_k T[k][s] y_k):
+    the contraction runs over S volumes instead of K (checked against the
+    general A and A^T built from the full switching matrix)."""
+    rng = np.random.default_rng(4)
+    ns, ny, nx, nz, K, nt, f = 3, 4, 5, 4, 6, 12, 3
+    t0, taps = synth.random_table(nz, f, nt, 4, rng, t0_lo=-2, t0_hi=nt - 1)
+    phi = rng.uniform(0.3, 1.0, size=(ny, nx, nz) if per_voxel else nz)
+    sp = synth.species(ns, gamma=0.0)
+    S = oracle.switching_matrix(phi, sp.a, sp.b, sp.tau, sp.gamma, K)
+    T = np.asarray(sp.a)[None, :] + np.asarray(sp.b)[None, :] * np.exp(
+        -np.arange(K)[:, None] / np.asarray(sp.tau)[None, :])
+    c = rng.standard_normal((ns, ny, nx, nz))
+    y = rng.standard_normal((K, ny, nx, nt))
+    ph = np.broadcast_to(phi, (ny, nx, nz))
+    h = oracle.apply_H(c * ph[None], t0, taps, nt)                  # [S][Ny][Nx][Nt]
+    np.testing.assert_allclose(np.einsum("ks,syxt->kyxt", T, h),
+                               oracle.apply_A(c, S, t0, taps, nt), rtol=1e-12, atol=1e-14)
+    rt = np.einsum("ks,kyxt->syxt", T, y)
+    g = ph[None] * oracle.apply_HT(rt, t0, taps, nz)
+    np.testing.assert_allclose(g, oracle.apply_AT(y, S, t0, taps, nz), rtol=1e-12, atol=1e-14)
