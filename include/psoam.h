@@ -61,6 +61,13 @@ typedef struct {
   int32_t nt;              /* samples per A-scan */
   int32_t f;               /* lateral footprint of the impulse response, odd; R = (f-1)/2 */
   int32_t phi_per_voxel;   /* 0: phi is [Nz]; 1: phi is [Ny][Nx][Nz] */
+  int32_t separable;       /* 1: separable fast form (requires gamma = 0): with a
+                              fluence-independent rate S_v[k][s] = phi_v T[k][s],
+                              T[k][s] = a_s + b_s exp(-k / tau_s), so
+                              A c = sum_s T[:, s] (x) H(phi c_s) and the
+                              contraction runs over the S species instead of
+                              the K pulses; results equal the general form's
+                              up to rounding.  0: general form. */
 } psoam_geom;
 
 /* Photo-physics of the species (Sec. 2.1.1, eqs. epsilon, final-H):

@@ -47,13 +47,13 @@ class Plan:
 
     def __init__(self, nx: int, ny: int, nz: int, n_pulses: int, nt: int, f: int,
                  phi: np.ndarray, species, t0: np.ndarray, taps: np.ndarray,
-                 prec: str = "fp32", stream=None):
+                 prec: str = "fp32", stream=None, separable: bool = False):
         lib = load()
         species_a, species_b, species_tau = list(species.a), list(species.b), list(species.tau)
         ns = len(species_a)
         phi = np.ascontiguousarray(phi, dtype=np.float32)
         per_voxel = 1 if phi.ndim == 3 else 0
-        self.geom = _lib.Geom(nx, ny, nz, ns, n_pulses, nt, f, per_voxel)
+        self.geom = _lib.Geom(nx, ny, nz, ns, n_pulses, nt, f, per_voxel, 1 if separable else 0)
         sp = _lib.Species()
         for s in range(ns):
             sp.a[s], sp.b[s], sp.tau[s] = species_a[s], species_b[s], species_tau[s]
@@ -76,9 +76,9 @@ class Plan:
         self.y_shape = (n_pulses, ny, nx, nt)
 
     @classmethod
-    def from_config(cls, cfg, phi, species, t0, taps, prec="fp32", stream=None):
+    def from_config(cls, cfg, phi, species, t0, taps, prec="fp32", stream=None, separable=False):
         return cls(cfg.nx, cfg.ny, cfg.nz, cfg.n_pulses, cfg.nt, cfg.f, phi, species, t0, taps,
-                   prec=prec, stream=stream)
+                   prec=prec, stream=stream, separable=separable)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -14,7 +14,7 @@ PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16_split": 3, "fp16_split": 4}
 class Geom(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("n_species", C.c_int32), ("n_pulses", C.c_int32), ("nt", C.c_int32),
-                ("f", C.c_int32), ("phi_per_voxel", C.c_int32)]
+                ("f", C.c_int32), ("phi_per_voxel", C.c_int32), ("separable", C.c_int32)]
 
 
 class Species(C.Structure):

@@ -62,7 +62,8 @@ int ensure_solve_ws(psoam_plan* P, SolveBufs& B) {
     PSOAM_HIP(hipMalloc(&P->solve_ws.base, need));
     P->solve_ws.bytes = need;
   }
-  const size_t np = std::max(band_partials(P, 1), (size_t)2 * reduce_blocks((int64_t)sv));
+  size_t np = std::max(band_partials(P->inner ? P->inner : P, 1), (size_t)2 * reduce_blocks((int64_t)sv));
+  if (P->inner) np = std::max({np, sep_blocks(P), reduce_blocks((int64_t)P->y_elems())});
   if (P->n_partial < np) {
     if (P->d_partial) PSOAM_HIP(hipFree(P->d_partial));
     P->d_partial = nullptr;
@@ -235,11 +236,48 @@ int copy_scalars(const psoam_plan* P, double* host, int n, hipStream_t s) {
   return PSOAM_OK;
 }
 
-// data term 1/2 |A c - p|^2 + TV + l1 sums of c into d_scalars[4..6]
+// Per-solve preparation of the measurements: the separable form works with
+// q = T^T p (d_q) and |p|^2 (d_scalars[9]) instead of p itself.
+int prepare_p(psoam_plan* P, const float* p, hipStream_t s) {
+  if (!P->inner) return PSOAM_OK;
+  PSOAM_HIP(launch_sep_contract(P, P->d_q, p, s));
+  PSOAM_HIP(launch_dot(p, p, (int64_t)P->y_elems(), P->d_partial, P->d_scalars + 9, s));
+  return PSOAM_OK;
+}
+
+// g = A^T (A x - p), or A^T A x when p is null.  General form: S and H with
+// the residual in H's epilogue, then H^T with S^T.  Separable form: h = H of
+// phi x_s over the S species, A^T (A x - p) = phi H^T(G h - T^T p) with
+// G = T^T T (prepare_p has put T^T p in d_q), never forming A x itself.
+int enqueue_grad(psoam_plan* P, const float* x, const float* p, float* g, hipStream_t s) {
+  if (P->inner) {
+    PSOAM_HIP(launch_switch_fwd(P->inner, x, s));
+    PSOAM_HIP(launch_band(P->inner, 0, P->d_h, nullptr, nullptr, s));
+    PSOAM_HIP(launch_sep_residual(P, P->d_rt, P->d_h, p ? P->d_q : nullptr, nullptr, s));
+    PSOAM_HIP(launch_pack_r(P->inner, P->d_rt, s));
+    PSOAM_HIP(launch_band(P->inner, 2, g, nullptr, nullptr, s));
+  } else {
+    PSOAM_HIP(launch_switch_fwd(P, x, s));
+    PSOAM_HIP(launch_band(P, 1, nullptr, p, P->d_partial, s));
+    PSOAM_HIP(launch_band(P, 2, g, nullptr, nullptr, s));
+  }
+  return PSOAM_OK;
+}
+
+// data term |A c - p|^2 into d_scalars[4] (separable: h^T G h - 2 h^T q, to
+// which |p|^2 in d_scalars[9] is added on the host), TV and l1 sums of c into
+// d_scalars[5..6], TV(S c) into d_scalars[7]
 int objective_terms(psoam_plan* P, const float* c, const float* p, bool with_tvs, hipStream_t s) {
-  PSOAM_HIP(launch_switch_fwd(P, c, s));
-  PSOAM_HIP(launch_band(P, 1, nullptr, p, P->d_partial, s));
-  PSOAM_HIP(launch_sum_partials(P->d_partial, band_partials(P, 1), P->d_scalars + 4, s));
+  if (P->inner) {
+    PSOAM_HIP(launch_switch_fwd(P->inner, c, s));
+    PSOAM_HIP(launch_band(P->inner, 0, P->d_h, nullptr, nullptr, s));
+    PSOAM_HIP(launch_sep_residual(P, P->d_rt, P->d_h, P->d_q, P->d_partial, s));
+    PSOAM_HIP(launch_sum_partials(P->d_partial, sep_blocks(P), P->d_scalars + 4, s));
+  } else {
+    PSOAM_HIP(launch_switch_fwd(P, c, s));
+    PSOAM_HIP(launch_band(P, 1, nullptr, p, P->d_partial, s));
+    PSOAM_HIP(launch_sum_partials(P->d_partial, band_partials(P, 1), P->d_scalars + 4, s));
+  }
   PSOAM_HIP(launch_tv_l1_sums(P, c, P->d_partial, P->d_scalars + 5, s));
   if (with_tvs) PSOAM_HIP(launch_tvs_sum(P, c, P->d_partial, P->d_scalars + 7, s));
   return PSOAM_OK;
@@ -272,9 +310,7 @@ int enqueue_power(psoam_plan* P, SolveBufs& B, const psoam_solve_opts* o, hipStr
   PSOAM_HIP(launch_dot(w, w, sv, P->d_partial, P->d_scalars + 1, s));
   PSOAM_HIP(launch_scale_by_rnorm(v, w, P->d_scalars + 1, sv, s));
   for (int i = 0; i < o->n_power; ++i) {
-    PSOAM_HIP(launch_switch_fwd(P, v, s));
-    PSOAM_HIP(launch_band(P, 1, nullptr, nullptr, P->d_partial, s));
-    PSOAM_HIP(launch_band(P, 2, w, nullptr, nullptr, s));
+    if (int rc = enqueue_grad(P, v, nullptr, w, s)) return rc;
     PSOAM_HIP(launch_dot(v, w, sv, P->d_partial, P->d_scalars + 0, s));
     PSOAM_HIP(launch_dot(w, w, sv, P->d_partial, P->d_scalars + 1, s));
     PSOAM_HIP(launch_scale_by_rnorm(v, w, P->d_scalars + 1, sv, s));
@@ -336,11 +372,10 @@ int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o
   bool have_f = false;
   const float* u_warm = nullptr;
   float* uw[3] = {B.u[0], B.u[1], B.u[2]};
+  if ((rc = prepare_p(P, p, s))) return rc;
   for (int k = 0; k < o->k1; ++k) {
     // gradient A^T (A xi - p)
-    PSOAM_HIP(launch_switch_fwd(P, B.xi, s));
-    PSOAM_HIP(launch_band(P, 1, nullptr, p, P->d_partial, s));
-    PSOAM_HIP(launch_band(P, 2, B.g, nullptr, nullptr, s));
+    if ((rc = enqueue_grad(P, B.xi, p, B.g, s))) return rc;
     PSOAM_HIP(launch_axpby(B.zb, B.xi, B.g, 1.0f, (float)(-alpha1), sv, s));
     // prox: TV dual iteration, then max(. - alpha1 lambda_l1, 0); with the
     // TV(S c) term the stacked dual iteration of the full regulariser
@@ -377,11 +412,12 @@ int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o
         rc = objective_terms(P, B.cprev, p, r3, s);
         if (rc) return rc;
       }
-      rc = copy_scalars(P, hs, 8, s);
+      rc = copy_scalars(P, hs, 10, s);
       if (rc) return rc;
       double f_now = 0.0;
       if (need_obj) {
-        f_now = 0.5 * hs[4] + o->lambda_tv * hs[5] + o->lambda_l1 * hs[6];
+        const double data = P->inner ? hs[4] + hs[9] : hs[4];
+        f_now = 0.5 * data + o->lambda_tv * hs[5] + o->lambda_l1 * hs[6];
         if (r3) f_now += o->lambda_tvs * hs[7];
         if (!std::isfinite(f_now)) {
           stats.status = PSOAM_EDIVERGED;
@@ -439,9 +475,7 @@ int enqueue_iteration(BatchItem& it, hipStream_t s) {
   const bool literal = o->literal_momentum != 0;
   const float th_tv = (float)(it.alpha1 * o->lambda_tv);
   const float th_l1 = (float)(it.alpha1 * o->lambda_l1);
-  PSOAM_HIP(launch_switch_fwd(P, B.xi, s));
-  PSOAM_HIP(launch_band(P, 1, nullptr, it.p, P->d_partial, s));
-  PSOAM_HIP(launch_band(P, 2, B.g, nullptr, nullptr, s));
+  if (int rc = enqueue_grad(P, B.xi, it.p, B.g, s)) return rc;
   PSOAM_HIP(launch_axpby(B.zb, B.xi, B.g, 1.0f, (float)(-it.alpha1), sv, s));
   float* uw[3] = {B.u[0], B.u[1], B.u[2]};
   if (o->lambda_tvs > 0.0) {
@@ -506,6 +540,7 @@ int solve_batch_graph(std::vector<BatchItem>& items, hipStream_t caller) {
     PSOAM_HIP(hipMemcpyAsync(it.B.cprev, it.c, sizeof(float) * sv, hipMemcpyDeviceToDevice, bs.ss[i]));
     PSOAM_HIP(hipMemcpyAsync(it.B.xi, it.c, sizeof(float) * sv, hipMemcpyDeviceToDevice, bs.ss[i]));
     PSOAM_HIP(launch_set_double(it.P->d_scalars + 8, 1.0, bs.ss[i]));
+    if (int rc = prepare_p(it.P, it.p, bs.ss[i])) return rc;
     it.remaining = it.o->k1;
     PSOAM_HIP(hipEventRecord(bs.ev[i], bs.ss[i]));
     PSOAM_HIP(hipStreamWaitEvent(bs.cs, bs.ev[i], 0));
@@ -602,6 +637,12 @@ int psoam_apply_A(const psoam_plan* plan, const float* c, float* y, void* stream
   if (int rc = check_plan(plan)) return rc;
   if (!c || !y) return fail(PSOAM_EINVAL, "apply_A: NULL argument");
   if (((uintptr_t)y & 15) != 0) return fail(PSOAM_EINVAL, "apply_A: y must be 16-byte aligned");
+  if (plan->inner) {
+    PSOAM_HIP(launch_switch_fwd(plan->inner, c, S(stream)));
+    PSOAM_HIP(launch_band(plan->inner, 0, plan->d_h, nullptr, nullptr, S(stream)));
+    PSOAM_HIP(launch_sep_expand(plan, y, plan->d_h, S(stream)));
+    return PSOAM_OK;
+  }
   PSOAM_HIP(launch_switch_fwd(plan, c, S(stream)));
   PSOAM_HIP(launch_band(plan, 0, y, nullptr, nullptr, S(stream)));
   return PSOAM_OK;
@@ -610,6 +651,12 @@ int psoam_apply_A(const psoam_plan* plan, const float* c, float* y, void* stream
 int psoam_apply_AT(const psoam_plan* plan, const float* y, float* c, void* stream) {
   if (int rc = check_plan(plan)) return rc;
   if (!c || !y) return fail(PSOAM_EINVAL, "apply_AT: NULL argument");
+  if (plan->inner) {
+    PSOAM_HIP(launch_sep_contract(plan, plan->d_rt, y, S(stream)));
+    PSOAM_HIP(launch_pack_r(plan->inner, plan->d_rt, S(stream)));
+    PSOAM_HIP(launch_band(plan->inner, 2, c, nullptr, nullptr, S(stream)));
+    return PSOAM_OK;
+  }
   PSOAM_HIP(launch_pack_r(plan, y, S(stream)));
   PSOAM_HIP(launch_band(plan, 2, c, nullptr, nullptr, S(stream)));
   return PSOAM_OK;
@@ -723,6 +770,7 @@ int psoam_solve_batch(int32_t n, const psoam_plan* const* plans, const float* co
 
 int psoam_plan_stats(const psoam_plan* plan, psoam_plan_info* info) {
   if (!plan || !info) return fail(PSOAM_EINVAL, "plan_stats: NULL argument");
+  if (plan->inner) plan = plan->inner;  // the contraction of the separable form
   const bool half = plan->prec != PSOAM_FP32;
   const int64_t tile = half ? 16 * 32 : 16 * 4;
   const BandTable* T[2] = {&plan->fwd, &plan->adj};
@@ -744,6 +792,7 @@ int psoam_band_only(const psoam_plan* plan, int32_t dir, float* out, void* strea
   if (!out || (dir != 0 && dir != 1)) return fail(PSOAM_EINVAL, "band_only: bad argument");
   if (dir == 0 && ((uintptr_t)out & 15) != 0)
     return fail(PSOAM_EINVAL, "band_only: y must be 16-byte aligned");
+  if (plan->inner) plan = plan->inner;  // the contraction of the separable form (S columns)
   PSOAM_HIP(launch_band(plan, dir == 0 ? 0 : 2, out, nullptr, nullptr, S(stream)));
   return PSOAM_OK;
 }

@@ -39,6 +39,7 @@ struct SwitchParams {
   int ns;
   int nk;
   int per_voxel;
+  int diag;        // 1: S_v[k][s] = phi_v if k == s else 0 (inner plan of the separable form)
   float gamma;
   float a[kMaxSpecies];
   float b[kMaxSpecies];
@@ -119,6 +120,17 @@ struct psoam_plan {
   psoam::Workspace r3_ws;
   // max over voxels of the largest eigenvalue of S_v^T S_v (FP64, at creation)
   double smax2 = 0.0;
+  // separable switching (fluence-independent rate): S_v[k][s] = phi_v T[k][s].
+  // The contraction runs in `inner`, a plan over the S species with
+  // S'_v = phi_v I; this plan keeps the true switching data for the prox
+  // steps and owns the small pulse-expansion buffers.
+  psoam_plan* inner = nullptr;
+  float* d_T = nullptr;       // [K][S]
+  float sep_g[psoam::kMaxSpecies * psoam::kMaxSpecies] = {};  // G = T^T T, [S][S]
+  float* d_h = nullptr;       // [S][Ny][Nx][Nt]: H of phi c_s
+  float* d_rt = nullptr;      // [S][Ny][Nx][Nt]: T^T r, the adjoint's input
+  float* d_q = nullptr;       // [S][Ny][Nx][Nt]: T^T p of the current solve
+  size_t h_elems() const { return (size_t)g.n_species * g.ny * g.nx * g.nt; }
   size_t y_elems() const { return (size_t)g.n_pulses * g.ny * g.nx * g.nt; }
   size_t c_elems() const { return (size_t)g.n_species * g.ny * g.nx * g.nz; }
   size_t v_elems() const { return (size_t)g.ny * g.nx * g.nz; }
@@ -192,6 +204,16 @@ hipError_t launch_r3_u(const psoam_plan* P, float* n1, float* n2, float* n3, con
                        const float* u1c, const float* u1p, const float* u2c, const float* u2p,
                        const float* u3c, const float* u3p, float beta, const float step[3],
                        const float theta[3], hipStream_t s);
+// separable form (n = Ny*Nx*Nt elements per volume; T [K][S] on the device):
+//   y[k] = sum_s T[k][s] h[s]           (expand)
+//   out[s] = sum_k T[k][s] y[k]         (contract)
+//   rt[s] = sum_s' G[s][s'] h[s'] - q[s] (q may be null); with partial, the
+//           FP64 block sums of sum_s h[s] (rt[s] - q[s]) = h^T G h - 2 h^T q
+hipError_t launch_sep_expand(const psoam_plan* P, float* y, const float* h, hipStream_t s);
+hipError_t launch_sep_contract(const psoam_plan* P, float* out, const float* y, hipStream_t s);
+hipError_t launch_sep_residual(const psoam_plan* P, float* rt, const float* h, const float* q,
+                               double* partial, hipStream_t s);
+size_t sep_blocks(const psoam_plan* P);
 // sum over pulses of the anisotropic TV of (S c)^k into out[0] (FP64)
 hipError_t launch_tvs_sum(const psoam_plan* P, const float* c, double* partial, double* out,
                           hipStream_t s);

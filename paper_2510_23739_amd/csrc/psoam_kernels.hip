@@ -66,6 +66,7 @@ struct Half<PSOAM_FP16> {
 // per pulse as phi^gamma / tau)
 // --------------------------------------------------------------------------
 __device__ __forceinline__ float scoef(const SwitchParams& sw, float phi, int k, int s) {
+  if (sw.diag) return k == s ? phi : 0.0f;
   const float pg = (sw.gamma == 0.0f) ? 1.0f : powf(phi, sw.gamma);
   return phi * (sw.a[s] + sw.b[s] * expf(-(float)k * pg * sw.inv_tau[s]));
 }
@@ -1558,6 +1559,98 @@ hipError_t launch_tvs_sum(const psoam_plan* P, const float* c, double* partial, 
   hipLaunchKernelGGL(tvs_kernel, dim3((unsigned)nb), dim3(256), 0, s, c, P->sw, P->d_phi,
                      P->d_stab, P->Kp, G, partial);
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out);
+  return hipGetLastError();
+}
+
+// ---- separable switching: pulse expansion and contraction -----------------
+struct SepG {
+  float g[kMaxSpecies * kMaxSpecies];
+};
+
+__global__ __launch_bounds__(256) void sep_expand_kernel(float* __restrict__ y,
+                                                         const float* __restrict__ h,
+                                                         const float* __restrict__ T, int ns,
+                                                         int nk, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    float hv[kMaxSpecies];
+    for (int s = 0; s < ns; ++s) hv[s] = h[(int64_t)s * n + i];
+    for (int k = 0; k < nk; ++k) {
+      float acc = 0.0f;
+      for (int s = 0; s < ns; ++s) acc += T[k * ns + s] * hv[s];
+      y[(int64_t)k * n + i] = acc;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void sep_contract_kernel(float* __restrict__ out,
+                                                           const float* __restrict__ y,
+                                                           const float* __restrict__ T, int ns,
+                                                           int nk, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    float acc[kMaxSpecies];
+    for (int s = 0; s < ns; ++s) acc[s] = 0.0f;
+    for (int k = 0; k < nk; ++k) {
+      const float v = y[(int64_t)k * n + i];
+      for (int s = 0; s < ns; ++s) acc[s] += T[k * ns + s] * v;
+    }
+    for (int s = 0; s < ns; ++s) out[(int64_t)s * n + i] = acc[s];
+  }
+}
+
+__global__ __launch_bounds__(256) void sep_residual_kernel(float* __restrict__ rt,
+                                                           const float* __restrict__ h,
+                                                           const float* __restrict__ q, SepG G,
+                                                           int ns, int64_t n,
+                                                           double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    float hv[kMaxSpecies];
+    for (int s = 0; s < ns; ++s) hv[s] = h[(int64_t)s * n + i];
+    for (int s = 0; s < ns; ++s) {
+      float r = 0.0f;
+      for (int t = 0; t < ns; ++t) r += G.g[s * kMaxSpecies + t] * hv[t];
+      const float qv = q ? q[(int64_t)s * n + i] : 0.0f;
+      r -= qv;
+      rt[(int64_t)s * n + i] = r;
+      acc += (double)hv[s] * ((double)r - (double)qv);
+    }
+  }
+  if (partial) {
+    const double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+  }
+}
+
+size_t sep_blocks(const psoam_plan* P) {
+  return reduce_blocks((int64_t)((size_t)P->g.ny * P->g.nx * P->g.nt));
+}
+
+hipError_t launch_sep_expand(const psoam_plan* P, float* y, const float* h, hipStream_t s) {
+  const int64_t n = (int64_t)P->g.ny * P->g.nx * P->g.nt;
+  hipLaunchKernelGGL(sep_expand_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0, s, y, h,
+                     (const float*)P->d_T, P->g.n_species, P->g.n_pulses, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_contract(const psoam_plan* P, float* out, const float* y, hipStream_t s) {
+  const int64_t n = (int64_t)P->g.ny * P->g.nx * P->g.nt;
+  hipLaunchKernelGGL(sep_contract_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0, s, out, y,
+                     (const float*)P->d_T, P->g.n_species, P->g.n_pulses, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_residual(const psoam_plan* P, float* rt, const float* h, const float* q,
+                               double* partial, hipStream_t s) {
+  const int64_t n = (int64_t)P->g.ny * P->g.nx * P->g.nt;
+  SepG G;
+  for (int i = 0; i < kMaxSpecies * kMaxSpecies; ++i) G.g[i] = P->sep_g[i];
+  const size_t nb = partial ? sep_blocks(P) : blocks_for((size_t)n);
+  hipLaunchKernelGGL(sep_residual_kernel, dim3((unsigned)nb), dim3(256), 0, s, rt, h, q, G,
+                     P->g.n_species, n, partial);
   return hipGetLastError();
 }
 

@@ -478,6 +478,10 @@ void free_plan(psoam_plan* P) {
   if (!P) return;
   (void)hipSetDevice(P->device);
   (void)hipDeviceSynchronize();
+  if (P->inner) free_plan(P->inner);
+  P->inner = nullptr;
+  for (void* b : {(void*)P->d_T, (void*)P->d_h, (void*)P->d_rt, (void*)P->d_q})
+    if (b) (void)hipFree(b);
   free_table(P->fwd);
   free_table(P->adj);
   void* bufs[] = {P->d_phi, P->d_stab, P->d_bq, P->d_bq_lo, P->d_rq, P->d_rq_lo,
@@ -487,9 +491,12 @@ void free_plan(psoam_plan* P) {
   delete P;
 }
 
-int create_plan(const psoam_geom* gp, const psoam_species* sp, const float* phi,
-                const int32_t* t0, const float* taps, int32_t sir_w, int32_t prec,
-                hipStream_t stream, psoam_plan** out) {
+// diag: switching S'_v = phi_v I over the species (inner plan of the
+// separable form); build_op = false skips the contraction tables and operand
+// buffers (outer plan of the separable form).
+static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const float* phi,
+                            const int32_t* t0, const float* taps, int32_t sir_w, int32_t prec,
+                            hipStream_t stream, int diag, bool build_op, psoam_plan** out) {
   if (!out) return fail(PSOAM_EINVAL, "plan_create: out is NULL");
   *out = nullptr;
   if (!gp || !sp || !phi || !t0 || !taps) return fail(PSOAM_EINVAL, "plan_create: NULL argument");
@@ -543,6 +550,7 @@ int create_plan(const psoam_geom* gp, const psoam_species* sp, const float* phi,
   sw.ns = g.n_species;
   sw.nk = g.n_pulses;
   sw.per_voxel = g.phi_per_voxel;
+  sw.diag = diag;
   sw.gamma = (float)sp->gamma;
   for (int s = 0; s < kMaxSpecies; ++s) {
     sw.a[s] = s < g.n_species ? (float)sp->a[s] : 0.0f;
@@ -571,10 +579,16 @@ int create_plan(const psoam_geom* gp, const psoam_species* sp, const float* phi,
           const double ph = phi[z];
           const double pg = sp->gamma == 0.0 ? 1.0 : std::pow(ph, sp->gamma);
           st[((size_t)z * P->Kp + k) * g.n_species + s] =
-              (float)(ph * (sp->a[s] + sp->b[s] * std::exp(-(double)k * pg / sp->tau[s])));
+              diag ? (k == s ? (float)ph : 0.0f)
+                   : (float)(ph * (sp->a[s] + sp->b[s] * std::exp(-(double)k * pg / sp->tau[s])));
         }
     PLAN_HIP(hipMalloc(&P->d_stab, sizeof(float) * st.size()));
     PLAN_HIP(hipMemcpy(P->d_stab, st.data(), sizeof(float) * st.size(), hipMemcpyHostToDevice));
+  }
+  if (!build_op) {
+    PLAN_HIP(hipStreamSynchronize(stream));
+    *out = P;
+    return PSOAM_OK;
   }
   const size_t esz = half ? 2 : 4;
   P->bq_bytes = (size_t)P->Yp * P->Xp * P->ps_b * esz;
@@ -595,6 +609,54 @@ int create_plan(const psoam_geom* gp, const psoam_species* sp, const float* phi,
   if (rc != PSOAM_OK) return bail(rc);
   PLAN_HIP(hipStreamSynchronize(stream));
 #undef PLAN_HIP
+  *out = P;
+  return PSOAM_OK;
+}
+
+int create_plan(const psoam_geom* gp, const psoam_species* sp, const float* phi,
+                const int32_t* t0, const float* taps, int32_t sir_w, int32_t prec,
+                hipStream_t stream, psoam_plan** out) {
+  if (!out) return fail(PSOAM_EINVAL, "plan_create: out is NULL");
+  *out = nullptr;
+  if (!gp || !sp) return fail(PSOAM_EINVAL, "plan_create: NULL argument");
+  if (gp->separable != 0 && gp->separable != 1)
+    return fail(PSOAM_EINVAL, "plan_create: separable must be 0 or 1");
+  if (!gp->separable) return create_plan_impl(gp, sp, phi, t0, taps, sir_w, prec, stream, 0, true, out);
+  if (sp->gamma != 0.0)
+    return fail(PSOAM_EINVAL, "plan_create: the separable form needs a fluence-independent rate (gamma = 0)");
+  // outer plan: geometry with K pulses and the true switching data (prox steps)
+  psoam_plan* P = nullptr;
+  if (int rc = create_plan_impl(gp, sp, phi, t0, taps, sir_w, prec, stream, 0, false, &P)) return rc;
+  // inner plan: the contraction over the S species with S'_v = phi_v I
+  psoam_geom gi = *gp;
+  gi.n_pulses = gp->n_species;
+  gi.separable = 0;
+  if (int rc = create_plan_impl(&gi, sp, phi, t0, taps, sir_w, prec, stream, 1, true, &P->inner)) {
+    free_plan(P);
+    return rc;
+  }
+  const int K = gp->n_pulses, ns = gp->n_species;
+  std::vector<double> T((size_t)K * ns);
+  for (int k = 0; k < K; ++k)
+    for (int s = 0; s < ns; ++s) T[(size_t)k * ns + s] = sp->a[s] + sp->b[s] * std::exp(-(double)k / sp->tau[s]);
+  std::vector<float> Tf(T.begin(), T.end());
+  for (int a = 0; a < ns; ++a)
+    for (int b = 0; b < ns; ++b) {
+      double acc = 0.0;
+      for (int k = 0; k < K; ++k) acc += T[(size_t)k * ns + a] * T[(size_t)k * ns + b];
+      P->sep_g[a * kMaxSpecies + b] = (float)acc;
+    }
+  auto bail = [&](hipError_t e, const char* what) {
+    free_plan(P);
+    return hip_fail(e, what);
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&P->d_T, sizeof(float) * Tf.size())) != hipSuccess) return bail(e, "hipMalloc T");
+  if ((e = hipMemcpy(P->d_T, Tf.data(), sizeof(float) * Tf.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(e, "hipMemcpy T");
+  float** bufs[] = {&P->d_h, &P->d_rt, &P->d_q};
+  for (float** b : bufs)
+    if ((e = hipMalloc(b, sizeof(float) * P->h_elems())) != hipSuccess) return bail(e, "hipMalloc separable buffers");
   *out = P;
   return PSOAM_OK;
 }

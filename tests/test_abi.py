@@ -83,6 +83,15 @@ def test_validation_before_device_work(lib):
                                  t0.ctypes.data_as(C.c_void_p),
                                  taps_bad.ctypes.data_as(C.c_void_p), 4, 0, None,
                                  C.byref(out)) == _lib.EINVAL
+    # the separable form needs gamma = 0 and a 0/1 flag
+    sep = _lib.Geom(4, 4, 4, 2, 3, 8, 3, 0, 1)
+    sp.gamma = 1.0
+    assert lib.psoam_plan_create(*args(sep)) == _lib.EINVAL
+    assert b"gamma" in lib.psoam_last_error()
+    sp.gamma = 0.0
+    assert lib.psoam_plan_create(*args(_lib.Geom(4, 4, 4, 2, 3, 8, 3, 0, 2))) == _lib.EINVAL
+    assert lib.psoam_prox_r3(None, None, None, 0.1, 0.1, 0.1, 3, None, None) == _lib.EINVAL
+    assert lib.psoam_prox_r3_ws_bytes(None) == 0
     # entry points on a NULL plan / bad sizes
     assert lib.psoam_apply_A(None, None, None, None) == _lib.EINVAL
     assert lib.psoam_apply_AT(None, None, None, None) == _lib.EINVAL
