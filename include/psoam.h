@@ -214,6 +214,34 @@ typedef struct {
 int psoam_solve(const psoam_plan* plan, const float* p, float* c, const psoam_solve_opts* o,
                 psoam_solve_stats* st, void* stream);
 
+/* ---- the two-step method (the paper's comparison, Sec. two-step approach) --
+ * Step 1, acoustic inversion (eq. acoustic-inverse with R1 of eq. reg-tv):
+ *   b = argmin_{b >= 0} 1/2 |H b - p|^2 + nu_1 sum_k TV(b^k)
+ * with a plan from psoam_plan_create_acoustic and psoam_solve (lambda_tv =
+ * nu_1, lambda_l1 = 0): the plan's "species" are the K pulse volumes and its
+ * switching is the identity.  Step 2, unmixing (eq. unmixing with R2 of eq.
+ * reg-unmixing):
+ *   c = argmin_{c >= 0} 1/2 |S c - b|^2 + nu_2 |c|_1 + nu_3 TV(c)
+ * with psoam_unmix on a plan of the species (the same FISTA and prox as
+ * psoam_solve, with the per-voxel S in place of A). */
+
+/* Plan of the acoustic operator alone on K pulse volumes: y[k] = H b[k],
+ * b: device [K][Ny][Nx][Nz] as the "concentrations" of psoam_apply_A /
+ * psoam_solve, y: [K][Ny][Nx][Nt].  g->n_species, phi_per_voxel and
+ * separable are ignored (set to K, 0, 0).  Same table arguments and errors
+ * as psoam_plan_create. */
+int psoam_plan_create_acoustic(const psoam_geom* g, const int32_t* sir_t0, const float* sir_taps,
+                               int32_t sir_w, int32_t prec, void* stream, psoam_plan** out);
+
+/* Unmixing step: psoam_solve's iteration with the per-voxel switching S of
+ * `plan` in place of A: gradient S^T (S xi - b) voxel by voxel, the same
+ * prox (lambda_tv = nu_3 on TV(c), lambda_l1 = nu_2), step alpha1 or the
+ * power-iteration estimate of eig_max(S^T S).  b: device [K][Ny][Nx][Nz]
+ * (e.g. step 1's result); c: device [S][Ny][Nx][Nz], initial guess in,
+ * result out.  lambda_tvs must be 0.  Errors as psoam_solve. */
+int psoam_unmix(const psoam_plan* plan, const float* b, float* c, const psoam_solve_opts* o,
+                psoam_solve_stats* st, void* stream);
+
 /* n independent solves (plans of different shapes and pulse counts allowed)
  * as one batch, the batched family of reconstructions of the same method
  * (Alg. alg:prox-outer per problem).  Arrays of length n; opts/st arrays

@@ -74,6 +74,32 @@ class Plan:
         self.prec = prec
         self.c_shape = (ns, ny, nx, nz)
         self.y_shape = (n_pulses, ny, nx, nt)
+        self.b_shape = (n_pulses, ny, nx, nz)
+
+    @classmethod
+    def acoustic(cls, nx: int, ny: int, nz: int, n_pulses: int, nt: int, f: int,
+                 t0: np.ndarray, taps: np.ndarray, prec: str = "fp32", stream=None):
+        """Plan of H alone on n_pulses volumes (first step of the two-step
+        method): its "concentrations" are the pulse volumes b [K][Ny][Nx][Nz]."""
+        self = cls.__new__(cls)
+        self._h = None
+        self.geom = _lib.Geom(nx, ny, nz, n_pulses, n_pulses, nt, f, 0, 0)
+        self._t0 = np.ascontiguousarray(t0, dtype=np.int32)
+        self._taps = np.ascontiguousarray(taps, dtype=np.float32)
+        if self._t0.shape != (nz, f, f) or self._taps.shape[:3] != (nz, f, f):
+            raise ValueError("impulse-response table shape does not match (nz, f, f)")
+        handle = C.c_void_p()
+        check(load().psoam_plan_create_acoustic(C.byref(self.geom),
+                                                self._t0.ctypes.data_as(C.c_void_p),
+                                                self._taps.ctypes.data_as(C.c_void_p),
+                                                int(self._taps.shape[3]), PREC[prec],
+                                                _stream(stream), C.byref(handle)))
+        self._h = handle
+        self.prec = prec
+        self.c_shape = (n_pulses, ny, nx, nz)
+        self.y_shape = (n_pulses, ny, nx, nt)
+        self.b_shape = self.c_shape
+        return self
 
     @classmethod
     def from_config(cls, cfg, phi, species, t0, taps, prec="fp32", stream=None, separable=False):
@@ -161,8 +187,23 @@ class Plan:
               alpha1=0.0, n_power=30, literal_momentum=False, warm_inner=False, v0=None,
               trace: bool = False, stream=None, lambda_tvs=0.0):
         """Returns (c, stats dict[, trace list])."""
-        torch = _torch()
         _check_f32(p, self.y_shape, "p")
+        return self._iterate("psoam_solve", p, c, lambda_tv, lambda_l1, k1, k2, eps1, eps2,
+                             alpha1, n_power, literal_momentum, warm_inner, v0, trace, stream,
+                             lambda_tvs)
+
+    def unmix(self, b, c=None, lambda_tv=0.0, lambda_l1=0.0, k1=100, k2=20, eps1=0.0, eps2=0.0,
+              alpha1=0.0, n_power=30, literal_momentum=False, v0=None, trace: bool = False,
+              stream=None):
+        """Unmixing step of the two-step method (psoam_unmix): c from pulse
+        volumes b [K][Ny][Nx][Nz].  Returns (c, stats dict[, trace list])."""
+        _check_f32(b, self.b_shape, "b")
+        return self._iterate("psoam_unmix", b, c, lambda_tv, lambda_l1, k1, k2, eps1, eps2,
+                             alpha1, n_power, literal_momentum, False, v0, trace, stream, 0.0)
+
+    def _iterate(self, fn, p, c, lambda_tv, lambda_l1, k1, k2, eps1, eps2, alpha1, n_power,
+                 literal_momentum, warm_inner, v0, trace, stream, lambda_tvs):
+        torch = _torch()
         if c is None:
             c = torch.zeros(self.c_shape, dtype=torch.float32, device=p.device)
         _check_f32(c, self.c_shape, "c")
@@ -175,13 +216,26 @@ class Plan:
                            C.cast(tr, C.POINTER(C.c_double)) if tr is not None else None,
                            float(lambda_tvs))
         st = _lib.SolveStats()
-        check(load().psoam_solve(self.handle, _ptr(p), _ptr(c), C.byref(o), C.byref(st),
-                                 _stream(stream)))
+        check(getattr(load(), fn)(self.handle, _ptr(p), _ptr(c), C.byref(o), C.byref(st),
+                                  _stream(stream)))
         stats = dict(iterations=st.iterations, status=st.status, alpha1=st.alpha1,
                      lambda_max=st.lambda_max, objective=st.objective)
         if trace:
             return c, stats, [tr[i] for i in range(st.iterations)]
         return c, stats
+
+
+def two_step(acoustic: Plan, species: Plan, p, nu1: float, nu2: float, nu3: float,
+             k1_acoustic: int = 100, k1_unmix: int = 100, k2: int = 20, alpha_acoustic=0.0,
+             alpha_unmix=0.0, n_power: int = 30, stream=None):
+    """The paper's two-step method: b = psoam_solve on the acoustic plan with
+    TV weight nu1 (nonnegative pulse images), then c = psoam_unmix on the
+    species plan with l1 weight nu2 and TV weight nu3.  Returns (b, c, stats)."""
+    b, st1 = acoustic.solve(p, lambda_tv=nu1, k1=k1_acoustic, k2=k2, alpha1=alpha_acoustic,
+                            n_power=n_power, stream=stream)
+    c, st2 = species.unmix(b, lambda_tv=nu3, lambda_l1=nu2, k1=k1_unmix, k2=k2,
+                           alpha1=alpha_unmix, n_power=n_power, stream=stream)
+    return b, c, (st1, st2)
 
 
 def solve_batch(plans: Sequence[Plan], ps, cs, opts: Sequence[dict], stream=None):

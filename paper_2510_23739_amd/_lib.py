@@ -46,6 +46,10 @@ EXPORTS = {
                                     C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
     "psoam_plan_destroy": (C.c_int, [C.c_void_p]),
+    "psoam_plan_create_acoustic": (C.c_int, [C.POINTER(Geom), C.c_void_p, C.c_void_p, C.c_int32,
+                                             C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "psoam_unmix": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts),
+                              C.POINTER(SolveStats), C.c_void_p]),
     "psoam_plan_geom": (C.c_int, [C.c_void_p, C.POINTER(Geom)]),
     "psoam_apply_A": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "psoam_apply_AT": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

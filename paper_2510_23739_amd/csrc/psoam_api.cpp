@@ -17,6 +17,8 @@ int create_plan(const psoam_geom* gp, const psoam_species* sp, const float* phi,
                 const int32_t* t0, const float* taps, int32_t sir_w, int32_t prec,
                 hipStream_t stream, psoam_plan** out);
 void free_plan(psoam_plan* P);
+int create_plan_acoustic(const psoam_geom* gp, const int32_t* t0, const float* taps,
+                         int32_t sir_w, int32_t prec, hipStream_t stream, psoam_plan** out);
 const char* last_error_cstr();
 
 namespace {
@@ -238,8 +240,13 @@ int copy_scalars(const psoam_plan* P, double* host, int n, hipStream_t s) {
 
 // Per-solve preparation of the measurements: the separable form works with
 // q = T^T p (d_q) and |p|^2 (d_scalars[9]) instead of p itself.
-int prepare_p(psoam_plan* P, const float* p, hipStream_t s) {
-  if (!P->inner) return PSOAM_OK;
+// Operator of a solve: the forward model A = H S (eq. one-step) or, for the
+// unmixing step of the two-step method, the per-voxel switching S alone
+// (eq. unmixing).
+enum Op { kOpA = 0, kOpUnmix = 1 };
+
+int prepare_p(psoam_plan* P, int op, const float* p, hipStream_t s) {
+  if (op != kOpA || !P->inner) return PSOAM_OK;
   PSOAM_HIP(launch_sep_contract(P, P->d_q, p, s));
   PSOAM_HIP(launch_dot(p, p, (int64_t)P->y_elems(), P->d_partial, P->d_scalars + 9, s));
   return PSOAM_OK;
@@ -249,8 +256,10 @@ int prepare_p(psoam_plan* P, const float* p, hipStream_t s) {
 // the residual in H's epilogue, then H^T with S^T.  Separable form: h = H of
 // phi x_s over the S species, A^T (A x - p) = phi H^T(G h - T^T p) with
 // G = T^T T (prepare_p has put T^T p in d_q), never forming A x itself.
-int enqueue_grad(psoam_plan* P, const float* x, const float* p, float* g, hipStream_t s) {
-  if (P->inner) {
+int enqueue_grad(psoam_plan* P, int op, const float* x, const float* p, float* g, hipStream_t s) {
+  if (op == kOpUnmix) {
+    PSOAM_HIP(launch_unmix_grad(P, g, x, p, nullptr, s));
+  } else if (P->inner) {
     PSOAM_HIP(launch_switch_fwd(P->inner, x, s));
     PSOAM_HIP(launch_band(P->inner, 0, P->d_h, nullptr, nullptr, s));
     PSOAM_HIP(launch_sep_residual(P, P->d_rt, P->d_h, p ? P->d_q : nullptr, nullptr, s));
@@ -267,8 +276,12 @@ int enqueue_grad(psoam_plan* P, const float* x, const float* p, float* g, hipStr
 // data term |A c - p|^2 into d_scalars[4] (separable: h^T G h - 2 h^T q, to
 // which |p|^2 in d_scalars[9] is added on the host), TV and l1 sums of c into
 // d_scalars[5..6], TV(S c) into d_scalars[7]
-int objective_terms(psoam_plan* P, const float* c, const float* p, bool with_tvs, hipStream_t s) {
-  if (P->inner) {
+int objective_terms(psoam_plan* P, int op, const float* c, const float* p, bool with_tvs,
+                    float* scratch, hipStream_t s) {
+  if (op == kOpUnmix) {
+    PSOAM_HIP(launch_unmix_grad(P, scratch, c, p, P->d_partial, s));
+    PSOAM_HIP(launch_sum_partials(P->d_partial, unmix_blocks(P), P->d_scalars + 4, s));
+  } else if (P->inner) {
     PSOAM_HIP(launch_switch_fwd(P->inner, c, s));
     PSOAM_HIP(launch_band(P->inner, 0, P->d_h, nullptr, nullptr, s));
     PSOAM_HIP(launch_sep_residual(P, P->d_rt, P->d_h, P->d_q, P->d_partial, s));
@@ -298,7 +311,7 @@ int check_opts(const float* p, const float* c, const psoam_solve_opts* o) {
 
 // power iteration on A^T A with FP64 norms, enqueued only: v <- v0/|v0|;
 // n_power times [w = A^T A v; lam = <v, w>; v = w/|w|]; lam in d_scalars[0]
-int enqueue_power(psoam_plan* P, SolveBufs& B, const psoam_solve_opts* o, hipStream_t s) {
+int enqueue_power(psoam_plan* P, int op, SolveBufs& B, const psoam_solve_opts* o, hipStream_t s) {
   const int64_t sv = (int64_t)P->c_elems();
   float* v = B.zb;
   float* w = B.g;
@@ -310,7 +323,7 @@ int enqueue_power(psoam_plan* P, SolveBufs& B, const psoam_solve_opts* o, hipStr
   PSOAM_HIP(launch_dot(w, w, sv, P->d_partial, P->d_scalars + 1, s));
   PSOAM_HIP(launch_scale_by_rnorm(v, w, P->d_scalars + 1, sv, s));
   for (int i = 0; i < o->n_power; ++i) {
-    if (int rc = enqueue_grad(P, v, nullptr, w, s)) return rc;
+    if (int rc = enqueue_grad(P, op, v, nullptr, w, s)) return rc;
     PSOAM_HIP(launch_dot(v, w, sv, P->d_partial, P->d_scalars + 0, s));
     PSOAM_HIP(launch_dot(w, w, sv, P->d_partial, P->d_scalars + 1, s));
     PSOAM_HIP(launch_scale_by_rnorm(v, w, P->d_scalars + 1, sv, s));
@@ -343,9 +356,11 @@ psoam_solve_stats fresh_stats() {
   return stats;
 }
 
-int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o,
+int solve_one(psoam_plan* P, int op, const float* p, float* c, const psoam_solve_opts* o,
               psoam_solve_stats* st, hipStream_t s) {
   if (int rc = check_opts(p, c, o)) return rc;
+  if (op == kOpUnmix && o->lambda_tvs != 0.0)
+    return fail(PSOAM_EINVAL, "unmix: the unmixing regulariser has no TV(S c) term (lambda_tvs must be 0)");
   SolveBufs B;
   int rc = ensure_solve_ws(P, B);
   if (rc) return rc;
@@ -354,7 +369,7 @@ int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o
   psoam_solve_stats stats = fresh_stats();
   double alpha1 = o->alpha1;
   if (alpha1 <= 0.0) {
-    if ((rc = enqueue_power(P, B, o, s))) return rc;
+    if ((rc = enqueue_power(P, op, B, o, s))) return rc;
     if ((rc = finish_power(P, stats, st, alpha1, s))) return rc;
   }
   stats.alpha1 = alpha1;
@@ -372,10 +387,10 @@ int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o
   bool have_f = false;
   const float* u_warm = nullptr;
   float* uw[3] = {B.u[0], B.u[1], B.u[2]};
-  if ((rc = prepare_p(P, p, s))) return rc;
+  if ((rc = prepare_p(P, op, p, s))) return rc;
   for (int k = 0; k < o->k1; ++k) {
     // gradient A^T (A xi - p)
-    if ((rc = enqueue_grad(P, B.xi, p, B.g, s))) return rc;
+    if ((rc = enqueue_grad(P, op, B.xi, p, B.g, s))) return rc;
     PSOAM_HIP(launch_axpby(B.zb, B.xi, B.g, 1.0f, (float)(-alpha1), sv, s));
     // prox: TV dual iteration, then max(. - alpha1 lambda_l1, 0); with the
     // TV(S c) term the stacked dual iteration of the full regulariser
@@ -409,14 +424,14 @@ int solve_one(psoam_plan* P, const float* p, float* c, const psoam_solve_opts* o
     bool stop = false;
     if (need_obj || o->eps2 > 0.0) {
       if (need_obj) {
-        rc = objective_terms(P, B.cprev, p, r3, s);
+        rc = objective_terms(P, op, B.cprev, p, r3, B.w, s);
         if (rc) return rc;
       }
       rc = copy_scalars(P, hs, 10, s);
       if (rc) return rc;
       double f_now = 0.0;
       if (need_obj) {
-        const double data = P->inner ? hs[4] + hs[9] : hs[4];
+        const double data = (op == kOpA && P->inner) ? hs[4] + hs[9] : hs[4];
         f_now = 0.5 * data + o->lambda_tv * hs[5] + o->lambda_l1 * hs[6];
         if (r3) f_now += o->lambda_tvs * hs[7];
         if (!std::isfinite(f_now)) {
@@ -475,7 +490,7 @@ int enqueue_iteration(BatchItem& it, hipStream_t s) {
   const bool literal = o->literal_momentum != 0;
   const float th_tv = (float)(it.alpha1 * o->lambda_tv);
   const float th_l1 = (float)(it.alpha1 * o->lambda_l1);
-  if (int rc = enqueue_grad(P, B.xi, it.p, B.g, s)) return rc;
+  if (int rc = enqueue_grad(P, kOpA, B.xi, it.p, B.g, s)) return rc;
   PSOAM_HIP(launch_axpby(B.zb, B.xi, B.g, 1.0f, (float)(-it.alpha1), sv, s));
   float* uw[3] = {B.u[0], B.u[1], B.u[2]};
   if (o->lambda_tvs > 0.0) {
@@ -529,7 +544,7 @@ int solve_batch_graph(std::vector<BatchItem>& items, hipStream_t caller) {
     BatchItem& it = items[i];
     it.alpha1 = it.o->alpha1;
     if (it.alpha1 <= 0.0)
-      if (int rc = enqueue_power(it.P, it.B, it.o, bs.ss[i])) return rc;
+      if (int rc = enqueue_power(it.P, kOpA, it.B, it.o, bs.ss[i])) return rc;
   }
   for (int i = 0; i < n; ++i) {
     BatchItem& it = items[i];
@@ -540,7 +555,7 @@ int solve_batch_graph(std::vector<BatchItem>& items, hipStream_t caller) {
     PSOAM_HIP(hipMemcpyAsync(it.B.cprev, it.c, sizeof(float) * sv, hipMemcpyDeviceToDevice, bs.ss[i]));
     PSOAM_HIP(hipMemcpyAsync(it.B.xi, it.c, sizeof(float) * sv, hipMemcpyDeviceToDevice, bs.ss[i]));
     PSOAM_HIP(launch_set_double(it.P->d_scalars + 8, 1.0, bs.ss[i]));
-    if (int rc = prepare_p(it.P, it.p, bs.ss[i])) return rc;
+    if (int rc = prepare_p(it.P, kOpA, it.p, bs.ss[i])) return rc;
     it.remaining = it.o->k1;
     PSOAM_HIP(hipEventRecord(bs.ev[i], bs.ss[i]));
     PSOAM_HIP(hipStreamWaitEvent(bs.cs, bs.ev[i], 0));
@@ -715,10 +730,21 @@ int psoam_prox_r3(const psoam_plan* plan, float* x, const float* z, float theta_
   return r3_prox_core(plan, x, z, th, n_inner, r3_carve(plan, ws), false, S(stream));
 }
 
+int psoam_plan_create_acoustic(const psoam_geom* g, const int32_t* sir_t0, const float* sir_taps,
+                               int32_t sir_w, int32_t prec, void* stream, psoam_plan** out) {
+  return create_plan_acoustic(g, sir_t0, sir_taps, sir_w, prec, S(stream), out);
+}
+
+int psoam_unmix(const psoam_plan* plan, const float* b, float* c, const psoam_solve_opts* o,
+                psoam_solve_stats* st, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  return solve_one(const_cast<psoam_plan*>(plan), kOpUnmix, b, c, o, st, S(stream));
+}
+
 int psoam_solve(const psoam_plan* plan, const float* p, float* c, const psoam_solve_opts* o,
                 psoam_solve_stats* st, void* stream) {
   if (int rc = check_plan(plan)) return rc;
-  return solve_one(const_cast<psoam_plan*>(plan), p, c, o, st, S(stream));
+  return solve_one(const_cast<psoam_plan*>(plan), kOpA, p, c, o, st, S(stream));
 }
 
 int psoam_solve_batch(int32_t n, const psoam_plan* const* plans, const float* const* p,
@@ -744,7 +770,7 @@ int psoam_solve_batch(int32_t n, const psoam_plan* const* plans, const float* co
     const bool graphable = distinct && oi->eps1 == 0.0 && oi->eps2 == 0.0 && !oi->trace &&
                            !oi->warm_inner && oi->k1 >= 2;
     if (!graphable) {
-      const int rc = solve_one(const_cast<psoam_plan*>(plans[i]), p[i], c[i], oi,
+      const int rc = solve_one(const_cast<psoam_plan*>(plans[i]), kOpA, p[i], c[i], oi,
                                st ? &st[i] : nullptr, S(stream));
       if (rc) return rc;
       continue;

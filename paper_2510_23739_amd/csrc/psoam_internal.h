@@ -214,6 +214,11 @@ hipError_t launch_sep_contract(const psoam_plan* P, float* out, const float* y, 
 hipError_t launch_sep_residual(const psoam_plan* P, float* rt, const float* h, const float* q,
                                double* partial, hipStream_t s);
 size_t sep_blocks(const psoam_plan* P);
+// per-voxel unmixing gradient g = S^T (S x - b) (b may be null), optional FP64
+// partial sums of |S x - b|^2 over unmix_blocks(P) blocks
+hipError_t launch_unmix_grad(const psoam_plan* P, float* g, const float* x, const float* b,
+                             double* partial, hipStream_t s);
+size_t unmix_blocks(const psoam_plan* P);
 // sum over pulses of the anisotropic TV of (S c)^k into out[0] (FP64)
 hipError_t launch_tvs_sum(const psoam_plan* P, const float* c, double* partial, double* out,
                           hipStream_t s);

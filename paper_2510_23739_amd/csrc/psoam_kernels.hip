@@ -104,7 +104,9 @@ __global__ __launch_bounds__(256) void switch_fwd16(const float* __restrict__ c,
   for (int j = 0; j < 8; ++j) b[j] = 0.0f;
   if (k < sw.nk) {
     const size_t col = ((size_t)y * nx + x) * nz;
-    for (int s = 0; s < sw.ns; ++s) {
+    // diagonal switching: only species k contributes
+    const int s0 = sw.diag ? k : 0, s1 = sw.diag ? (k < sw.ns ? k + 1 : k) : sw.ns;
+    for (int s = s0; s < s1; ++s) {
       const float* cs = c + (size_t)s * ny * nx * nz + col;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
@@ -144,7 +146,8 @@ __global__ __launch_bounds__(256) void switch_fwd32(const float* __restrict__ c,
   float b = 0.0f;
   if (k < sw.nk) {
     const size_t col = ((size_t)y * nx + x) * nz;
-    for (int s = 0; s < sw.ns; ++s)
+    const int s0 = sw.diag ? k : 0, s1 = sw.diag ? (k < sw.ns ? k + 1 : k) : sw.ns;
+    for (int s = s0; s < s1; ++s)
       b += coef_at(sw, phi, stab, kp, col, z, k, s) * c[(size_t)s * ny * nx * nz + col + z];
   }
   bq[((size_t)(y + r) * xp + (x + r)) * ps + (size_t)z * kp + k] = b;
@@ -381,6 +384,25 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
     static_assert(NP == 8 || NP == 16, "positions per wave");
     constexpr int kSh = NP == 16 ? 0 : 1;
     const int nz = A.nz;
+    if (A.sw.diag) {
+      // diagonal switching (S_v[k][s] = phi_v if k == s): the lane of pulse k
+      // holds species k's column, written directly (pulse blocks cover
+      // disjoint species, so no accumulation across calls)
+      if (k >= A.nk || k >= A.sw.ns) return;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int ix = ix0 + p;
+        if (ix >= A.nx) continue;
+        const size_t col = ((size_t)iy * A.nx + ix) * nz;
+        float* co = A.out + (size_t)k * A.ny * A.nx * nz + col + row0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int z = row0 + j;
+          if (z < nz) co[j] = coef_at(A.sw, A.phi, A.stab, A.kp, col, z, k, k) * (acc[p][j] * A.inv_scale);
+        }
+      }
+      return;
+    }
     const int pme = n >> kSh;
     const int ixm = ix0 + pme;
     const bool writer = (n & ((1 << kSh) - 1)) == 0 && ixm < A.nx;
@@ -1559,6 +1581,53 @@ hipError_t launch_tvs_sum(const psoam_plan* P, const float* c, double* partial, 
   hipLaunchKernelGGL(tvs_kernel, dim3((unsigned)nb), dim3(256), 0, s, c, P->sw, P->d_phi,
                      P->d_stab, P->Kp, G, partial);
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out);
+  return hipGetLastError();
+}
+
+// ---- per-voxel unmixing (second step of the two-step method) --------------
+// g[s][v] = sum_k S_v[k][s] (sum_s' S_v[k][s'] x[s'][v] - b[k][v]) (b may be
+// null); with partial, FP64 block sums of sum_k (S x - b)^2
+__global__ __launch_bounds__(256) void unmix_grad_kernel(float* __restrict__ g,
+                                                         const float* __restrict__ x,
+                                                         const float* __restrict__ b,
+                                                         SwitchParams sw,
+                                                         const float* __restrict__ phi,
+                                                         const float* __restrict__ stab, int kp,
+                                                         Grid3 G, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int64_t vol = (int64_t)G.ny * G.nx * G.nz;
+  double ss = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < vol; v += stride) {
+    const int iz = (int)(v % G.nz);
+    const size_t col = (size_t)v - iz;
+    float xv[kMaxSpecies], acc[kMaxSpecies];
+    for (int s = 0; s < sw.ns; ++s) {
+      xv[s] = x[(int64_t)s * vol + v];
+      acc[s] = 0.0f;
+    }
+    for (int k = 0; k < sw.nk; ++k) {
+      float r = b ? -b[(int64_t)k * vol + v] : 0.0f;
+      for (int s = 0; s < sw.ns; ++s) r += coef_at(sw, phi, stab, kp, col, iz, k, s) * xv[s];
+      for (int s = 0; s < sw.ns; ++s) acc[s] += coef_at(sw, phi, stab, kp, col, iz, k, s) * r;
+      ss += (double)r * (double)r;
+    }
+    for (int s = 0; s < sw.ns; ++s) g[(int64_t)s * vol + v] = acc[s];
+  }
+  if (partial) {
+    const double r = block_sum(ss, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+  }
+}
+
+size_t unmix_blocks(const psoam_plan* P) { return reduce_blocks((int64_t)P->v_elems()); }
+
+hipError_t launch_unmix_grad(const psoam_plan* P, float* g, const float* x, const float* b,
+                             double* partial, hipStream_t s) {
+  const Grid3 G = grid3(P);
+  const size_t nb = partial ? unmix_blocks(P) : blocks_for(P->v_elems());
+  hipLaunchKernelGGL(unmix_grad_kernel, dim3((unsigned)nb), dim3(256), 0, s, g, x, b, P->sw,
+                     P->d_phi, P->d_stab, P->Kp, G, partial);
   return hipGetLastError();
 }
 

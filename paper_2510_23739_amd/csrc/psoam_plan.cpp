@@ -504,7 +504,8 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
   if (g.nx <= 0 || g.ny <= 0 || g.nz <= 0 || g.nt <= 0 || g.n_pulses <= 0)
     return fail(PSOAM_EINVAL, "plan_create: sizes must be positive");
   if (g.f <= 0 || (g.f % 2) == 0) return fail(PSOAM_EINVAL, "plan_create: footprint f must be odd and positive");
-  if (g.n_species < 1 || g.n_species > kMaxSpecies)
+  // diagonal switching (pulse volumes as "species") allows one volume per pulse
+  if (g.n_species < 1 || g.n_species > (diag ? 64 : kMaxSpecies))
     return fail(PSOAM_EINVAL, "plan_create: n_species must be in 1..8");
   if (sir_w < 1 || sir_w > 64) return fail(PSOAM_EINVAL, "plan_create: sir_w must be in 1..64");
   if (g.phi_per_voxel != 0 && g.phi_per_voxel != 1)
@@ -512,7 +513,7 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
   if (prec < PSOAM_FP32 || prec > PSOAM_FP16_SPLIT)
     return fail(PSOAM_EUNSUPPORTED, "plan_create: unknown precision");
   if (g.n_pulses > 64) return fail(PSOAM_EUNSUPPORTED, "plan_create: at most 64 pulses");
-  for (int s = 0; s < g.n_species; ++s) {
+  for (int s = 0; s < (diag ? 0 : g.n_species); ++s) {
     if (!std::isfinite(sp->a[s]) || !std::isfinite(sp->b[s]) || !(sp->tau[s] > 0.0) ||
         !std::isfinite(sp->tau[s]))
       return fail(PSOAM_EINVAL, "plan_create: species constants must be finite, tau > 0");
@@ -555,7 +556,7 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
   for (int s = 0; s < kMaxSpecies; ++s) {
     sw.a[s] = s < g.n_species ? (float)sp->a[s] : 0.0f;
     sw.b[s] = s < g.n_species ? (float)sp->b[s] : 0.0f;
-    sw.inv_tau[s] = s < g.n_species ? (float)(1.0 / sp->tau[s]) : 0.0f;
+    sw.inv_tau[s] = (!diag && s < g.n_species) ? (float)(1.0 / sp->tau[s]) : 0.0f;
   }
   int rc = PSOAM_OK;
   auto bail = [&](int code) {
@@ -567,7 +568,13 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
     hipError_t _e = (call);                             \
     if (_e != hipSuccess) return bail(hip_fail(_e, #call)); \
   } while (0)
-  P->smax2 = switching_norm2(g, sp, phi, nphi);
+  if (diag) {
+    double m = 0.0;  // S'_v = phi_v I
+    for (size_t i = 0; i < nphi; ++i) m = std::max(m, (double)phi[i] * (double)phi[i]);
+    P->smax2 = m;
+  } else {
+    P->smax2 = switching_norm2(g, sp, phi, nphi);
+  }
   PLAN_HIP(hipMalloc(&P->d_phi, sizeof(float) * nphi));
   PLAN_HIP(hipMemcpy(P->d_phi, phi, sizeof(float) * nphi, hipMemcpyHostToDevice));
   if (!g.phi_per_voxel) {
@@ -611,6 +618,21 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
 #undef PLAN_HIP
   *out = P;
   return PSOAM_OK;
+}
+
+int create_plan_acoustic(const psoam_geom* gp, const int32_t* t0, const float* taps,
+                         int32_t sir_w, int32_t prec, hipStream_t stream, psoam_plan** out) {
+  if (!out) return fail(PSOAM_EINVAL, "plan_create_acoustic: out is NULL");
+  *out = nullptr;
+  if (!gp) return fail(PSOAM_EINVAL, "plan_create_acoustic: NULL argument");
+  if (gp->nz <= 0 || gp->n_pulses <= 0) return fail(PSOAM_EINVAL, "plan_create_acoustic: sizes must be positive");
+  psoam_geom g = *gp;
+  g.n_species = g.n_pulses;  // one volume per pulse
+  g.phi_per_voxel = 0;
+  g.separable = 0;
+  psoam_species sp{};
+  std::vector<float> ones((size_t)g.nz, 1.0f);  // S_v = I
+  return create_plan_impl(&g, &sp, ones.data(), t0, taps, sir_w, prec, stream, 1, true, out);
 }
 
 int create_plan(const psoam_geom* gp, const psoam_species* sp, const float* phi,

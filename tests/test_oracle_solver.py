@@ -74,3 +74,27 @@ def test_fista_trace_reported_and_ends_below_start():
     trace = []
     oracle.fista(p, A, AT, 1.0 / (1.01 * lam), 0.05, 0.05, 50, 20, trace=trace, shape_c=shape)
     assert len(trace) == 50 and trace[-1] < trace[0]
+
+
+def test_unmixing_step_converges_to_per_voxel_nnls():
+    """The two-step method's unmixing (eq. unmixing) run by the same FISTA with
+    A = S (block diagonal over voxels) and no regulariser reaches, voxel by
+    voxel, the nonnegative least-squares solution (SciPy NNLS)."""
+    from scipy.optimize import nnls
+    rng = np.random.default_rng(12)
+    ns, ny, nx, nz, K = 3, 2, 3, 2, 7
+    phi = rng.uniform(0.3, 1.0, size=(ny, nx, nz))
+    sp = synth.species(ns, gamma=1.0)
+    S = oracle.switching_matrix(phi, sp.a, sp.b, sp.tau, sp.gamma, K)
+    b = rng.uniform(0.0, 1.0, size=(K, ny, nx, nz)) * 1e-2
+    A = lambda c: oracle.apply_S(c, S)
+    AT = lambda r: oracle.apply_ST(r, S)
+    alpha1 = 1.0 / oracle.switching_norm2(S)
+    c, _ = oracle.fista(b, A, AT, alpha1, 0.0, 0.0, 60000, 1, shape_c=(ns, ny, nx, nz))
+    for iy in range(ny):
+        for ix in range(nx):
+            for iz in range(nz):
+                ref, _ = nnls(S[iy, ix, iz], b[:, iy, ix, iz])
+                # the per-voxel blocks are ill-conditioned (similar switching
+                # curves), so the iteration is compared at a 1e-4 relative level
+                np.testing.assert_allclose(c[:, iy, ix, iz], ref, rtol=1e-4, atol=1e-6)
