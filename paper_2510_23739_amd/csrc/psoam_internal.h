@@ -105,6 +105,7 @@ struct psoam_plan {
   int device;
   float* d_phi = nullptr;
   float* d_stab = nullptr;   // [Nz][Kp][S] when phi is per depth
+  float* d_stab_t = nullptr; // [K][S][Nz]: the same table with depth fastest (per-voxel kernels)
   void* d_bq = nullptr;      // H operand (hi)
   void* d_bq_lo = nullptr;
   void* d_rq = nullptr;      // H^T operand (hi)

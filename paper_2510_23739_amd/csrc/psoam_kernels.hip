@@ -71,6 +71,15 @@ __device__ __forceinline__ float scoef(const SwitchParams& sw, float phi, int k,
   return phi * (sw.a[s] + sw.b[s] * expf(-(float)k * pg * sw.inv_tau[s]));
 }
 
+// the same coefficient from the depth-fastest table [K][S][Nz] (kernels whose
+// consecutive lanes are consecutive depths read it coalesced)
+__device__ __forceinline__ float coef_zt(const SwitchParams& sw, const float* __restrict__ phi,
+                                         const float* __restrict__ stab_t, int nz, size_t col,
+                                         int z, int k, int s) {
+  if (stab_t) return stab_t[((size_t)k * sw.ns + s) * nz + z];
+  return scoef(sw, phi[col + z], k, s);
+}
+
 __device__ __forceinline__ float coef_at(const SwitchParams& sw, const float* __restrict__ phi,
                                          const float* __restrict__ stab, int kp, size_t col,
                                          int z, int k, int s) {
@@ -1425,7 +1434,7 @@ __global__ __launch_bounds__(256) void r3_w_kernel(
       if (idx[d] > 0) gt += eta3(u2c, u2p, beta, base + v - st[d]);
       if (idx[d] < nd[d] - 1) gt -= eta3(u2c, u2p, beta, base + v);
     }
-    for (int s = 0; s < ns; ++s) acc[s] += coef_at(sw, phi, stab, kp, col, iz, k, s) * gt;
+    for (int s = 0; s < ns; ++s) acc[s] += coef_zt(sw, phi, stab, G.nz, col, iz, k, s) * gt;
   }
   for (int s = 0; s < ns; ++s) {
     float gt = 0.0f;
@@ -1489,8 +1498,8 @@ __global__ __launch_bounds__(256) void r3_u_kernel(
     float sq[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (stab) {
       for (int s = 0; s < ns; ++s) {
-        const float c0 = stab[((size_t)iz * kp + k) * ns + s];
-        const float c1 = stab[((size_t)zn * kp + k) * ns + s];
+        const float c0 = stab[((size_t)k * ns + s) * G.nz + iz];
+        const float c1 = stab[((size_t)k * ns + s) * G.nz + zn];
         sq[0] += c0 * wv[0][s];
         sq[1] += c0 * wv[1][s];
         sq[2] += c0 * wv[2][s];
@@ -1535,12 +1544,12 @@ __global__ __launch_bounds__(256) void tvs_kernel(const float* __restrict__ c, S
     for (int k = 0; k < sw.nk; ++k) {
       double b0 = 0.0;
       for (int s = 0; s < sw.ns; ++s)
-        b0 += (double)coef_at(sw, phi, stab, kp, col0, iz, k, s) * (double)c[(int64_t)s * vol + v];
+        b0 += (double)coef_zt(sw, phi, stab, G.nz, col0, iz, k, s) * (double)c[(int64_t)s * vol + v];
       for (int d = 0; d < 3; ++d) {
         if (!fwd[d]) continue;
         double bd = 0.0;
         for (int s = 0; s < sw.ns; ++s)
-          bd += (double)coef_at(sw, phi, stab, kp, colq[d], zq[d], k, s) *
+          bd += (double)coef_zt(sw, phi, stab, G.nz, colq[d], zq[d], k, s) *
                 (double)c[(int64_t)s * vol + v + st[d]];
         acc += fabs(bd - b0);
       }
@@ -1557,7 +1566,7 @@ hipError_t launch_r3_w(const psoam_plan* P, float* out, const float* z, const fl
   const size_t vol = P->v_elems();
   if (vol == 0) return hipSuccess;
   hipLaunchKernelGGL(r3_w_kernel, dim3(blocks_for(vol)), dim3(256), 0, s, out, z, u1c, u1p, u2c,
-                     u2p, u3c, u3p, beta, P->sw, P->d_phi, P->d_stab, P->Kp, G, clamp_out);
+                     u2p, u3c, u3p, beta, P->sw, P->d_phi, P->d_stab_t, P->Kp, G, clamp_out);
   return hipGetLastError();
 }
 
@@ -1570,7 +1579,7 @@ hipError_t launch_r3_u(const psoam_plan* P, float* n1, float* n2, float* n3, con
   if (vol == 0) return hipSuccess;
   hipLaunchKernelGGL(r3_u_kernel, dim3(blocks_for(vol)), dim3(256), 0, s, n1, n2, n3, w, u1c, u1p,
                      u2c, u2p, u3c, u3p, beta, step[0], step[1], step[2], theta[0], theta[1],
-                     theta[2], P->sw, P->d_phi, P->d_stab, P->Kp, G);
+                     theta[2], P->sw, P->d_phi, P->d_stab_t, P->Kp, G);
   return hipGetLastError();
 }
 
@@ -1579,7 +1588,7 @@ hipError_t launch_tvs_sum(const psoam_plan* P, const float* c, double* partial, 
   const Grid3 G = grid3(P);
   const size_t nb = reduce_blocks((int64_t)P->v_elems());
   hipLaunchKernelGGL(tvs_kernel, dim3((unsigned)nb), dim3(256), 0, s, c, P->sw, P->d_phi,
-                     P->d_stab, P->Kp, G, partial);
+                     P->d_stab_t, P->Kp, G, partial);
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out);
   return hipGetLastError();
 }
@@ -1608,8 +1617,8 @@ __global__ __launch_bounds__(256) void unmix_grad_kernel(float* __restrict__ g,
     }
     for (int k = 0; k < sw.nk; ++k) {
       float r = b ? -b[(int64_t)k * vol + v] : 0.0f;
-      for (int s = 0; s < sw.ns; ++s) r += coef_at(sw, phi, stab, kp, col, iz, k, s) * xv[s];
-      for (int s = 0; s < sw.ns; ++s) acc[s] += coef_at(sw, phi, stab, kp, col, iz, k, s) * r;
+      for (int s = 0; s < sw.ns; ++s) r += coef_zt(sw, phi, stab, G.nz, col, iz, k, s) * xv[s];
+      for (int s = 0; s < sw.ns; ++s) acc[s] += coef_zt(sw, phi, stab, G.nz, col, iz, k, s) * r;
       ss += (double)r * (double)r;
     }
     for (int s = 0; s < sw.ns; ++s) g[(int64_t)s * vol + v] = acc[s];
@@ -1627,7 +1636,7 @@ hipError_t launch_unmix_grad(const psoam_plan* P, float* g, const float* x, cons
   const Grid3 G = grid3(P);
   const size_t nb = partial ? unmix_blocks(P) : blocks_for(P->v_elems());
   hipLaunchKernelGGL(unmix_grad_kernel, dim3((unsigned)nb), dim3(256), 0, s, g, x, b, P->sw,
-                     P->d_phi, P->d_stab, P->Kp, G, partial);
+                     P->d_phi, P->d_stab_t, P->Kp, G, partial);
   return hipGetLastError();
 }
 

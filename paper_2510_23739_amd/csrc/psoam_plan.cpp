@@ -484,7 +484,7 @@ void free_plan(psoam_plan* P) {
     if (b) (void)hipFree(b);
   free_table(P->fwd);
   free_table(P->adj);
-  void* bufs[] = {P->d_phi, P->d_stab, P->d_bq, P->d_bq_lo, P->d_rq, P->d_rq_lo,
+  void* bufs[] = {P->d_phi, P->d_stab, P->d_stab_t, P->d_bq, P->d_bq_lo, P->d_rq, P->d_rq_lo,
                   P->solve_ws.base, P->r3_ws.base, P->d_partial, P->d_scalars};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -591,6 +591,13 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
         }
     PLAN_HIP(hipMalloc(&P->d_stab, sizeof(float) * st.size()));
     PLAN_HIP(hipMemcpy(P->d_stab, st.data(), sizeof(float) * st.size(), hipMemcpyHostToDevice));
+    std::vector<float> stt((size_t)g.n_pulses * g.n_species * g.nz);
+    for (int z = 0; z < g.nz; ++z)
+      for (int k = 0; k < g.n_pulses; ++k)
+        for (int s = 0; s < g.n_species; ++s)
+          stt[((size_t)k * g.n_species + s) * g.nz + z] = st[((size_t)z * P->Kp + k) * g.n_species + s];
+    PLAN_HIP(hipMalloc(&P->d_stab_t, sizeof(float) * stt.size()));
+    PLAN_HIP(hipMemcpy(P->d_stab_t, stt.data(), sizeof(float) * stt.size(), hipMemcpyHostToDevice));
   }
   if (!build_op) {
     PLAN_HIP(hipStreamSynchronize(stream));
