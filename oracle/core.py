@@ -31,6 +31,9 @@ __all__ = [
     "switching_matrix", "apply_S", "apply_ST", "band_matrix", "band_stack",
     "apply_H", "apply_HT", "apply_A", "apply_AT", "dense_A",
     "apply_A_scans", "apply_AT_columns",
+    "shell_mask", "shell_matrix", "shell_stack", "apply_Lambda", "apply_LambdaT",
+    "eir_conv", "eir_corr", "apply_A_fact", "apply_AT_fact", "apply_A_fact_scans",
+    "apply_AT_fact_columns",
     "grad", "grad_T", "tv", "tv_step_constant", "prox_l1", "prox_tv", "prox_w",
     "switching_norm2", "r3_dual_steps", "prox_r3",
     "power_iteration", "objective", "fista", "fista_momentum", "rel_err",
@@ -217,10 +220,10 @@ def apply_A_scans(c, S, t0, taps, nt, scans: Sequence[Tuple[int, int]],
     """A c evaluated at the listed scan positions only: returns [len(scans)][K][Nt].
     Same definition as apply_A, restricted to the outputs asked for."""
     c = np.asarray(c, dtype=np.float64)
-    f = t0.shape[1]
-    R = (f - 1) // 2
     if Hs is None:
         Hs = band_stack(t0, taps, nt)                       # [F][F][Nt][Nz]
+    f = Hs.shape[0]
+    R = (f - 1) // 2
     out = []
     for (iy, ix) in scans:
         cp = _patch(c, iy, ix, R)                           # [S][F][F][Nz]
@@ -243,11 +246,11 @@ def apply_AT_columns(y, S, t0, taps, nz, columns: Sequence[Tuple[int, int]],
                      Hs: Optional[np.ndarray] = None) -> np.ndarray:
     """A^T y evaluated at the listed voxel columns only: returns [len][S][Nz]."""
     y = np.asarray(y, dtype=np.float64)
-    f = t0.shape[1]
-    R = (f - 1) // 2
     nt = y.shape[3]
     if Hs is None:
         Hs = band_stack(t0, taps, nt)
+    f = Hs.shape[0]
+    R = (f - 1) // 2
     out = []
     for (jy, jx) in columns:
         yp = _patch(y, jy, jx, R)                           # yp[:, R+a, R+b] = y[:, jy+a, jx+b]
@@ -257,6 +260,165 @@ def apply_AT_columns(y, S, t0, taps, nz, columns: Sequence[Tuple[int, int]],
         Sv = S[jy, jx] if S.ndim == 5 else S                # [Nz][K][S]
         out.append(np.einsum("zks,kz->sz", Sv, bh))
     return np.stack(out)
+
+
+# ----------------------------------------------------------------------------
+# factorised acoustic operator: unit-weight discrete semicircles (shells in 3D)
+# weighted by the spatial response image, then the temporal convolution with
+# the electrical impulse response (Sec. 2.2.3 "Acoustic Model": eqs.
+# q-above-final, q-below-final, discrete-upper-circle, discrete-lower-circle,
+# acoustic-temporal-conv; App. E)
+# ----------------------------------------------------------------------------
+def shell_mask(nz: int, f: int, nt: int, dr: float, z_focus: float, t_focus: int) -> np.ndarray:
+    """Members of the discrete shells, bool [Nt][Nz][F][F] (offset index jdy,
+    jdx as in the banded table).
+
+    Sample t is the sphere of radius rho_t = |t - t_focus| dr (in voxel
+    pitches) around the focal point: its upper half (voxels whose centre lies
+    above the focal plane, z < z_focus) for t < t_focus and its lower half
+    (centre depth >= z_focus) for t >= t_focus.  A voxel belongs to the
+    shell when its box (one pitch wide around its centre) meets the sphere:
+    the box's nearest point is at distance <= rho_t and its farthest at
+    distance >= rho_t.  The paper keeps every pixel the semicircle crosses
+    with unit weight instead of its arc length; this is the same rule with
+    voxels and spheres.  Squared distances are summed in the order y, x, z."""
+    R = (f - 1) // 2
+    off = np.arange(-R, R + 1, dtype=np.float64)
+    dz = np.arange(nz, dtype=np.float64) - z_focus
+    near = lambda o: np.maximum(np.abs(o) - 0.5, 0.0)   # nearest box coordinate
+    far = lambda o: np.abs(o) + 0.5                     # farthest box coordinate
+    lat_near = near(off)[:, None] * near(off)[:, None] + near(off)[None, :] * near(off)[None, :]
+    lat_far = far(off)[:, None] * far(off)[:, None] + far(off)[None, :] * far(off)[None, :]
+    dmin2 = lat_near[None] + (near(dz) * near(dz))[:, None, None]      # [Nz][F][F]
+    dmax2 = lat_far[None] + (far(dz) * far(dz))[:, None, None]
+    below = np.broadcast_to((dz >= 0.0)[:, None, None], dmin2.shape)
+    t = np.arange(nt, dtype=np.int64)
+    rho = np.abs(t - int(t_focus)).astype(np.float64) * dr
+    rho2 = (rho * rho)[:, None, None, None]
+    lower = (t >= t_focus)[:, None, None, None]
+    side = np.where(lower, below[None], ~below[None])
+    return side & (dmin2[None] <= rho2) & (rho2 <= dmax2[None])
+
+
+def shell_matrix(spr: np.ndarray, mask: np.ndarray, jdy: int, jdx: int) -> np.ndarray:
+    """Nt x Nz matrix of one lateral offset: eta[z][jdy][jdx] where voxel z is
+    in shell t, zero elsewhere."""
+    return mask[:, :, jdy, jdx] * np.asarray(spr, dtype=np.float64)[None, :, jdy, jdx]
+
+
+def shell_stack(spr: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """All offsets' shell matrices, [F][F][Nt][Nz]."""
+    f = spr.shape[1]
+    return np.stack([np.stack([shell_matrix(spr, mask, jy, jx) for jx in range(f)])
+                     for jy in range(f)])
+
+
+def apply_Lambda(b: np.ndarray, spr: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """Spatial integration of every pulse: q[k][iy][ix][t] = sum over the voxels
+    (iy + dy, ix + dx, z) of shell t of eta[z][dy][dx] b[k][iy+dy][ix+dx][z]
+    (the product of the initial pressure with the spatial response shifted to
+    the scan position, summed over the discrete semicircle).  Voxels outside
+    the grid do not exist."""
+    b = np.asarray(b, dtype=np.float64)
+    K, ny, nx, nz = b.shape
+    nt, f = mask.shape[0], mask.shape[2]
+    R = (f - 1) // 2
+    q = np.zeros((K, ny, nx, nt), dtype=np.float64)
+    for jdy in range(f):
+        dy = jdy - R
+        y0, y1 = _overlap(ny, dy)
+        if y0 >= y1:
+            continue
+        for jdx in range(f):
+            dx = jdx - R
+            x0, x1 = _overlap(nx, dx)
+            if x0 >= x1:
+                continue
+            L = shell_matrix(spr, mask, jdy, jdx)
+            q[:, y0:y1, x0:x1, :] += b[:, y0 + dy:y1 + dy, x0 + dx:x1 + dx, :] @ L.T
+    return q
+
+
+def apply_LambdaT(q: np.ndarray, spr: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """Adjoint of apply_Lambda."""
+    q = np.asarray(q, dtype=np.float64)
+    K, ny, nx, nt = q.shape
+    nz, f = mask.shape[1], mask.shape[2]
+    R = (f - 1) // 2
+    b = np.zeros((K, ny, nx, nz), dtype=np.float64)
+    for jdy in range(f):
+        dy = jdy - R
+        y0, y1 = _overlap(ny, dy)
+        if y0 >= y1:
+            continue
+        for jdx in range(f):
+            dx = jdx - R
+            x0, x1 = _overlap(nx, dx)
+            if x0 >= x1:
+                continue
+            L = shell_matrix(spr, mask, jdy, jdx)
+            b[:, y0 + dy:y1 + dy, x0 + dx:x1 + dx, :] += q[:, y0:y1, x0:x1, :] @ L
+    return b
+
+
+def eir_conv(q: np.ndarray, v: np.ndarray, origin: int) -> np.ndarray:
+    """Temporal convolution of every A-scan with the electrical impulse
+    response: p[t] = sum_j v[j] q[t - j + origin] (v[origin] is the zero-lag
+    tap); samples outside [0, Nt) are zero."""
+    q = np.asarray(q, dtype=np.float64)
+    nt = q.shape[-1]
+    p = np.zeros_like(q)
+    for j, vj in enumerate(np.asarray(v, dtype=np.float64)):
+        lag = j - origin
+        if abs(lag) >= nt:
+            continue
+        if lag >= 0:
+            p[..., lag:] += vj * q[..., :nt - lag]
+        else:
+            p[..., :nt + lag] += vj * q[..., -lag:]
+    return p
+
+
+def eir_corr(r: np.ndarray, v: np.ndarray, origin: int) -> np.ndarray:
+    """Adjoint of eir_conv: u[t] = sum_j v[j] r[t + j - origin]."""
+    r = np.asarray(r, dtype=np.float64)
+    nt = r.shape[-1]
+    u = np.zeros_like(r)
+    for j, vj in enumerate(np.asarray(v, dtype=np.float64)):
+        lag = j - origin
+        if abs(lag) >= nt:
+            continue
+        if lag >= 0:
+            u[..., :nt - lag] += vj * r[..., lag:]
+        else:
+            u[..., -lag:] += vj * r[..., :nt + lag]
+    return u
+
+
+def apply_A_fact(c, S, spr, mask, v, origin):
+    """A = V Lambda S: switching, spatial integration over the shells, then the
+    temporal convolution (eq. full-forward with the factorised W)."""
+    return eir_conv(apply_Lambda(apply_S(c, S), spr, mask), v, origin)
+
+
+def apply_AT_fact(y, S, spr, mask, v, origin):
+    """A^T = S^T Lambda^T V^T."""
+    return apply_ST(apply_LambdaT(eir_corr(y, v, origin), spr, mask), S)
+
+
+def apply_A_fact_scans(c, S, spr, mask, v, origin, scans, Ls=None):
+    """apply_A_fact at the listed scan positions only: [len(scans)][K][Nt]."""
+    if Ls is None:
+        Ls = shell_stack(spr, mask)
+    q = apply_A_scans(c, S, None, None, mask.shape[0], scans, Hs=Ls)
+    return eir_conv(q, v, origin)
+
+
+def apply_AT_fact_columns(y, S, spr, mask, v, origin, columns, Ls=None):
+    """apply_AT_fact at the listed voxel columns only: [len(columns)][S][Nz]."""
+    if Ls is None:
+        Ls = shell_stack(spr, mask)
+    return apply_AT_columns(eir_corr(y, v, origin), S, None, None, mask.shape[1], columns, Hs=Ls)
 
 
 # ----------------------------------------------------------------------------

@@ -197,6 +197,37 @@ def random_table(nz: int, f: int, nt: int, width: int, rng: np.random.Generator,
 
 
 # ----------------------------------------------------------------------------
+# inputs of the factorised acoustic operator: the spatial response image on
+# the voxel grid, the sampled electrical impulse response and the geometry of
+# the delay shells
+# ----------------------------------------------------------------------------
+def spr_table(nz: int, f: int) -> np.ndarray:
+    """Spatial response image eta[z][jdy][jdx] (float32): the lateral beam
+    weight exp(-(dx^2 + dy^2) / 2 sigma(z)^2) of the banded table, without
+    the pulse."""
+    r = (f - 1) // 2
+    iz = np.arange(nz, dtype=np.float64)[:, None, None]
+    d = np.arange(-r, r + 1, dtype=np.float64)
+    sig = beam_sigma_vox(iz, nz, f)
+    w = np.exp(-(d[None, :, None] ** 2 + d[None, None, :] ** 2) / (2.0 * sig * sig))
+    return w.astype(np.float32)
+
+
+def eir_taps() -> Tuple[np.ndarray, int]:
+    """Electrical impulse response sampled at DT_S over its kept support
+    |u| <= 6 s: v[j] = pulse((j - origin) dt); returns (v float32, origin)."""
+    half = int(math.floor(BAND_HALF_SIGMAS * pulse_sigma_s() / DT_S + 1e-9))
+    u = np.arange(-half, half + 1, dtype=np.float64) * DT_S
+    return pulse(u).astype(np.float32), half
+
+
+def shell_geometry(nz: int, nt: int) -> Tuple[float, float, int]:
+    """(dr, z_focus, t_focus): radius step per sample in voxel pitches
+    (c0 dt / pitch), focal depth in voxel units and the focal sample Nt/2."""
+    return C0_M_S * DT_S / PITCH_M, focal_depth_vox(nz), nt // 2
+
+
+# ----------------------------------------------------------------------------
 # optics and photo-physics constants
 # ----------------------------------------------------------------------------
 def phi_depth(nz: int) -> np.ndarray:
