@@ -233,6 +233,51 @@ int psoam_solve(const psoam_plan* plan, const float* p, float* c, const psoam_so
 int psoam_plan_create_acoustic(const psoam_geom* g, const int32_t* sir_t0, const float* sir_taps,
                                int32_t sir_w, int32_t prec, void* stream, psoam_plan** out);
 
+/* ---- the factorised acoustic operator (Sec. 2.2.3 "Acoustic Model": eqs.
+ * q-above-final, q-below-final, discrete-upper-circle, discrete-lower-circle,
+ * acoustic-temporal-conv; App. E) ----
+ * The paper's own discretisation of one acoustic process: the signal at
+ * sample t is the initial pressure times the spatial response image eta,
+ * summed with unit weight over the voxels that the delay sphere of t
+ * crosses, then convolved in time with the electrical impulse response v:
+ *   q[k][iy][ix][t] = sum_{(z,jdy,jdx) in Shell(t)} eta[z][jdy][jdx] *
+ *                     b[k][iy+jdy-R][ix+jdx-R][z],          b = S c
+ *   y[k][iy][ix][t] = sum_j v[j] q[k][iy][ix][t - j + eir_origin]
+ * Shell(t): radius rho_t = |t - t_focus| * dr voxel pitches around the
+ * focal point (scan position, z_focus).  For t < t_focus the voxels whose
+ * centre depth is < z_focus, for t >= t_focus those with centre depth
+ * >= z_focus; of these, the voxels whose box (one pitch wide) meets the
+ * sphere: nearest box point at distance <= rho_t <= farthest box point.
+ * Distances use the box coordinates max(|o| - 1/2, 0) and |o| + 1/2 of each
+ * offset o (dy, dx, z - z_focus), squared and summed in the order y, x, z,
+ * in double precision.  Samples outside [0, Nt) and voxels outside the grid
+ * are absent. */
+typedef struct {
+  double dr;            /* radius step per time sample, voxel pitches (c0 dt / pitch), > 0 */
+  double z_focus;       /* focal depth in voxel units (voxel centres at 0 .. Nz-1) */
+  int32_t t_focus;      /* sample of radius 0 */
+  int32_t n_eir;        /* taps of v, 1..32 */
+  int32_t eir_origin;   /* index of v's zero-lag tap, 0 .. n_eir-1 */
+} psoam_shell;
+
+/* Plan of A = V Lambda S with the factorised acoustic operator above in
+ * place of the banded H; every other entry point (psoam_apply_A/AT,
+ * psoam_solve, psoam_solve_batch, the prox calls) takes it like any plan.
+ * The shell sums run on the matrix cores as a narrow band (each voxel
+ * column meets a few consecutive samples), the convolution as a separate
+ * pass over the A-scans; the plan owns one extra [K][Ny][Nx][Nt] buffer.
+ * HOST pointers, read during the call only:
+ *   phi  float [Nz] or [Ny][Nx][Nz];  spr  float [Nz][F][F] (eta);
+ *   eir  float [n_eir] (v).
+ * g->separable must be 0.  Synchronises `stream`.
+ * Errors: EINVAL (null pointer, bad size or shell parameter, non-finite
+ * eta or v; the psoam_plan_create checks), EUNSUPPORTED (nt > 4096, a shell
+ * band wider than 64 samples, i.e. dr too small, or separable = 1), ENOMEM,
+ * EHIP.  *out is NULL on error. */
+int psoam_plan_create_factorised(const psoam_geom* g, const psoam_species* sp, const float* phi,
+                                 const float* spr, const float* eir, const psoam_shell* sh,
+                                 int32_t prec, void* stream, psoam_plan** out);
+
 /* Unmixing step: psoam_solve's iteration with the per-voxel switching S of
  * `plan` in place of A: gradient S^T (S xi - b) voxel by voxel, the same
  * prox (lambda_tv = nu_3 on TV(c), lambda_l1 = nu_2), step alpha1 or the

@@ -102,6 +102,43 @@ class Plan:
         return self
 
     @classmethod
+    def factorised(cls, nx: int, ny: int, nz: int, n_pulses: int, nt: int, f: int,
+                   phi: np.ndarray, species, spr: np.ndarray, eir: np.ndarray, eir_origin: int,
+                   dr: float, z_focus: float, t_focus: int, prec: str = "fp32", stream=None):
+        """Plan of A = V Lambda S with the paper's factorised acoustic operator
+        (unit-weight discrete shells weighted by the spatial response image
+        spr [Nz][F][F], then the temporal convolution with eir; see
+        psoam_plan_create_factorised)."""
+        self = cls.__new__(cls)
+        self._h = None
+        species_a, species_b, species_tau = list(species.a), list(species.b), list(species.tau)
+        ns = len(species_a)
+        phi = np.ascontiguousarray(phi, dtype=np.float32)
+        self.geom = _lib.Geom(nx, ny, nz, ns, n_pulses, nt, f, 1 if phi.ndim == 3 else 0, 0)
+        sp = _lib.Species()
+        for s in range(ns):
+            sp.a[s], sp.b[s], sp.tau[s] = species_a[s], species_b[s], species_tau[s]
+        sp.gamma = float(species.gamma)
+        self._spr = np.ascontiguousarray(spr, dtype=np.float32)
+        self._eir = np.ascontiguousarray(eir, dtype=np.float32).ravel()
+        if self._spr.shape != (nz, f, f):
+            raise ValueError("spatial response image shape does not match (nz, f, f)")
+        sh = _lib.Shell(float(dr), float(z_focus), int(t_focus), int(self._eir.size), int(eir_origin))
+        handle = C.c_void_p()
+        check(load().psoam_plan_create_factorised(C.byref(self.geom), C.byref(sp),
+                                                  phi.ctypes.data_as(C.c_void_p),
+                                                  self._spr.ctypes.data_as(C.c_void_p),
+                                                  self._eir.ctypes.data_as(C.c_void_p),
+                                                  C.byref(sh), PREC[prec], _stream(stream),
+                                                  C.byref(handle)))
+        self._h = handle
+        self.prec = prec
+        self.c_shape = (ns, ny, nx, nz)
+        self.y_shape = (n_pulses, ny, nx, nt)
+        self.b_shape = (n_pulses, ny, nx, nz)
+        return self
+
+    @classmethod
     def from_config(cls, cfg, phi, species, t0, taps, prec="fp32", stream=None, separable=False):
         return cls(cfg.nx, cfg.ny, cfg.nz, cfg.n_pulses, cfg.nt, cfg.f, phi, species, t0, taps,
                    prec=prec, stream=stream, separable=separable)

@@ -22,6 +22,11 @@ class Species(C.Structure):
                 ("gamma", C.c_double)]
 
 
+class Shell(C.Structure):
+    _fields_ = [("dr", C.c_double), ("z_focus", C.c_double), ("t_focus", C.c_int32),
+                ("n_eir", C.c_int32), ("eir_origin", C.c_int32)]
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("lambda_tv", C.c_double), ("lambda_l1", C.c_double),
                 ("k1", C.c_int32), ("k2", C.c_int32),
@@ -48,6 +53,9 @@ EXPORTS = {
     "psoam_plan_destroy": (C.c_int, [C.c_void_p]),
     "psoam_plan_create_acoustic": (C.c_int, [C.POINTER(Geom), C.c_void_p, C.c_void_p, C.c_int32,
                                              C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "psoam_plan_create_factorised": (C.c_int, [C.POINTER(Geom), C.POINTER(Species), C.c_void_p,
+                                               C.c_void_p, C.c_void_p, C.POINTER(Shell),
+                                               C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "psoam_unmix": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts),
                               C.POINTER(SolveStats), C.c_void_p]),
     "psoam_plan_geom": (C.c_int, [C.c_void_p, C.POINTER(Geom)]),

@@ -19,6 +19,9 @@ int create_plan(const psoam_geom* gp, const psoam_species* sp, const float* phi,
 void free_plan(psoam_plan* P);
 int create_plan_acoustic(const psoam_geom* gp, const int32_t* t0, const float* taps,
                          int32_t sir_w, int32_t prec, hipStream_t stream, psoam_plan** out);
+int create_plan_factorised(const psoam_geom* gp, const psoam_species* sp, const float* phi,
+                           const float* spr, const float* eir, const psoam_shell* sh,
+                           int32_t prec, hipStream_t stream, psoam_plan** out);
 const char* last_error_cstr();
 
 namespace {
@@ -66,6 +69,7 @@ int ensure_solve_ws(psoam_plan* P, SolveBufs& B) {
   }
   size_t np = std::max(band_partials(P->inner ? P->inner : P, 1), (size_t)2 * reduce_blocks((int64_t)sv));
   if (P->inner) np = std::max({np, sep_blocks(P), reduce_blocks((int64_t)P->y_elems())});
+  if (P->fact) np = std::max(np, eir_blocks(P));
   if (P->n_partial < np) {
     if (P->d_partial) PSOAM_HIP(hipFree(P->d_partial));
     P->d_partial = nullptr;
@@ -253,7 +257,9 @@ int prepare_p(psoam_plan* P, int op, const float* p, hipStream_t s) {
 }
 
 // g = A^T (A x - p), or A^T A x when p is null.  General form: S and H with
-// the residual in H's epilogue, then H^T with S^T.  Separable form: h = H of
+// the residual in H's epilogue, then H^T with S^T.  Factorised form: the
+// shell sums q = Lambda S x, then V^T (V q - p) row by row in place, then
+// Lambda^T with S^T.  Separable form: h = H of
 // phi x_s over the S species, A^T (A x - p) = phi H^T(G h - T^T p) with
 // G = T^T T (prepare_p has put T^T p in d_q), never forming A x itself.
 int enqueue_grad(psoam_plan* P, int op, const float* x, const float* p, float* g, hipStream_t s) {
@@ -265,6 +271,12 @@ int enqueue_grad(psoam_plan* P, int op, const float* x, const float* p, float* g
     PSOAM_HIP(launch_sep_residual(P, P->d_rt, P->d_h, p ? P->d_q : nullptr, nullptr, s));
     PSOAM_HIP(launch_pack_r(P->inner, P->d_rt, s));
     PSOAM_HIP(launch_band(P->inner, 2, g, nullptr, nullptr, s));
+  } else if (P->fact) {
+    PSOAM_HIP(launch_switch_fwd(P, x, s));
+    PSOAM_HIP(launch_band(P, 0, P->d_fq, nullptr, nullptr, s));
+    PSOAM_HIP(launch_eir_rows(P, 2, P->d_fq, P->d_fq, p, nullptr, s));
+    PSOAM_HIP(launch_pack_r(P, P->d_fq, s));
+    PSOAM_HIP(launch_band(P, 2, g, nullptr, nullptr, s));
   } else {
     PSOAM_HIP(launch_switch_fwd(P, x, s));
     PSOAM_HIP(launch_band(P, 1, nullptr, p, P->d_partial, s));
@@ -286,6 +298,11 @@ int objective_terms(psoam_plan* P, int op, const float* c, const float* p, bool 
     PSOAM_HIP(launch_band(P->inner, 0, P->d_h, nullptr, nullptr, s));
     PSOAM_HIP(launch_sep_residual(P, P->d_rt, P->d_h, P->d_q, P->d_partial, s));
     PSOAM_HIP(launch_sum_partials(P->d_partial, sep_blocks(P), P->d_scalars + 4, s));
+  } else if (P->fact) {
+    PSOAM_HIP(launch_switch_fwd(P, c, s));
+    PSOAM_HIP(launch_band(P, 0, P->d_fq, nullptr, nullptr, s));
+    PSOAM_HIP(launch_eir_rows(P, 3, nullptr, P->d_fq, p, P->d_partial, s));
+    PSOAM_HIP(launch_sum_partials(P->d_partial, eir_blocks(P), P->d_scalars + 4, s));
   } else {
     PSOAM_HIP(launch_switch_fwd(P, c, s));
     PSOAM_HIP(launch_band(P, 1, nullptr, p, P->d_partial, s));
@@ -658,6 +675,12 @@ int psoam_apply_A(const psoam_plan* plan, const float* c, float* y, void* stream
     PSOAM_HIP(launch_sep_expand(plan, y, plan->d_h, S(stream)));
     return PSOAM_OK;
   }
+  if (plan->fact) {
+    PSOAM_HIP(launch_switch_fwd(plan, c, S(stream)));
+    PSOAM_HIP(launch_band(plan, 0, plan->d_fq, nullptr, nullptr, S(stream)));
+    PSOAM_HIP(launch_eir_rows(plan, 0, y, plan->d_fq, nullptr, nullptr, S(stream)));
+    return PSOAM_OK;
+  }
   PSOAM_HIP(launch_switch_fwd(plan, c, S(stream)));
   PSOAM_HIP(launch_band(plan, 0, y, nullptr, nullptr, S(stream)));
   return PSOAM_OK;
@@ -670,6 +693,12 @@ int psoam_apply_AT(const psoam_plan* plan, const float* y, float* c, void* strea
     PSOAM_HIP(launch_sep_contract(plan, plan->d_rt, y, S(stream)));
     PSOAM_HIP(launch_pack_r(plan->inner, plan->d_rt, S(stream)));
     PSOAM_HIP(launch_band(plan->inner, 2, c, nullptr, nullptr, S(stream)));
+    return PSOAM_OK;
+  }
+  if (plan->fact) {
+    PSOAM_HIP(launch_eir_rows(plan, 1, plan->d_fq, y, nullptr, nullptr, S(stream)));
+    PSOAM_HIP(launch_pack_r(plan, plan->d_fq, S(stream)));
+    PSOAM_HIP(launch_band(plan, 2, c, nullptr, nullptr, S(stream)));
     return PSOAM_OK;
   }
   PSOAM_HIP(launch_pack_r(plan, y, S(stream)));
@@ -733,6 +762,12 @@ int psoam_prox_r3(const psoam_plan* plan, float* x, const float* z, float theta_
 int psoam_plan_create_acoustic(const psoam_geom* g, const int32_t* sir_t0, const float* sir_taps,
                                int32_t sir_w, int32_t prec, void* stream, psoam_plan** out) {
   return create_plan_acoustic(g, sir_t0, sir_taps, sir_w, prec, S(stream), out);
+}
+
+int psoam_plan_create_factorised(const psoam_geom* g, const psoam_species* sp, const float* phi,
+                                 const float* spr, const float* eir, const psoam_shell* sh,
+                                 int32_t prec, void* stream, psoam_plan** out) {
+  return create_plan_factorised(g, sp, phi, spr, eir, sh, prec, S(stream), out);
 }
 
 int psoam_unmix(const psoam_plan* plan, const float* b, float* c, const psoam_solve_opts* o,

@@ -32,6 +32,14 @@ constexpr float kFp16Scale = 256.0f; // FP16 operands carry this power-of-two sc
 constexpr int kLdsPos = 16;          // staged kernel: positions per wave
 constexpr int kLdsMaxBytes = 160 * 1024;
 constexpr int kRunMax = 4;           // longest sliding run (chunks) of the staged kernel
+constexpr int kMaxEir = 32;          // taps of the electrical impulse response (factorised form)
+constexpr int kMaxEirNt = 4096;      // longest A-scan of the factorised form (LDS row buffer)
+
+// electrical impulse response of the factorised form: y[t] = sum_j v[j] q[t - j + origin]
+struct EirParams {
+  int n, origin;
+  float v[kMaxEir];
+};
 
 // Photo-switching coefficients in the form the kernels evaluate:
 //   S_v[k][s] = phi_v * (a[s] + b[s] * exp(-k * phi_v^gamma * inv_tau[s]))
@@ -131,6 +139,11 @@ struct psoam_plan {
   float* d_h = nullptr;       // [S][Ny][Nx][Nt]: H of phi c_s
   float* d_rt = nullptr;      // [S][Ny][Nx][Nt]: T^T r, the adjoint's input
   float* d_q = nullptr;       // [S][Ny][Nx][Nt]: T^T p of the current solve
+  // factorised acoustic operator: the band holds the shell sums Lambda, the
+  // impulse response runs as a separate pass over the A-scans
+  int fact = 0;
+  psoam::EirParams eir{};
+  float* d_fq = nullptr;      // [K][Ny][Nx][Nt]: shell sums q = Lambda S c (and V^T r)
   size_t h_elems() const { return (size_t)g.n_species * g.ny * g.nx * g.nt; }
   size_t y_elems() const { return (size_t)g.n_pulses * g.ny * g.nx * g.nt; }
   size_t c_elems() const { return (size_t)g.n_species * g.ny * g.nx * g.nz; }
@@ -220,6 +233,14 @@ size_t sep_blocks(const psoam_plan* P);
 hipError_t launch_unmix_grad(const psoam_plan* P, float* g, const float* x, const float* b,
                              double* partial, hipStream_t s);
 size_t unmix_blocks(const psoam_plan* P);
+// factorised form, one pass over the K*Ny*Nx A-scans of Nt samples:
+//   mode 0: out = V in;  mode 1: out = V^T in;
+//   mode 2: r = V in - p (p may be null), out = V^T r (out may alias in);
+//   mode 3: r = V in - p, FP64 sums of r^2 only.
+// Modes 2 and 3 write eir_blocks(P) partial sums when partial is not null.
+hipError_t launch_eir_rows(const psoam_plan* P, int mode, float* out, const float* in,
+                           const float* p, double* partial, hipStream_t s);
+size_t eir_blocks(const psoam_plan* P);
 // sum over pulses of the anisotropic TV of (S c)^k into out[0] (FP64)
 hipError_t launch_tvs_sum(const psoam_plan* P, const float* c, double* partial, double* out,
                           hipStream_t s);

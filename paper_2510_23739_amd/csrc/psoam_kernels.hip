@@ -20,6 +20,7 @@
 // chunk and reuses it for kPosPerWave positions x (Kp/16) pulse blocks.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "psoam_internal.h"
@@ -1701,6 +1702,110 @@ __global__ __launch_bounds__(256) void sep_residual_kernel(float* __restrict__ r
     const double r = block_sum(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
   }
+}
+
+// Temporal convolution pass of the factorised operator (eq.
+// acoustic-temporal-conv on every A-scan): one wave per row of nt samples,
+// staged in LDS with kMaxEir zero samples on either side so that every tap
+// reads inside the buffer; modes 2 and 3 put the residual in a second row
+// buffer.  The grid strides over groups of rows; every wave of a block runs
+// the same number of groups (block-uniform loop), so the barriers match.
+//   mode 0: out[t] = sum_j v[j] in[t - j + origin]
+//   mode 1: out[t] = sum_j v[j] in[t + j - origin]          (the adjoint)
+//   mode 2: r = (V in) - p, out = V^T r, FP64 block sums of r^2
+//   mode 3: r = (V in) - p, FP64 block sums of r^2 only
+// `out` may alias `in` (each row is read whole before it is written).
+template <int MODE>
+__global__ __launch_bounds__(256) void eir_rows_kernel(float* out, const float* in,
+                                                       const float* __restrict__ pm, EirParams e,
+                                                       int nt, int64_t rows,
+                                                       double* __restrict__ partial) {
+  extern __shared__ float eir_lds[];
+  __shared__ double sh[4];
+  const int wpb = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int stride = nt + 2 * kMaxEir;
+  float* qb = eir_lds + (size_t)w * stride * (MODE >= 2 ? 2 : 1);
+  float* rb = qb + stride;
+  double ss = 0.0;
+  for (int64_t base = (int64_t)blockIdx.x * wpb; base < rows; base += (int64_t)gridDim.x * wpb) {
+    const int64_t row = base + w;
+    const bool live = row < rows;
+    const size_t off = live ? (size_t)row * nt : 0;
+    for (int i = lane; i < stride; i += 64) {
+      const int t = i - kMaxEir;
+      qb[i] = (live && t >= 0 && t < nt) ? in[off + t] : 0.0f;
+      if (MODE >= 2 && (t < 0 || t >= nt)) rb[i] = 0.0f;
+    }
+    __syncthreads();
+    if (MODE <= 1) {
+      for (int t = lane; t < nt; t += 64) {
+        float acc = 0.0f;
+        for (int j = 0; j < e.n; ++j) {
+          const int lag = j - e.origin;
+          acc += e.v[j] * qb[kMaxEir + (MODE == 0 ? t - lag : t + lag)];
+        }
+        if (live) out[off + t] = acc;
+      }
+    } else {
+      for (int t = lane; t < nt; t += 64) {
+        float acc = 0.0f;
+        for (int j = 0; j < e.n; ++j) acc += e.v[j] * qb[kMaxEir + t - (j - e.origin)];
+        const float r = acc - ((pm && live) ? pm[off + t] : 0.0f);
+        rb[kMaxEir + t] = r;
+        if (live) ss += (double)r * (double)r;
+      }
+      if (MODE == 2) {
+        __syncthreads();
+        for (int t = lane; t < nt; t += 64) {
+          float acc = 0.0f;
+          for (int j = 0; j < e.n; ++j) acc += e.v[j] * rb[kMaxEir + t + (j - e.origin)];
+          if (live) out[off + t] = acc;
+        }
+      }
+    }
+    __syncthreads();  // the next group overwrites the row buffers
+  }
+  if (MODE >= 2 && partial) {
+    const double r = block_sum(ss, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+  }
+}
+
+static inline int eir_waves(int nt) { return nt <= 1024 ? 4 : 1; }
+
+size_t eir_blocks(const psoam_plan* P) {
+  const int64_t rows = (int64_t)P->g.n_pulses * P->g.ny * P->g.nx;
+  const int wpb = eir_waves(P->g.nt);
+  const int64_t b = (rows + wpb - 1) / wpb;
+  return (size_t)std::min<int64_t>(std::max<int64_t>(b, 1), 2048);
+}
+
+hipError_t launch_eir_rows(const psoam_plan* P, int mode, float* out, const float* in,
+                           const float* p, double* partial, hipStream_t s) {
+  const int nt = P->g.nt;
+  if (nt <= 0 || nt > kMaxEirNt) return hipErrorInvalidValue;
+  const int64_t rows = (int64_t)P->g.n_pulses * P->g.ny * P->g.nx;
+  if (rows == 0) return hipSuccess;
+  const int wpb = eir_waves(nt);
+  const size_t lds = sizeof(float) * (size_t)wpb * (nt + 2 * kMaxEir) * (mode >= 2 ? 2 : 1);
+  const dim3 grid((unsigned)eir_blocks(P)), block(64 * wpb);
+  switch (mode) {
+    case 0:
+      hipLaunchKernelGGL(eir_rows_kernel<0>, grid, block, lds, s, out, in, p, P->eir, nt, rows, partial);
+      break;
+    case 1:
+      hipLaunchKernelGGL(eir_rows_kernel<1>, grid, block, lds, s, out, in, p, P->eir, nt, rows, partial);
+      break;
+    case 2:
+      hipLaunchKernelGGL(eir_rows_kernel<2>, grid, block, lds, s, out, in, p, P->eir, nt, rows, partial);
+      break;
+    case 3:
+      hipLaunchKernelGGL(eir_rows_kernel<3>, grid, block, lds, s, out, in, p, P->eir, nt, rows, partial);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 size_t sep_blocks(const psoam_plan* P) {

@@ -480,7 +480,7 @@ void free_plan(psoam_plan* P) {
   (void)hipDeviceSynchronize();
   if (P->inner) free_plan(P->inner);
   P->inner = nullptr;
-  for (void* b : {(void*)P->d_T, (void*)P->d_h, (void*)P->d_rt, (void*)P->d_q})
+  for (void* b : {(void*)P->d_T, (void*)P->d_h, (void*)P->d_rt, (void*)P->d_q, (void*)P->d_fq})
     if (b) (void)hipFree(b);
   free_table(P->fwd);
   free_table(P->adj);
@@ -686,6 +686,97 @@ int create_plan(const psoam_geom* gp, const psoam_species* sp, const float* phi,
   float** bufs[] = {&P->d_h, &P->d_rt, &P->d_q};
   for (float** b : bufs)
     if ((e = hipMalloc(b, sizeof(float) * P->h_elems())) != hipSuccess) return bail(e, "hipMalloc separable buffers");
+  *out = P;
+  return PSOAM_OK;
+}
+
+// Factorised acoustic operator (Sec. 2.2.3, eqs. q-above-final, q-below-final):
+// the shell membership of every voxel column (z, jdy, jdx) is a run of
+// consecutive samples (the radius grows with |t - t_focus| and each column
+// sits on one side of the focal plane), so Lambda is a band of eta values
+// and goes through the same packing as the impulse-response table; the
+// impulse response v is kept for the per-A-scan convolution pass.
+int create_plan_factorised(const psoam_geom* gp, const psoam_species* sp, const float* phi,
+                           const float* spr, const float* eir, const psoam_shell* sh,
+                           int32_t prec, hipStream_t stream, psoam_plan** out) {
+  if (!out) return fail(PSOAM_EINVAL, "plan_create_factorised: out is NULL");
+  *out = nullptr;
+  if (!gp || !sp || !phi || !spr || !eir || !sh)
+    return fail(PSOAM_EINVAL, "plan_create_factorised: NULL argument");
+  const psoam_geom g = *gp;
+  if (g.separable != 0)
+    return fail(PSOAM_EUNSUPPORTED, "plan_create_factorised: no separable form of the factorised operator");
+  if (g.nx <= 0 || g.ny <= 0 || g.nz <= 0 || g.nt <= 0 || g.n_pulses <= 0)
+    return fail(PSOAM_EINVAL, "plan_create_factorised: sizes must be positive");
+  if (g.f <= 0 || (g.f % 2) == 0)
+    return fail(PSOAM_EINVAL, "plan_create_factorised: footprint f must be odd and positive");
+  if (g.nt > kMaxEirNt) return fail(PSOAM_EUNSUPPORTED, "plan_create_factorised: nt above 4096");
+  if (!(sh->dr > 0.0) || !std::isfinite(sh->dr))
+    return fail(PSOAM_EINVAL, "plan_create_factorised: dr must be finite and > 0");
+  if (!std::isfinite(sh->z_focus)) return fail(PSOAM_EINVAL, "plan_create_factorised: z_focus not finite");
+  if (sh->t_focus < -(1 << 28) || sh->t_focus > (1 << 28))
+    return fail(PSOAM_EINVAL, "plan_create_factorised: t_focus out of range");
+  if (sh->n_eir < 1 || sh->n_eir > kMaxEir)
+    return fail(PSOAM_EINVAL, "plan_create_factorised: n_eir must be in 1..32");
+  if (sh->eir_origin < 0 || sh->eir_origin >= sh->n_eir)
+    return fail(PSOAM_EINVAL, "plan_create_factorised: eir_origin outside 0..n_eir-1");
+  for (int j = 0; j < sh->n_eir; ++j)
+    if (!std::isfinite(eir[j])) return fail(PSOAM_EINVAL, "plan_create_factorised: non-finite eir tap");
+  const int F = g.f, R = (F - 1) / 2;
+  const size_t ncol = (size_t)g.nz * F * F;
+  for (size_t i = 0; i < ncol; ++i)
+    if (!std::isfinite(spr[i])) return fail(PSOAM_EINVAL, "plan_create_factorised: non-finite spr entry");
+  // nearest and farthest coordinate of the unit box around offset o
+  auto near = [](double o) { return std::max(std::fabs(o) - 0.5, 0.0); };
+  auto far = [](double o) { return std::fabs(o) + 0.5; };
+  std::vector<int32_t> first(ncol, -1), count(ncol, 0);
+  int width = 1;
+  for (int z = 0; z < g.nz; ++z) {
+    const double dz = (double)z - sh->z_focus;
+    const double nz2 = near(dz) * near(dz), fz2 = far(dz) * far(dz);
+    const bool below = dz >= 0.0;
+    for (int jy = 0; jy < F; ++jy) {
+      const double oy = (double)(jy - R);
+      for (int jx = 0; jx < F; ++jx) {
+        const double ox = (double)(jx - R);
+        const double dmin2 = (near(oy) * near(oy) + near(ox) * near(ox)) + nz2;
+        const double dmax2 = (far(oy) * far(oy) + far(ox) * far(ox)) + fz2;
+        const size_t col = ((size_t)z * F + jy) * F + jx;
+        for (int t = 0; t < g.nt; ++t) {
+          if ((t >= sh->t_focus) != below) continue;
+          const double rho = (double)std::abs(t - sh->t_focus) * sh->dr;
+          const double rho2 = rho * rho;
+          if (!(dmin2 <= rho2 && rho2 <= dmax2)) continue;
+          if (first[col] < 0) first[col] = t;
+          if (t != first[col] + count[col])
+            return fail(PSOAM_EINVAL, "plan_create_factorised: shell samples of a column not consecutive");
+          ++count[col];
+        }
+        width = std::max(width, (int)count[col]);
+      }
+    }
+  }
+  if (width > 64)
+    return fail(PSOAM_EUNSUPPORTED, "plan_create_factorised: shell band wider than 64 samples (dr too small)");
+  std::vector<int32_t> t0(ncol, 0);
+  std::vector<float> taps(ncol * (size_t)width, 0.0f);
+  for (size_t col = 0; col < ncol; ++col) {
+    if (count[col] == 0) continue;
+    t0[col] = first[col];
+    for (int j = 0; j < count[col]; ++j) taps[col * width + j] = spr[col];
+  }
+  psoam_plan* P = nullptr;
+  if (int rc = create_plan_impl(&g, sp, phi, t0.data(), taps.data(), width, prec, stream, 0, true, &P))
+    return rc;
+  P->fact = 1;
+  P->eir.n = sh->n_eir;
+  P->eir.origin = sh->eir_origin;
+  for (int j = 0; j < sh->n_eir; ++j) P->eir.v[j] = eir[j];
+  hipError_t e = hipMalloc(&P->d_fq, sizeof(float) * P->y_elems());
+  if (e != hipSuccess) {
+    free_plan(P);
+    return hip_fail(e, "hipMalloc factorised buffer");
+  }
   *out = P;
   return PSOAM_OK;
 }

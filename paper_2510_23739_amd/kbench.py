@@ -25,6 +25,8 @@ def main():
     ap.add_argument("--prec", default="bf16")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--what", default="fwd,adj,tv")
+    ap.add_argument("--fact", action="store_true",
+                    help="factorised acoustic operator (shell sums + impulse-response pass)")
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -40,7 +42,14 @@ def main():
     sp = synth.species(cfg.n_species)
     rng = np.random.default_rng(0)
     c = torch.from_numpy(rng.random(cfg.c_shape, dtype=np.float32)).cuda()
-    plan = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=args.prec)
+    if args.fact:
+        dr, z_focus, t_focus = synth.shell_geometry(cfg.nz, cfg.nt)
+        eir, origin = synth.eir_taps()
+        plan = pk.Plan.factorised(cfg.nx, cfg.ny, cfg.nz, cfg.n_pulses, cfg.nt, cfg.f, phi, sp,
+                                  synth.spr_table(cfg.nz, cfg.f), eir, origin, dr, z_focus,
+                                  t_focus, prec=args.prec)
+    else:
+        plan = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=args.prec)
     y = torch.empty(cfg.y_shape, dtype=torch.float32, device="cuda")
     g = torch.empty(cfg.c_shape, dtype=torch.float32, device="cuda")
     st = torch.cuda.current_stream()
@@ -56,7 +65,7 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / args.reps
 
-    out = {"config": cfg.name, "prec": args.prec, "stats": plan.stats()}
+    out = {"config": cfg.name, "prec": args.prec, "factorised": args.fact, "stats": plan.stats()}
     what = args.what.split(",")
     if "copy" in what:
         # plain device copy of a known size: calibrates the HBM byte counters
@@ -73,6 +82,9 @@ def main():
         plan.apply_A(c, y)
         plan.apply_AT(y, g)
         out["HT_ms"] = timed(lambda: plan.band_only(1, g))
+    if "apply" in what:
+        out["apply_A_ms"] = timed(lambda: plan.apply_A(c, y))
+        out["apply_AT_ms"] = timed(lambda: plan.apply_AT(y, g))
     if "tv" in what:
         out["prox_tv_k20_ms"] = timed(lambda: plan.prox_tv(c, 0.01, 20, x=g))
     if "r3" in what:

@@ -107,3 +107,46 @@ def test_validation_before_device_work(lib):
     assert lib.psoam_solve_batch(0, None, None, None, None, None, None) == _lib.OK
     assert lib.psoam_plan_destroy(None) == _lib.OK
     assert lib.psoam_plan_geom(None, None) == _lib.EINVAL
+
+
+def test_factorised_validation_before_device_work(lib):
+    import numpy as np
+    from paper_2510_23739_amd import _lib
+    out = C.c_void_p(1)
+    sp = _lib.Species()
+    for s in range(2):
+        sp.tau[s] = 2.0
+    phi = np.ones(6, np.float32)
+    spr = np.ones((6, 3, 3), np.float32)
+    eir = np.array([0.5, 1.0, -0.5], np.float32)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+
+    def call(g, sh, spr_=spr, eir_=eir):
+        return lib.psoam_plan_create_factorised(C.byref(g), C.byref(sp), ptr(phi), ptr(spr_),
+                                                ptr(eir_), C.byref(sh), 0, None, C.byref(out))
+
+    g = _lib.Geom(4, 4, 6, 2, 3, 32, 3, 0, 0)
+    good = dict(dr=0.6, z_focus=2.5, t_focus=16, n_eir=3, eir_origin=1)
+    sh = lambda **kw: _lib.Shell(**{**good, **kw})
+    assert lib.psoam_plan_create_factorised(None, C.byref(sp), ptr(phi), ptr(spr), ptr(eir),
+                                            C.byref(sh()), 0, None, C.byref(out)) == _lib.EINVAL
+    assert out.value is None
+    assert call(g, sh(dr=0.0)) == _lib.EINVAL
+    assert call(g, sh(dr=float("inf"))) == _lib.EINVAL
+    assert call(g, sh(z_focus=float("nan"))) == _lib.EINVAL
+    assert call(g, sh(n_eir=0)) == _lib.EINVAL
+    assert call(g, sh(n_eir=33)) == _lib.EINVAL
+    assert call(g, sh(eir_origin=3)) == _lib.EINVAL
+    assert call(g, sh(eir_origin=-1)) == _lib.EINVAL
+    bad_eir = eir.copy()
+    bad_eir[2] = np.nan
+    assert call(g, sh(), eir_=bad_eir) == _lib.EINVAL
+    bad_spr = spr.copy()
+    bad_spr[3, 1, 2] = np.inf
+    assert call(g, sh(), spr_=bad_spr) == _lib.EINVAL
+    assert call(_lib.Geom(4, 4, 6, 2, 3, 32, 3, 0, 1), sh()) == _lib.EUNSUPPORTED
+    assert call(_lib.Geom(4, 4, 6, 2, 3, 4097, 3, 0, 0), sh()) == _lib.EUNSUPPORTED
+    assert call(_lib.Geom(4, 4, 6, 2, 3, 32, 4, 0, 0), sh()) == _lib.EINVAL
+    # a radius step so small that one voxel spans more than 64 samples
+    assert call(_lib.Geom(4, 4, 6, 2, 3, 400, 3, 0, 0), sh(dr=0.01, t_focus=200)) == _lib.EUNSUPPORTED
+    assert b"wider" in lib.psoam_last_error()

@@ -1,0 +1,192 @@
+"""The factorised acoustic operator (Sec. 2.2.3 "Acoustic Model": unit-weight
+discrete shells weighted by the spatial response image, then the temporal
+convolution with the electrical impulse response) through the library,
+against the oracle's apply_A_fact / apply_AT_fact: small ragged sizes with
+asymmetric random inputs, a focal sample outside the A-scan, long A-scans
+(the one-wave launch shape of the convolution pass), the small and the full
+workload (sampled A-scans and voxel columns, adjoint identity), FISTA, and a
+batch mixing it with a banded plan."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import nan_buf, oracle_S, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16": 8e-3, "fp16": 1.5e-3, "bf16_split": 2e-5, "fp16_split": 2e-5}
+
+
+class Fact:
+    """Inputs of one factorised problem (host arrays; the oracle's mask is
+    built from the same shell parameters)."""
+
+    def __init__(self, cfg, phi, sp, spr, eir, origin, dr, z_focus, t_focus):
+        self.cfg, self.phi, self.sp = cfg, phi, sp
+        self.spr, self.eir, self.origin = spr, eir, origin
+        self.dr, self.z_focus, self.t_focus = dr, z_focus, t_focus
+        self.S = oracle_S(cfg, phi, sp)
+        self.mask = oracle.shell_mask(cfg.nz, cfg.f, cfg.nt, dr, z_focus, t_focus)
+
+    def plan(self, prec):
+        import paper_2510_23739_amd as pk
+        c = self.cfg
+        return pk.Plan.factorised(c.nx, c.ny, c.nz, c.n_pulses, c.nt, c.f, self.phi, self.sp,
+                                  self.spr, self.eir, self.origin, self.dr, self.z_focus,
+                                  self.t_focus, prec=prec)
+
+    def A(self, c):
+        return oracle.apply_A_fact(c, self.S, self.spr, self.mask, self.eir, self.origin)
+
+    def AT(self, y):
+        return oracle.apply_AT_fact(y, self.S, self.spr, self.mask, self.eir, self.origin)
+
+
+def _ragged(which):
+    rng = np.random.default_rng(17)
+    nt = 1100 if which == "long" else 45
+    cfg = synth.Config("fact-ragged", nx=13, ny=7, nz=11, n_species=3, n_pulses=19, nt=nt, f=5,
+                       k1=6, k2=5, seed=17)
+    phi = rng.uniform(0.2, 1.0, size=(cfg.ny, cfg.nx, cfg.nz)).astype(np.float32)
+    spr = rng.uniform(0.1, 1.0, size=(cfg.nz, cfg.f, cfg.f)).astype(np.float32)
+    eir = rng.standard_normal(6).astype(np.float32)
+    t_focus = {"ragged": 20, "focus_before": -3, "focus_after": nt + 4, "long": 550}[which]
+    dr = 0.45 if which != "long" else 0.05
+    return Fact(cfg, phi, synth.species(3, gamma=1.0), spr, eir, 2, dr, 5.0, t_focus)
+
+
+def _standard(cfg):
+    dr, z_focus, t_focus = synth.shell_geometry(cfg.nz, cfg.nt)
+    eir, origin = synth.eir_taps()
+    return Fact(cfg, synth.phi_depth(cfg.nz), synth.species(cfg.n_species), synth.spr_table(cfg.nz, cfg.f),
+                eir, origin, dr, z_focus, t_focus)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16_split"])
+@pytest.mark.parametrize("which", ["ragged", "focus_before", "focus_after", "long", "c1"])
+def test_factorised_apply_matches_oracle(which, prec):
+    torch = torch_cuda()
+    F = _standard(synth.C1) if which == "c1" else _ragged(which)
+    cfg = F.cfg
+    rng = np.random.default_rng(3)
+    c = rng.uniform(0, 1, cfg.c_shape).astype(np.float32)
+    y = rng.standard_normal(cfg.y_shape).astype(np.float32)
+    say(f"[fact] {which} {prec}: building plan nt {cfg.nt} t_focus {F.t_focus} dr {F.dr}")
+    plan = F.plan(prec)
+    ya = nan_buf(cfg.y_shape)
+    plan.apply_A(torch.from_numpy(c).cuda(), ya)
+    ca = nan_buf(cfg.c_shape)
+    plan.apply_AT(torch.from_numpy(y).cuda(), ca)
+    ref_a, ref_t = F.A(c), F.AT(y)
+    assert np.abs(ref_a).max() > 0 and np.abs(ref_t).max() > 0
+    e_a = oracle.rel_err(ya.cpu().numpy(), ref_a)
+    e_t = oracle.rel_err(ca.cpu().numpy(), ref_t)
+    say(f"[fact] {which} {prec}: A {e_a:.3e}  A^T {e_t:.3e}")
+    assert e_a <= TOL[prec] and e_t <= TOL[prec]
+    plan.close()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return _standard(synth.C2)
+
+
+def _corners(n):
+    return [(0, 0), (0, n - 1), (n - 1, n - 1), (n - 1, 0)]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_factorised_c2_sampled_and_adjoint(c2, prec):
+    """Full workload (128 x 128 x 64, 3 species, 32 pulses, Nt 256, F 31):
+    sampled A-scans and voxel columns against the oracle (buffers start as
+    NaN), and <A x, y> = <x, A^T y> over the whole grid."""
+    torch = torch_cuda()
+    cfg = c2.cfg
+    c = synth.phantom(cfg).astype(np.float32)
+    y = np.random.default_rng(cfg.seed + 17).standard_normal(cfg.y_shape).astype(np.float32)
+    plan = c2.plan(prec)
+    Ls = oracle.shell_stack(c2.spr, c2.mask)
+    pts = _corners(128) + [(64, 64), (5, 120), (90, 33), (15, 16)]
+    xt, yt = torch.from_numpy(c).cuda(), torch.from_numpy(y).cuda()
+    ya = nan_buf(cfg.y_shape)
+    plan.apply_A(xt, ya)
+    assert bool(torch.isfinite(ya).all())
+    got = np.stack([ya[:, a, b, :].cpu().numpy() for a, b in pts])
+    ref = oracle.apply_A_fact_scans(c, c2.S, c2.spr, c2.mask, c2.eir, c2.origin, pts, Ls=Ls)
+    e_a = oracle.rel_err(got, ref)
+    ca = nan_buf(cfg.c_shape)
+    plan.apply_AT(yt, ca)
+    assert bool(torch.isfinite(ca).all())
+    got = np.stack([ca[:, a, b, :].cpu().numpy() for a, b in pts])
+    ref = oracle.apply_AT_fact_columns(y, c2.S, c2.spr, c2.mask, c2.eir, c2.origin, pts, Ls=Ls)
+    e_t = oracle.rel_err(got, ref)
+    lhs = float((ya.double() * yt.double()).sum())
+    rhs = float((xt.double() * ca.double()).sum())
+    scale = float(ya.double().norm() * yt.double().norm())
+    say(f"[fact] C2 {prec}: A-scans {e_a:.3e} columns {e_t:.3e} adjoint gap {abs(lhs - rhs) / scale:.3e}")
+    assert e_a <= TOL[prec] and e_t <= TOL[prec]
+    assert abs(lhs - rhs) <= (1e-6 if prec == "fp32" else 5e-3) * scale
+    plan.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 1e-2)])
+def test_factorised_fista_matches_oracle(prec, tol):
+    torch = torch_cuda()
+    F = _standard(synth.C1)
+    cfg = F.cfg
+    c_true, _, _, _, _, n0, v0 = synth.inputs(cfg)
+    yc = F.A(c_true.astype(np.float64))
+    p = (yc + synth.noise_sigma(float(np.sqrt(np.mean(yc ** 2)))) * n0).astype(np.float32)
+    aty = float(np.abs(F.AT(p.astype(np.float64))).max())
+    lam_tv, lam_l1 = 5e-3 * aty, 1e-2 * aty
+    alpha1 = 1.0 / (1.01 * oracle.power_iteration(F.A, F.AT, v0, 30))
+    k1, k2 = 10, 10
+    tr_ref = []
+    c_ref, _ = oracle.fista(p.astype(np.float64), F.A, F.AT, alpha1, lam_tv, lam_l1, k1, k2,
+                            shape_c=cfg.c_shape, trace=tr_ref)
+    plan = F.plan(prec)
+    c, st, tr = plan.solve(torch.from_numpy(p).cuda(), lambda_tv=lam_tv, lambda_l1=lam_l1, k1=k1,
+                           k2=k2, alpha1=alpha1, trace=True)
+    e = oracle.rel_err(c.cpu().numpy(), c_ref)
+    say(f"[fact] FISTA C1 {prec}: rel err c {e:.3e}; F {tr[-1]:.6e} vs {tr_ref[-1]:.6e}")
+    assert st["iterations"] == k1
+    assert e <= tol
+    np.testing.assert_allclose(tr, tr_ref, rtol=10 * tol)
+    # the solver's own step estimate (power iteration through the same kernels)
+    _, st2 = plan.solve(torch.from_numpy(p).cuda(), k1=0, n_power=30,
+                        v0=torch.from_numpy(v0.astype(np.float32)).cuda())
+    lam_ref = 1.0 / (1.01 * alpha1)
+    say(f"[fact] power iteration {prec}: {st2['lambda_max']:.6e} vs oracle {lam_ref:.6e}")
+    assert st2["lambda_max"] == pytest.approx(lam_ref, rel=10 * tol)
+    plan.close()
+
+
+def test_factorised_in_a_batch_matches_one_by_one():
+    torch = torch_cuda()
+    import paper_2510_23739_amd as pk
+    from gpu_common import lib_plan, ragged_cfg
+    F = _ragged("ragged")
+    cfg2, t02, taps2, phi2, sp2 = ragged_cfg(4)
+    plans = [F.plan("bf16"), lib_plan(cfg2, t02, taps2, phi2, sp2, "fp32")]
+    ps, opts, ref = [], [], []
+    for i, pl in enumerate(plans):
+        p = torch.from_numpy(np.random.default_rng(80 + i).standard_normal(pl.y_shape)
+                             .astype(np.float32)).cuda()
+        o = dict(lambda_tv=0.05, lambda_l1=0.02, k1=5, k2=4, alpha1=1e-3)
+        c, _ = pl.solve(p, **o)
+        ps.append(p)
+        opts.append(o)
+        ref.append(c.clone())
+    for call in range(2):
+        cs = [torch.zeros(pl.c_shape, dtype=torch.float32, device="cuda") for pl in plans]
+        pk.solve_batch(plans, ps, cs, opts)
+        torch.cuda.synchronize()
+        for c, r in zip(cs, ref):
+            assert torch.equal(c, r)
+        plans[0].apply_A(cs[0])
+        torch.cuda.synchronize()
+    for pl in plans:
+        pl.close()
