@@ -1,7 +1,9 @@
 """Parity at the full sizes, in the launch configuration the benchmark times.
 
 128 x 128 x 64 voxels, 3 species, 32 pulses, Nt 256, footprint 31 x 31 (the
-benchmark workload) and 256 x 256 x 96, 32 pulses, Nt 384, footprint 41 x 41:
+benchmark workload), 256 x 256 x 96, 32 pulses, Nt 384, footprint 41 x 41,
+320 x 320 x 128, 40 pulses, Nt 512, footprint 51 x 51, and two instances of
+the batched family:
 A and A^T through the library, compared with the FP64 oracle on outputs the
 oracle evaluates one by one (A-scans at chosen scan positions, A^T at chosen
 voxel columns, including the grid corners where the footprint is cut), every
@@ -141,3 +143,56 @@ def test_c2_first_iteration_sampled(c2, prec):
     say(f"[full] C2 first solver iteration {prec}: rel err {e:.3e}")
     assert e <= 3 * TOL[prec]
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# the largest single solve (320 x 320 x 128, 3 species, 40 pulses, Nt 512,
+# footprint 51 x 51) and two instances of the batched family, in the
+# precision and launch configuration the benchmark times (BF16).  Inputs are
+# seeded uniform values (the tube phantom takes longer to draw at this size
+# than the check itself); outputs start as NaN, so a tile left unwritten
+# fails the finiteness check.
+# ---------------------------------------------------------------------------
+def _uniform_problem(cfg):
+    t0, taps = synth.sir_table(cfg.nz, cfg.f, cfg.nt)
+    phi = synth.phi_depth(cfg.nz)
+    sp = synth.species(cfg.n_species)
+    rng = np.random.default_rng(cfg.seed + 5)
+    c = rng.random(cfg.c_shape, dtype=np.float32)
+    y = rng.random(cfg.y_shape, dtype=np.float32)
+    y -= 0.5
+    S = oracle_S(cfg, phi, sp)
+    Hs = oracle.band_stack(t0, taps, cfg.nt)
+    return t0, taps, phi, sp, c, S, Hs, y
+
+
+@pytest.fixture(scope="module")
+def c5():
+    cfg = synth.C5
+    return (cfg,) + _uniform_problem(cfg)
+
+
+def test_c5_apply_A_sampled(c5):
+    torch = torch_cuda()
+    n = c5[0].nx
+    assert _check_A(torch, c5, "bf16", [(0, 0), (n - 1, n // 3), (n // 2, n // 2)]) <= TOL["bf16"]
+
+
+def test_c5_apply_AT_sampled(c5):
+    torch = torch_cuda()
+    n = c5[0].nx
+    assert _check_AT(torch, c5, "bf16", [(n - 1, 0), (n // 2, n // 2 + 7)]) <= TOL["bf16"]
+
+
+@pytest.mark.parametrize("inst", [8, 4])
+def test_batched_family_instance_sampled(inst):
+    """Instance 8 (191 x 191 x 51, 22 pulses, Nt 320) and 4 (89 x 89 x 59,
+    48 pulses, Nt 352): neither lateral size is a multiple of the position
+    block, and 48 pulses fill three 16-pulse blocks."""
+    torch = torch_cuda()
+    cfg = synth.c4_instance(inst)
+    data = (cfg,) + _uniform_problem(cfg)
+    n = cfg.nx
+    pts = [(0, n - 1), (n - 1, n - 1), (n // 2, 3), (n - 2, n // 2)]
+    assert _check_A(torch, data, "bf16", pts) <= TOL["bf16"]
+    assert _check_AT(torch, data, "bf16", pts) <= TOL["bf16"]
