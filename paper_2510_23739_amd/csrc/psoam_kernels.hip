@@ -314,6 +314,15 @@ __device__ __forceinline__ void zero_acc(f32x4 (&acc)[NP]) {
   for (int p = 0; p < NP; ++p) acc[p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 }
 
+// Block index with the blocks of each XCD made contiguous: the hardware deals
+// blocks to the 8 XCDs round-robin, so block b runs on XCD b % 8; mapping it
+// to (b % 8) * (n / 8) + b / 8 gives every XCD one contiguous range of tiles,
+// whose neighbours (stencil halos) then come from that XCD's own L2.
+__device__ __forceinline__ int xcd_block() {
+  const int n = (int)gridDim.x, b = (int)blockIdx.x;
+  return (n & 7) == 0 ? (b & 7) * (n >> 3) + (b >> 3) : b;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -1132,7 +1141,9 @@ __global__ __launch_bounds__(256) void tv_step_kernel(float* __restrict__ un,
   __shared__ float s_w[EY * EX * EZ];
   const int nzb = (G.nz + kTvZ - 1) / kTvZ, nxb = (G.nx + kTvX - 1) / kTvX;
   const int nyb = (G.ny + kTvY - 1) / kTvY;
-  int bb = blockIdx.x;
+  // a tile's z, x and y neighbours (whose duals it reads as halo) mostly run
+  // from the same L2
+  int bb = xcd_block();
   const int zb = bb % nzb;
   bb /= nzb;
   const int xb = bb % nxb;
