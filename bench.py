@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--no-scales", action="store_true",
                     help="skip the 256x256x96 / 320x320x128 applies and the 16-problem batch")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline plan (no separable, two-step or factorised forms, "
+                         "no larger workloads): every band-kernel launch of a profiled run then "
+                         "belongs to the headline plan")
     return ap.parse_args()
 
 
@@ -383,7 +387,7 @@ def main():
     # the separable fast form (valid only for this workload's fluence-independent
     # rate, gamma = 0), reported apart from the general path
     sep = None
-    if sp.gamma == 0.0:
+    if sp.gamma == 0.0 and not args.headline_only:
         log(f"[bench] separable form {args.prec}")
         rs = run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1,
                       args.prec, args.steps, args.warmup, args.kernel_reps, separable=True)
@@ -461,6 +465,11 @@ def main():
         "precisions": per_prec,
         "separable_form": sep,
     }
+    if args.headline_only:
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(cfg, t0, taps, phi, sp, args.cpu_crop, args.steps)
+        print(json.dumps(out), flush=True)
+        return
     # the two-step method (the paper's comparison): acoustic inversion of the
     # K pulse volumes with TV, then per-voxel unmixing with l1 + TV
     log("[bench] two-step method")
