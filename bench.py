@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "A+Aᵀ applies/s & FISTA s-to-tol, BF16-MFMA vs FP32, at rel err ≤1e-3"
 PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "bf16_split": 2500.0, "fp16_split": 2500.0,
-               "fp32": 157.3}
+               "bf16_refined": 2500.0, "fp32": 157.3}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -39,8 +39,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", default="bf16")
-    ap.add_argument("--compare", default="fp16,bf16_split,fp16_split,fp32",
+    ap.add_argument("--prec", default="bf16_refined")
+    ap.add_argument("--compare", default="bf16,fp16,bf16_split,fp16_split,fp32",
                     help="other precisions reported beside, comma separated ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c1-oracle", action="store_true",
@@ -243,7 +243,7 @@ def profiled_traffic():
     """HBM bytes per launch of the H kernel from the committed counter summary,
     valid only while the kernel and plan sources hash to what was profiled."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "band16_lds_H_C2_bf16_hbm.md")
+    path = os.path.join(ROOT, "profiles", "band16_lds_H_C2_bf16_refined_hbm.md")
     if not os.path.exists(path):
         return None, "no counter summary"
     want = {}
@@ -448,7 +448,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.prec,
+        "dtype": "fp16" if args.prec.startswith("fp16") else ("fp32" if args.prec == "fp32" else "bf16"),
+        "precision_mode": args.prec,
         "data": "synthetic: seeded tube phantom, synthesized focused-transducer impulse response, 20 dB noise",
         "config": {"workload": "128x128x64 voxels, 3 species, 32 pulses, Nt 256, footprint 31x31, "
                                "K2 20; step = one solver iteration (A, A^T, TV prox, l1, momentum)",

@@ -44,13 +44,21 @@ enum {
 /* Arithmetic of the acoustic contraction (H and its adjoint).  FP32 runs
  * float32 matrix cores; BF16/FP16 round both operands to 16 bits and
  * accumulate in float32; the _SPLIT forms add the low-order parts of both
- * operands (three products per tile) for about 16 significant bits. */
+ * operands (three products per tile) for about 16 significant bits.
+ * BF16_REFINED is BF16 plus the low-order BF16 part of the impulse-response
+ * table for the columns (z, jdy, jdx) that carry most of the table's
+ * rounding error: the fewest columns, by decreasing squared rounding error,
+ * whose squared errors sum to at least 90% of the table's, chosen in FP64 at
+ * plan creation.  Those corrections run as extra matrix-core tiles on the
+ * same operand windows; H and H^T use the same columns, so they stay exact
+ * transposes of each other. */
 typedef enum {
   PSOAM_FP32 = 0,
   PSOAM_BF16 = 1,
   PSOAM_FP16 = 2,
   PSOAM_BF16_SPLIT = 3,
-  PSOAM_FP16_SPLIT = 4
+  PSOAM_FP16_SPLIT = 4,
+  PSOAM_BF16_REFINED = 5
 } psoam_prec;
 
 /* Geometry of one reconstruction. */

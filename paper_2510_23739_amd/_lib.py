@@ -8,7 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpsoam.so")
 
 OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM, EDIVERGED = range(6)
-PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16_split": 3, "fp16_split": 4}
+PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16_split": 3, "fp16_split": 4, "bf16_refined": 5}
 
 
 class Geom(C.Structure):

@@ -847,7 +847,8 @@ hipError_t launch_switch_fwd(const psoam_plan* P, const float* c, hipStream_t s)
                        g.nz, P->Lz / 8, P->Kp, P->Xp, P->R, P->ps_b);                       \
     break;                                                                                  \
   }
-    case PSOAM_BF16: PSOAM_SW16(PSOAM_BF16, false)
+    case PSOAM_BF16:
+    case PSOAM_BF16_REFINED: PSOAM_SW16(PSOAM_BF16, false)
     case PSOAM_FP16: PSOAM_SW16(PSOAM_FP16, false)
     case PSOAM_BF16_SPLIT: PSOAM_SW16(PSOAM_BF16, true)
     case PSOAM_FP16_SPLIT: PSOAM_SW16(PSOAM_FP16, true)
@@ -876,7 +877,8 @@ hipError_t launch_pack_r(const psoam_plan* P, const float* y, hipStream_t s) {
                        P->Kp, P->Xp, P->R, P->ps_r, vec4);                                  \
     break;                                                                                  \
   }
-    case PSOAM_BF16: PSOAM_PK16(PSOAM_BF16, false)
+    case PSOAM_BF16:
+    case PSOAM_BF16_REFINED: PSOAM_PK16(PSOAM_BF16, false)
     case PSOAM_FP16: PSOAM_PK16(PSOAM_FP16, false)
     case PSOAM_BF16_SPLIT: PSOAM_PK16(PSOAM_BF16, true)
     case PSOAM_FP16_SPLIT: PSOAM_PK16(PSOAM_FP16, true)
@@ -951,7 +953,8 @@ static hipError_t launch_band_lds(const psoam_plan* P, const BandTable& T, BandA
     break;                                                                                  \
   }
   switch (P->prec) {
-    case PSOAM_BF16: PSOAM_LDS(PSOAM_BF16, false)
+    case PSOAM_BF16:
+    case PSOAM_BF16_REFINED: PSOAM_LDS(PSOAM_BF16, false)
     case PSOAM_FP16: PSOAM_LDS(PSOAM_FP16, false)
     case PSOAM_BF16_SPLIT: PSOAM_LDS(PSOAM_BF16, true)
     case PSOAM_FP16_SPLIT: PSOAM_LDS(PSOAM_FP16, true)
@@ -990,7 +993,8 @@ static hipError_t launch_band_mode(const psoam_plan* P, BandArgs& A, dim3 grid, 
     }                                                                                       \
     break;                                                                                  \
   }
-    case PSOAM_BF16: PSOAM_B16(PSOAM_BF16, false)
+    case PSOAM_BF16:
+    case PSOAM_BF16_REFINED: PSOAM_B16(PSOAM_BF16, false)
     case PSOAM_FP16: PSOAM_B16(PSOAM_FP16, false)
     case PSOAM_BF16_SPLIT: PSOAM_B16(PSOAM_BF16, true)
     case PSOAM_FP16_SPLIT: PSOAM_B16(PSOAM_FP16, true)

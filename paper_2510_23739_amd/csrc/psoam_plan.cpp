@@ -52,6 +52,7 @@ inline float from_f16(uint16_t u) {
 
 struct Group {
   int jy, jx, l;  // lateral offset indices (already flipped for H^T) and contracted index
+  int layer = 0;  // 0: the band values; 1: their low-order BF16 parts (refined BF16)
 };
 
 }  // namespace
@@ -76,8 +77,11 @@ const char* last_error_cstr() { return g_last_error.c_str(); }
 // Two packings of the same band blocks: chunks per output tile (global-operand
 // kernel, offsets relative to the position base) and, for 16-bit operands,
 // chunks per (tile, dy) for the LDS-staged kernel (groups as octet << 16 | dx).
+// refine: per column (z, jdy, jdx), 1 where the refined BF16 form adds the
+// low-order part of the column's band values as a second layer of groups
+// (null for every other precision).
 static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* taps,
-                       BandTable& T) {
+                       const uint8_t* refine, BandTable& T) {
   const auto& g = P->g;
   const int F = P->F, W = P->W;
   const bool half = P->prec != PSOAM_FP32;
@@ -89,9 +93,13 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   const int lc = dir == 0 ? P->Lz : P->Lt;         // padded contracted length
   const int n_l = lc / gw;                         // groups along the contracted axis
   const size_t ps = dir == 0 ? P->ps_b : P->ps_r;
-  // mark[(tile*F + jy)*F + jx][l]
+  // mark[layer][(tile*F + jy)*F + jx][l]
   const size_t n_off = (size_t)F * F;
-  std::vector<uint8_t> mark((size_t)n_mt * n_off * n_l, 0);
+  const size_t layer_sz = (size_t)n_mt * n_off * n_l;
+  const int n_layers = refine ? 2 : 1;
+  std::vector<uint8_t> mark(layer_sz * n_layers, 0);
+  // low-order BF16 part of a band value (second layer of the refined form)
+  auto low = [](float v) { return v - from_bf16(to_bf16(v)); };
   size_t useful = 0;
   for (int z = 0; z < g.nz; ++z)
     for (int jdy = 0; jdy < F; ++jdy)
@@ -109,6 +117,8 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
             tile = z / 16; jy = F - 1 - jdy; jx = F - 1 - jdx; l = t / gw;
           }
           mark[((size_t)tile * n_off + (size_t)jy * F + jx) * n_l + l] = 1;
+          if (refine && refine[col] && low(v) != 0.0f)
+            mark[layer_sz + ((size_t)tile * n_off + (size_t)jy * F + jx) * n_l + l] = 1;
         }
       }
   T.n_mtiles = n_mt;
@@ -128,7 +138,8 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
           const int t = t0[col] + j;
           if (t < tile * 16 || t >= tile * 16 + 16 || t >= g.nt) continue;
           const int lane = 16 * gi + (t - tile * 16);
-          vals[((size_t)c * 64 + lane) * gw + e] = taps[col * W + j];
+          const float v = taps[col * W + j];
+          vals[((size_t)c * 64 + lane) * gw + e] = G.layer ? low(v) : v;
         }
       }
     } else {
@@ -140,7 +151,8 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
           const int t = t0[col] + j;
           if (t < 0 || t >= g.nt || t / gw != G.l) continue;
           const int lane = 16 * gi + zi;
-          vals[((size_t)c * 64 + lane) * gw + (t - G.l * gw)] = taps[col * W + j];
+          const float v = taps[col * W + j];
+          vals[((size_t)c * 64 + lane) * gw + (t - G.l * gw)] = G.layer ? low(v) : v;
         }
       }
     }
@@ -185,10 +197,12 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   std::vector<Group> chunk_groups;  // 4 per chunk
   for (int tile = 0; tile < n_mt; ++tile) {
     groups.clear();
-    for (int jy = 0; jy < F; ++jy)
-      for (int jx = 0; jx < F; ++jx)
-        for (int l = 0; l < n_l; ++l)
-          if (mark[((size_t)tile * n_off + (size_t)jy * F + jx) * n_l + l]) groups.push_back({jy, jx, l});
+    for (int layer = 0; layer < n_layers; ++layer)
+      for (int jy = 0; jy < F; ++jy)
+        for (int jx = 0; jx < F; ++jx)
+          for (int l = 0; l < n_l; ++l)
+            if (mark[layer * layer_sz + ((size_t)tile * n_off + (size_t)jy * F + jx) * n_l + l])
+              groups.push_back({jy, jx, l, layer});
     const int nch = (int)((groups.size() + 3) / 4);
     T.h_start[tile + 1] = T.h_start[tile] + nch;
     for (int i = 0; i < nch * 4; ++i)
@@ -227,7 +241,7 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   // first); a lane shorter than the run is placed so that its idle chunks
   // still address columns inside [0, F) (with zero band values).
   const int run_max = std::max(1, std::min(kRunMax, (F + 1) / 2));
-  struct Piece { int l, lo, len; };
+  struct Piece { int l, lo, len, layer; };
   std::vector<int> rstart((size_t)n_mt * F + 1, 0);
   std::vector<uint32_t> rgrp;   // 4 per run: octet << 16 | dx at the run's first chunk
   std::vector<int> rlen, rcb;   // run length, first chunk index
@@ -239,16 +253,20 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
     for (int jy = 0; jy < F; ++jy) {
       const size_t key = (size_t)tile * F + jy;
       pieces.clear();
-      for (int l = 0; l < n_l; ++l) {
-        int jx = 0;
-        while (jx < F) {
-          if (!mark[((size_t)tile * n_off + (size_t)jy * F + jx) * n_l + l]) { ++jx; continue; }
-          int e = jx;
-          while (e + 1 < F && mark[((size_t)tile * n_off + (size_t)jy * F + e + 1) * n_l + l]) ++e;
-          for (int lo = jx; lo <= e; lo += run_max) pieces.push_back({l, lo, std::min(run_max, e - lo + 1)});
-          lo_l[key] = std::min(lo_l[key], l);
-          hi_l[key] = std::max(hi_l[key], l);
-          jx = e + 1;
+      for (int layer = 0; layer < n_layers; ++layer) {
+        const uint8_t* mk = mark.data() + layer * layer_sz;
+        for (int l = 0; l < n_l; ++l) {
+          int jx = 0;
+          while (jx < F) {
+            if (!mk[((size_t)tile * n_off + (size_t)jy * F + jx) * n_l + l]) { ++jx; continue; }
+            int e = jx;
+            while (e + 1 < F && mk[((size_t)tile * n_off + (size_t)jy * F + e + 1) * n_l + l]) ++e;
+            for (int lo = jx; lo <= e; lo += run_max)
+              pieces.push_back({l, lo, std::min(run_max, e - lo + 1), layer});
+            lo_l[key] = std::min(lo_l[key], l);
+            hi_l[key] = std::max(hi_l[key], l);
+            jx = e + 1;
+          }
         }
       }
       std::stable_sort(pieces.begin(), pieces.end(),
@@ -257,11 +275,12 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
         const int m = pieces[i].len;
         rlen.push_back(m);
         rcb.push_back(l_chunks);
-        int dstart[4], lane_l[4], first[4], len[4];
+        int dstart[4], lane_l[4], first[4], len[4], lane_layer[4];
         for (int gi = 0; gi < 4; ++gi) {
           if (i + gi < pieces.size()) {
             const Piece& pc = pieces[i + gi];
             lane_l[gi] = pc.l;
+            lane_layer[gi] = pc.layer;
             len[gi] = pc.len;
             if (pc.lo + m - 1 <= F - 1) {        // piece at the end of the run
               dstart[gi] = pc.lo + m - 1;
@@ -273,6 +292,7 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
             }
           } else {                               // idle lane: zero band, valid columns
             lane_l[gi] = pieces[i].l;
+            lane_layer[gi] = 0;
             len[gi] = 0;
             dstart[gi] = m - 1;
             first[gi] = 0;
@@ -282,7 +302,7 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
         for (int c = 0; c < m; ++c) {
           for (int gi = 0; gi < 4; ++gi) {
             const bool on = c >= first[gi] && c < first[gi] + len[gi];
-            lgroups.push_back(on ? Group{jy, dstart[gi] - c, lane_l[gi]} : Group{-1, -1, -1});
+            lgroups.push_back(on ? Group{jy, dstart[gi] - c, lane_l[gi], lane_layer[gi]} : Group{-1, -1, -1});
           }
           ++l_chunks;
         }
@@ -510,7 +530,7 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
   if (sir_w < 1 || sir_w > 64) return fail(PSOAM_EINVAL, "plan_create: sir_w must be in 1..64");
   if (g.phi_per_voxel != 0 && g.phi_per_voxel != 1)
     return fail(PSOAM_EINVAL, "plan_create: phi_per_voxel must be 0 or 1");
-  if (prec < PSOAM_FP32 || prec > PSOAM_FP16_SPLIT)
+  if (prec < PSOAM_FP32 || prec > PSOAM_BF16_REFINED)
     return fail(PSOAM_EUNSUPPORTED, "plan_create: unknown precision");
   if (g.n_pulses > 64) return fail(PSOAM_EUNSUPPORTED, "plan_create: at most 64 pulses");
   for (int s = 0; s < (diag ? 0 : g.n_species); ++s) {
@@ -617,9 +637,36 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
     PLAN_HIP(hipMemsetAsync(P->d_bq_lo, 0, P->bq_bytes, stream));
     PLAN_HIP(hipMemsetAsync(P->d_rq_lo, 0, P->rq_bytes, stream));
   }
-  rc = build_table(P, 0, t0, taps, P->fwd);
+  // refined BF16: the fewest columns, by decreasing squared rounding error of
+  // their band values, that hold 90% of the table's squared rounding error
+  std::vector<uint8_t> refine;
+  if (prec == PSOAM_BF16_REFINED) {
+    const size_t ncol = (size_t)g.nz * g.f * g.f;
+    std::vector<double> err(ncol, 0.0);
+    double tot = 0.0;
+    for (size_t col = 0; col < ncol; ++col) {
+      for (int j = 0; j < sir_w; ++j) {
+        const int t = t0[col] + j;
+        if (t < 0 || t >= g.nt) continue;
+        const double e = (double)taps[col * sir_w + j] - (double)from_bf16(to_bf16(taps[col * sir_w + j]));
+        err[col] += e * e;
+      }
+      tot += err[col];
+    }
+    std::vector<size_t> idx(ncol);
+    for (size_t i = 0; i < ncol; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return err[a] > err[b]; });
+    refine.assign(ncol, 0);
+    double acc = 0.0;
+    for (size_t i = 0; i < ncol && acc < 0.9 * tot; ++i) {
+      refine[idx[i]] = 1;
+      acc += err[idx[i]];
+    }
+  }
+  const uint8_t* rf = refine.empty() ? nullptr : refine.data();
+  rc = build_table(P, 0, t0, taps, rf, P->fwd);
   if (rc != PSOAM_OK) return bail(rc);
-  rc = build_table(P, 1, t0, taps, P->adj);
+  rc = build_table(P, 1, t0, taps, rf, P->adj);
   if (rc != PSOAM_OK) return bail(rc);
   PLAN_HIP(hipStreamSynchronize(stream));
 #undef PLAN_HIP

@@ -66,6 +66,7 @@ def test_validation_before_device_work(lib):
     assert lib.psoam_plan_create(*args(bad_s)) == _lib.EINVAL
     assert lib.psoam_plan_create(*args(g, w=0)) == _lib.EINVAL
     assert lib.psoam_plan_create(*args(g, prec=7)) == _lib.EUNSUPPORTED
+    assert lib.psoam_plan_create(*args(g, prec=6)) == _lib.EUNSUPPORTED
     # tau must be positive
     assert lib.psoam_plan_create(*args(g)) == _lib.EINVAL
     assert b"tau" in lib.psoam_last_error()
