@@ -39,8 +39,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", default="bf16_refined")
-    ap.add_argument("--compare", default="bf16,fp16,bf16_split,fp16_split,fp32",
+    ap.add_argument("--prec", default="bf16")
+    ap.add_argument("--compare", default="bf16_refined,fp16,bf16_split,fp16_split,fp32",
                     help="other precisions reported beside, comma separated ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c1-oracle", action="store_true",
@@ -243,7 +243,7 @@ def profiled_traffic():
     """HBM bytes per launch of the H kernel from the committed counter summary,
     valid only while the kernel and plan sources hash to what was profiled."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "band16_lds_H_C2_bf16_refined_hbm.md")
+    path = os.path.join(ROOT, "profiles", "band16_lds_H_C2_bf16_hbm.md")
     if not os.path.exists(path):
         return None, "no counter summary"
     want = {}

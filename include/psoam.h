@@ -45,6 +45,10 @@ enum {
  * float32 matrix cores; BF16/FP16 round both operands to 16 bits and
  * accumulate in float32; the _SPLIT forms add the low-order parts of both
  * operands (three products per tile) for about 16 significant bits.
+ * BF16 rounds the impulse-response table with error feedback along dy (for
+ * each dx, sample and depth, the rounding error of an entry is added to the
+ * next entry inside the band before it is rounded), so that the table's
+ * errors cancel in sums over neighbouring lateral offsets.
  * BF16_REFINED is BF16 plus the low-order BF16 part of the impulse-response
  * table for the columns (z, jdy, jdx) that carry most of the table's
  * rounding error: the fewest columns, by decreasing squared rounding error,

@@ -664,9 +664,39 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
     }
   }
   const uint8_t* rf = refine.empty() ? nullptr : refine.data();
-  rc = build_table(P, 0, t0, taps, rf, P->fwd);
+  // BF16: the band values are rounded with error feedback along dy.  For each
+  // (dx, t, z), walking dy = -R .. R over the entries inside the band, every
+  // entry is rounded (to nearest) after adding the rounding error carried
+  // from the previous one, so the table's errors cancel in sums over nearby
+  // lateral offsets, which is how they reach images that are smooth on the
+  // scale of the beam.  Every entry stays a BF16 value within about one unit
+  // in the last place of the exact one; H and H^T read the same table.
+  std::vector<float> tq;
+  const float* tab = taps;
+  if (prec == PSOAM_BF16) {
+    const int F = g.f;
+    tq.assign(taps, taps + (size_t)g.nz * F * F * sir_w);
+    for (int z = 0; z < g.nz; ++z)
+      for (int jx = 0; jx < F; ++jx)
+        for (int t = 0; t < g.nt; ++t) {
+          double e = 0.0;
+          for (int jy = 0; jy < F; ++jy) {
+            const size_t col = ((size_t)z * F + jy) * F + jx;
+            const int j = t - t0[col];
+            if (j < 0 || j >= sir_w) continue;
+            const float v = taps[col * sir_w + j];
+            if (v == 0.0f) continue;
+            const double w = (double)v + e;
+            const float r = from_bf16(to_bf16((float)w));
+            tq[col * sir_w + j] = r;
+            e = w - (double)r;
+          }
+        }
+    tab = tq.data();
+  }
+  rc = build_table(P, 0, t0, tab, rf, P->fwd);
   if (rc != PSOAM_OK) return bail(rc);
-  rc = build_table(P, 1, t0, taps, rf, P->adj);
+  rc = build_table(P, 1, t0, tab, rf, P->adj);
   if (rc != PSOAM_OK) return bail(rc);
   PLAN_HIP(hipStreamSynchronize(stream));
 #undef PLAN_HIP

@@ -174,7 +174,7 @@ def test_power_iteration_matches_oracle(c1):
     assert st["alpha1"] == pytest.approx(1.0 / (1.01 * lam_ref), rel=1e-5)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16_split", 1e-4), ("bf16", 1e-2),
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16_split", 1e-4), ("bf16", 1e-3),
                                       ("fp16", 1e-3), ("bf16_refined", 1e-3)])
 def test_fista_C1_matches_oracle(c1, prec, tol):
     """C1 end to end: 20 FISTA iterations, 20 dual TV iterations, TV + l1 +
