@@ -688,7 +688,9 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
             if (v == 0.0f) continue;
             const double w = (double)v + e;
             const float r = from_bf16(to_bf16((float)w));
-            tq[col * sir_w + j] = r;
+            // an entry that rounds to zero (values near the float32 underflow)
+            // keeps its place in the band, as without the feedback
+            tq[col * sir_w + j] = r != 0.0f ? r : v;
             e = w - (double)r;
           }
         }
