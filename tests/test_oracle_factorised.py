@@ -35,17 +35,11 @@ def _sphere_points(radius, h):
     return np.concatenate(pts)            # columns: y, x, z offsets from the focus
 
 
-def _box_dist(p, cy, cx, cz):
-    """Distance from points p [n,3] to the unit box centred at (cy, cx, cz)."""
-    d = np.maximum(np.abs(p - np.array([cy, cx, cz])) - 0.5, 0.0)
-    return np.sqrt((d * d).sum(axis=1))
-
-
 @pytest.mark.parametrize("nz,z_focus", [(8, 3.5), (7, 3.0)])
 def test_shell_mask_matches_sampled_spheres(nz, z_focus):
     f, nt, dr, t_focus = 7, 22, 0.6, 11
     R = (f - 1) // 2
-    h = 0.02
+    h = 0.05
     mask = oracle.shell_mask(nz, f, nt, dr, z_focus, t_focus)
     for t in range(nt):
         rho = abs(t - t_focus) * dr
@@ -66,8 +60,13 @@ def test_shell_mask_matches_sampled_spheres(nz, z_focus):
         hit[vz[ok], vy[ok] + R, vx[ok] + R] = True
         assert not (hit & ~mask[t]).any(), f"sample {t}: a crossed voxel is missing"
         # every member is within the sampling gap of the sphere
-        for (z, jy, jx) in zip(*np.nonzero(mask[t])):
-            assert _box_dist(pts, jy - R, jx - R, z - z_focus).min() <= h, (t, z, jy, jx)
+        mem = np.argwhere(mask[t])                       # (z, jy, jx)
+        centres = np.stack([mem[:, 1] - R, mem[:, 2] - R, mem[:, 0] - z_focus], axis=1)
+        for k in range(0, len(centres), 16):
+            c = centres[k:k + 16]
+            d = np.maximum(np.abs(pts[:, None, :] - c[None, :, :]) - 0.5, 0.0)
+            dist = np.sqrt((d * d).sum(axis=2)).min(axis=0)
+            assert (dist <= h).all(), (t, mem[k:k + 16][dist > h])
         # the sides never mix
         dz = np.arange(nz) - z_focus
         assert not mask[t][(dz < 0) if lower else (dz >= 0)].any()
