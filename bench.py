@@ -71,11 +71,22 @@ def time_events(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(cfg, t0, taps, phi, sp, crop, steps_hint):
-    """The FP64 oracle, as it stands, timed on the host for one solver step
-    (A, A^T, TV prox with K2 inner steps, l1, momentum) on a crop x crop
-    lateral sample of the same geometry; scaled by the number of (scan,
-    offset) pairs evaluated, which is what the oracle's time follows."""
+SCANS = [(5, 7), (64, 64), (127, 0), (90, 33)]   # A-scans compared with the oracle
+
+
+def cpu_baseline_leg(torch, pk, cfg, t0, taps, phi, sp, c_true, crop, samples, fact, precs,
+                     with_c1):
+    """The CPU leg: the only part of the benchmark that runs the FP64 oracle.
+
+    1. The oracle, as it stands, timed on the host for one solver step (A,
+       A^T, TV prox with K2 inner steps, l1, momentum) on a crop x crop
+       lateral sample of the same geometry, scaled by the number of (scan,
+       offset) pairs evaluated, which is what the oracle's time follows.
+    2. The accuracy statements: the A-scans the GPU legs kept (`samples`,
+       `fact`) against the oracle's, and for each precision the GPU solve of
+       the 32x32x16 problem against the oracle's FISTA, on measurements and a
+       step both made by the oracle.
+    Returns (cpu_baseline dict, accuracy dict)."""
     import oracle
     import synth
     try:
@@ -98,11 +109,41 @@ def cpu_baseline(cfg, t0, taps, phi, sp, crop, steps_hint):
         return sum(max(0, n - abs(d)) for d in range(-cfg.r, cfg.r + 1))
     scale = (pairs(cfg.nx) * pairs(cfg.ny)) / float(pairs(crop) ** 2)
     step_s = dt * scale
-    return {"value": 1.0 / step_s, "unit": "A+AT applies/s", "cores": int(cores), "kind": "oracle",
+    base = {"value": 1.0 / step_s, "unit": "A+AT applies/s", "cores": int(cores), "kind": "oracle",
             "sample": (f"one FP64 oracle solver step (A, A^T, TV prox K2={cfg.k2}, l1, momentum) on a "
                        f"{crop}x{crop}-scan lateral crop (full Nz, K, Nt, F), {dt:.1f} s, scaled "
                        f"x{scale:.1f} by the number of (scan, offset) pairs to {cfg.nx}x{cfg.ny} "
                        f"scans (extrapolated)")}
+    acc = {"A": {}, "c_C1": {}, "factorised_A": None}
+    y_s = oracle.apply_A_scans(c_true, S, t0, taps, cfg.nt, SCANS)
+    for q, y_g in samples.items():
+        acc["A"][q] = oracle.rel_err(y_g, y_s)
+    if fact is not None:
+        mask = oracle.shell_mask(cfg.nz, cfg.f, cfg.nt, fact["dr"], fact["z_focus"], fact["t_focus"])
+        y_f = oracle.apply_A_fact_scans(c_true, S, fact["spr"], mask, fact["eir"], fact["origin"],
+                                        SCANS)
+        acc["factorised_A"] = oracle.rel_err(fact["y"], y_f)
+    if with_c1:
+        c1 = synth.C1
+        c1_true, t01, taps1, phi1, sp1, n0, v0 = synth.inputs(c1)
+        S1 = oracle.switching_matrix(np.asarray(phi1, np.float64), sp1.a, sp1.b, sp1.tau,
+                                     sp1.gamma, c1.n_pulses)
+        A1 = lambda v: oracle.apply_A(v, S1, t01, taps1, c1.nt)
+        AT1 = lambda w: oracle.apply_AT(w, S1, t01, taps1, c1.nz)
+        y1 = A1(c1_true.astype(np.float64))
+        p1 = (y1 + synth.noise_sigma(float(np.sqrt(np.mean(y1 ** 2)))) * n0).astype(np.float32)
+        aty = float(np.abs(AT1(p1.astype(np.float64))).max())
+        lam_tv, lam_l1 = 5e-3 * aty, 1e-2 * aty
+        alpha1 = 1.0 / (1.01 * oracle.power_iteration(A1, AT1, v0, 30))
+        c_ref, _ = oracle.fista(p1.astype(np.float64), A1, AT1, alpha1, lam_tv, lam_l1, c1.k1,
+                                c1.k2, shape_c=c1.c_shape)
+        for q in precs:
+            plan = pk.Plan.from_config(c1, phi1, sp1, t01, taps1, prec=q)
+            cg, _ = plan.solve(torch.from_numpy(p1).cuda(), lambda_tv=lam_tv, lambda_l1=lam_l1,
+                               k1=c1.k1, k2=c1.k2, alpha1=alpha1)
+            acc["c_C1"][q] = oracle.rel_err(cg.cpu().numpy(), c_ref)
+            plan.close()
+    return base, acc
 
 
 def run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1, prec,
@@ -158,8 +199,7 @@ def factorised_run(torch, pk, cfg, phi, sp, c_true, p_t, lam_tv, lam_l1, prec, s
     sums Lambda on the matrix cores (a narrow band), then the impulse-response
     pass over the A-scans.  Times the isolated applies, the shell-sum kernels
     alone and solver steps (step size from its own power iteration), and
-    compares sampled A-scans with the FP64 oracle's factorised operator."""
-    import oracle
+    keeps sampled A-scans for the CPU leg's comparison with the oracle."""
     import synth
     dr, z_focus, t_focus = synth.shell_geometry(cfg.nz, cfg.nt)
     eir, origin = synth.eir_taps()
@@ -186,57 +226,22 @@ def factorised_run(torch, pk, cfg, phi, sp, c_true, p_t, lam_tv, lam_l1, prec, s
     plan.solve(p_t, c=c, lambda_tv=lam_tv, lambda_l1=lam_l1, k1=steps, k2=cfg.k2, alpha1=alpha1)
     torch.cuda.synchronize()
     step = (time.perf_counter() - t0_) / steps
-    S = oracle.switching_matrix(phi, sp.a, sp.b, sp.tau, sp.gamma, cfg.n_pulses)
-    mask = oracle.shell_mask(cfg.nz, cfg.f, cfg.nt, dr, z_focus, t_focus)
-    scans = [(5, 7), (64, 64), (127, 0), (90, 33)]
-    y_s = oracle.apply_A_fact_scans(c_true, S, spr, mask, eir, origin, scans)
     plan.apply_A(c_in, y)
-    y_g = np.stack([y[:, iy, ix, :].cpu().numpy() for (iy, ix) in scans])
-    alg_macs = int(mask.sum()) + len(eir) * cfg.nt     # per A-scan of one pulse: shells + EIR
+    y_g = np.stack([y[:, iy, ix, :].cpu().numpy() for (iy, ix) in SCANS])
+    alg_macs = int(info["useful_macs"][0]) + len(eir) * cfg.nt   # per A-scan of one pulse: shells + EIR
     out = {"dtype": prec, "ms_per_step": step * 1e3, "applies_per_s_in_solver": 1.0 / step,
            "apply_A_ms": t_A, "apply_AT_ms": t_AT, "isolated_applies_per_s": 1e3 / (t_A + t_AT),
            "shell_kernel_ms": t_L, "shell_adjoint_kernel_ms": t_LT,
            "shell_nonzeros_per_ascan": info["useful_macs"][0],
            "chunks": info["chunks"], "band_fill": info["useful_macs"][0] / max(1, info["executed_macs"][0]),
            "alg_macs_per_ascan": alg_macs,
-           "rel_err_A_vs_oracle_sampled": oracle.rel_err(y_g, y_s),
+           "rel_err_A_vs_oracle_sampled": None,
            "note": "a different discretisation of the acoustic model (unit-weight shells "
                    "then the 1D pulse convolution), not the banded impulse response: its "
                    "timings are a comparison point, not the headline"}
     plan.close()
-    return out
-
-
-def c1_oracle_errors(torch, pk, precs):
-    """Relative error of c after the C1 solve (20 FISTA steps, 20 dual TV steps,
-    TV + l1 + nonnegativity) against the FP64 oracle's c on the same inputs and
-    the same step alpha1, for each precision."""
-    import oracle
-    import synth
-    cfg = synth.C1
-    c_true, t0, taps, phi, sp, n0, v0 = synth.inputs(cfg)
-    S = oracle.switching_matrix(np.asarray(phi, np.float64), sp.a, sp.b, sp.tau, sp.gamma,
-                                cfg.n_pulses)
-    A = lambda v: oracle.apply_A(v, S, t0, taps, cfg.nt)
-    AT = lambda w: oracle.apply_AT(w, S, t0, taps, cfg.nz)
-    y = A(c_true.astype(np.float64))
-    p = (y + synth.noise_sigma(float(np.sqrt(np.mean(y ** 2)))) * n0).astype(np.float32)
-    aty = float(np.abs(AT(p.astype(np.float64))).max())
-    lam_tv, lam_l1 = 5e-3 * aty, 1e-2 * aty
-    ref = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec="fp32")
-    _, st = ref.solve(torch.from_numpy(p).cuda(), k1=0, n_power=30, v0=torch.from_numpy(v0).cuda())
-    alpha1 = st["alpha1"]
-    ref.close()
-    c_ref, _ = oracle.fista(p.astype(np.float64), A, AT, alpha1, lam_tv, lam_l1, cfg.k1, cfg.k2,
-                            shape_c=cfg.c_shape)
-    out = {}
-    for prec in precs:
-        plan = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=prec)
-        c, _ = plan.solve(torch.from_numpy(p).cuda(), lambda_tv=lam_tv, lambda_l1=lam_l1,
-                          k1=cfg.k1, k2=cfg.k2, alpha1=alpha1)
-        out[prec] = oracle.rel_err(c.cpu().numpy(), c_ref)
-        plan.close()
-    return out
+    sample = dict(y=y_g, spr=spr, eir=eir, origin=origin, dr=dr, z_focus=z_focus, t_focus=t_focus)
+    return out, sample
 
 
 def profiled_traffic():
@@ -257,7 +262,7 @@ def profiled_traffic():
     if want.get("source_sha1") != h.hexdigest():
         return None, "kernel sources changed since the counters were taken"
     try:
-        return float(want["hbm_bytes_per_launch"]), path
+        return float(want["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
     except (KeyError, ValueError):
         return None, "summary without hbm_bytes_per_launch"
 
@@ -373,17 +378,12 @@ def main():
         runs[q] = run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1,
                            q, max(2, args.steps // 4) if slow else args.steps, 1 if slow else args.warmup,
                            max(2, args.kernel_reps // 4) if slow else args.kernel_reps)
-    # accuracy of each precision's operator vs the FP64 oracle on sampled A-scans
-    import oracle
-    S = oracle.switching_matrix(phi, sp.a, sp.b, sp.tau, sp.gamma, cfg.n_pulses)
-    scans = [(5, 7), (64, 64), (127, 0), (90, 33)]
-    y_s = oracle.apply_A_scans(c_true, S, t0, taps, cfg.nt, scans)
+    # sampled A-scans of each precision, compared with the oracle by the CPU leg
     c_in = torch.from_numpy(c_true).cuda()
-    err_A = {}
+    samples = {}
     for q, r in runs.items():
         r["plan"].apply_A(c_in, r["y"])
-        y_g = np.stack([r["y"][:, iy, ix, :].cpu().numpy() for (iy, ix) in scans])
-        err_A[q] = oracle.rel_err(y_g, y_s)
+        samples[q] = np.stack([r["y"][:, iy, ix, :].cpu().numpy() for (iy, ix) in SCANS])
     # the separable fast form (valid only for this workload's fluence-independent
     # rate, gamma = 0), reported apart from the general path
     sep = None
@@ -392,14 +392,14 @@ def main():
         rs = run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1,
                       args.prec, args.steps, args.warmup, args.kernel_reps, separable=True)
         rs["plan"].apply_A(c_in, rs["y"])
-        y_g = np.stack([rs["y"][:, iy, ix, :].cpu().numpy() for (iy, ix) in scans])
+        samples["separable"] = np.stack([rs["y"][:, iy, ix, :].cpu().numpy() for (iy, ix) in SCANS])
         sep = {"dtype": args.prec, "ms_per_step": rs["step_s"] * 1e3,
                "applies_per_s_in_solver": 1.0 / rs["step_s"],
                "apply_A_ms": rs["t_A"], "apply_AT_ms": rs["t_AT"],
                "isolated_applies_per_s": 1e3 / (rs["t_A"] + rs["t_AT"]),
                "contraction_H_ms": rs["t_H"], "contraction_HT_ms": rs["t_HT"],
                "fista_s_to_tol": rs["solve_s"],
-               "rel_err_A_vs_oracle_sampled": oracle.rel_err(y_g, y_s),
+               "rel_err_A_vs_oracle_sampled": None,
                "rel_err_c_vs_fp32_general": (
                    float((rs["c_full"] - runs["fp32"]["c_full"]).double().norm()
                          / runs["fp32"]["c_full"].double().norm()) if "fp32" in runs else None),
@@ -407,10 +407,7 @@ def main():
                        "S species (one 16-column block) and the pulses are expanded after; "
                        "not valid for the fluence-dependent rate"}
         rs["plan"].close()
-    c1_err = {}
-    if not args.no_c1_oracle:
-        log("[bench] C1 solves vs the FP64 oracle")
-        c1_err = c1_oracle_errors(torch, pk, list(runs))
+    precs = list(runs)
     info = res["info"]
     alg_flops = 2.0 * info["useful_macs"][0] * cfg.n_pulses * cfg.nx * cfg.ny
     peak = PEAK_TFLOPS[args.prec]
@@ -433,9 +430,9 @@ def main():
             "H_kernel_ms": r["t_H"], "HT_kernel_ms": r["t_HT"],
             "H_alg_frac_of_peak": alg_flops / (r["t_H"] * 1e-3) / 1e12 / PEAK_TFLOPS[q],
             "fista_s_to_tol": r["solve_s"], "fista_iterations": cfg.k1,
-            "rel_err_A_vs_oracle_sampled": err_A[q],
+            "rel_err_A_vs_oracle_sampled": None,
             "rel_err_c_vs_fp32_C2": err_vs_fp32(r),
-            "rel_err_c_vs_oracle_C1": c1_err.get(q),
+            "rel_err_c_vs_oracle_C1": None,
         }
     out = {
         "metric": METRIC,
@@ -466,9 +463,9 @@ def main():
         "precisions": per_prec,
         "separable_form": sep,
     }
+    fact = None
     if args.headline_only:
-        if not args.no_cpu_baseline:
-            out["cpu_baseline"] = cpu_baseline(cfg, t0, taps, phi, sp, args.cpu_crop, args.steps)
+        cpu_leg(out, args, torch, pk, cfg, t0, taps, phi, sp, c_true, samples, fact, precs)
         print(json.dumps(out), flush=True)
         return
     # the two-step method (the paper's comparison): acoustic inversion of the
@@ -503,16 +500,33 @@ def main():
     ac.close()
     del b, c_u
     log("[bench] factorised acoustic operator")
-    out["factorised"] = factorised_run(torch, pk, cfg, phi, sp, c_true, p_t, lam_tv, lam_l1,
-                                       args.prec, args.steps, args.warmup, args.kernel_reps)
+    out["factorised"], fact = factorised_run(torch, pk, cfg, phi, sp, c_true, p_t, lam_tv, lam_l1,
+                                             args.prec, args.steps, args.warmup,
+                                             args.kernel_reps)
     if not args.no_scales:
         del runs, res, fp32
         torch.cuda.empty_cache()
         out["scales"] = scale_runs(torch, pk)
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(cfg, t0, taps, phi, sp, args.cpu_crop, args.steps)
+    cpu_leg(out, args, torch, pk, cfg, t0, taps, phi, sp, c_true, samples, fact, precs)
     print(json.dumps(out), flush=True)
+
+
+def cpu_leg(out, args, torch, pk, cfg, t0, taps, phi, sp, c_true, samples, fact, precs):
+    """Runs the CPU leg (unless --no-cpu-baseline) and files its results in the
+    bench line: cpu_baseline and the rel_err_*_vs_oracle fields."""
+    if args.no_cpu_baseline:
+        return
+    log("[bench] cpu baseline and accuracy (oracle)")
+    base, acc = cpu_baseline_leg(torch, pk, cfg, t0, taps, phi, sp, c_true, args.cpu_crop,
+                                 samples, fact, precs, not args.no_c1_oracle)
+    out["cpu_baseline"] = base
+    for q, r in out["precisions"].items():
+        r["rel_err_A_vs_oracle_sampled"] = acc["A"].get(q)
+        r["rel_err_c_vs_oracle_C1"] = acc["c_C1"].get(q)
+    if out.get("separable_form"):
+        out["separable_form"]["rel_err_A_vs_oracle_sampled"] = acc["A"].get("separable")
+    if out.get("factorised"):
+        out["factorised"]["rel_err_A_vs_oracle_sampled"] = acc["factorised_A"]
 
 
 if __name__ == "__main__":
