@@ -109,6 +109,7 @@ struct psoam_plan {
   int Kp, NB;       // padded pulses, 16-pulse column blocks
   int Yp, Xp;
   int Lz, Lt;       // contracted lengths of the H operand (z) and H^T operand (t), in samples
+  int tsh = 0;      // 16-bit H^T operand: sample t is stored at t + tsh (0 or 4)
   size_t ps_b, ps_r;  // elements per padded position of the H / H^T operands
   int device;
   float* d_phi = nullptr;

@@ -174,7 +174,8 @@ __global__ __launch_bounds__(256) void pack_r16(const float* __restrict__ yin,
                                                 typename Half<PREC>::E* __restrict__ rq,
                                                 typename Half<PREC>::E* __restrict__ rq_lo,
                                                 int nk, int ny, int nx, int nt, int to_n,
-                                                int kp, int xp, int r, size_t ps, int vec4) {
+                                                int kp, int xp, int r, size_t ps, int vec4,
+                                                int tsh) {
   using H = Half<PREC>;
   using V = typename H::V;
   __shared__ V t_hi[256];
@@ -191,15 +192,17 @@ __global__ __launch_bounds__(256) void pack_r16(const float* __restrict__ yin,
         const int k = kc + a, to = oc + c;
         V hi, lo;
         if (k < nk && to < to_n) {
-          const float* src = yin + (((size_t)k * ny + y) * nx + x) * nt + (size_t)to * 8;
+          // octet `to` holds samples to*8 - tsh .. to*8 - tsh + 7
+          const int tb = to * 8 - tsh;
+          const float* row = yin + (((size_t)k * ny + y) * nx + x) * nt;
           float v[8];
-          if (vec4 && to * 8 + 7 < nt) {
-            const f32x4 v0 = *(const f32x4*)src, v1 = *(const f32x4*)(src + 4);
+          if (vec4 && tb >= 0 && tb + 7 < nt) {
+            const f32x4 v0 = *(const f32x4*)(row + tb), v1 = *(const f32x4*)(row + tb + 4);
             v[0] = v0[0]; v[1] = v0[1]; v[2] = v0[2]; v[3] = v0[3];
             v[4] = v1[0]; v[5] = v1[1]; v[6] = v1[2]; v[7] = v1[3];
           } else {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = to * 8 + j < nt ? src[j] : 0.0f;
+            for (int j = 0; j < 8; ++j) v[j] = (tb + j >= 0 && tb + j < nt) ? row[tb + j] : 0.0f;
           }
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
@@ -280,6 +283,7 @@ struct BandArgs {
   void* rq_lo;
   size_t ps_r;
   int r;
+  int tsh;          // 16-bit H^T operand: sample t stored at t + tsh (0 or 4)
   float rq_scale;
   double* partial;
   SwitchParams sw;
@@ -390,7 +394,9 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
           hi[j] = (typename H::E)v;
           lo[j] = (typename H::E)(v - (float)hi[j]);
         }
-        const size_t o = pos + ((size_t)(row0 >> 3) * A.kp + k) * 8 + ((row0 >> 2) & 1) * 4;
+        // tsh is 0 or 4, so the quarter-octet stays aligned
+        const int rs = row0 + A.tsh;
+        const size_t o = pos + ((size_t)(rs >> 3) * A.kp + k) * 8 + ((rs >> 2) & 1) * 4;
         *(typename H::V4*)((typename H::E*)A.rq + o) = hi;
         if constexpr (SPLIT) *(typename H::V4*)((typename H::E*)A.rq_lo + o) = lo;
       }
@@ -816,8 +822,11 @@ __global__ __launch_bounds__(64 * ROWS) __attribute__((amdgpu_waves_per_eu(!SPLI
   band16_lds_body<PREC, SPLIT, MODE, ROWS>(A, L);
 }
 
+// H^T with one-part operands is held to two waves per SIMD (256 registers)
+// so that two 4-row workgroups can share a CU when their staged window fits
 template <int PREC, bool SPLIT, int ROWS>
-__global__ __launch_bounds__(64 * ROWS) void band16_lds_adj(BandArgs A, LdsArgs L) {
+__global__ __launch_bounds__(64 * ROWS) __attribute__((amdgpu_waves_per_eu(SPLIT ? 1 : 2))) void band16_lds_adj(
+    BandArgs A, LdsArgs L) {
   band16_lds_body<PREC, SPLIT, 2, ROWS>(A, L);
 }
 
@@ -874,7 +883,7 @@ hipError_t launch_pack_r(const psoam_plan* P, const float* y, hipStream_t s) {
     const size_t n = (size_t)g.ny * g.nx;                                                   \
     hipLaunchKernelGGL((pack_r16<PR, SP>), dim3((unsigned)n), dim3(256), 0, s, y,           \
                        (E*)P->d_rq, (E*)P->d_rq_lo, g.n_pulses, g.ny, g.nx, g.nt, P->Lt / 8, \
-                       P->Kp, P->Xp, P->R, P->ps_r, vec4);                                  \
+                       P->Kp, P->Xp, P->R, P->ps_r, vec4, P->tsh);                          \
     break;                                                                                  \
   }
     case PSOAM_BF16:
@@ -1035,6 +1044,7 @@ hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* p
   A.rq_lo = P->d_rq_lo;
   A.ps_r = P->ps_r;
   A.r = P->R;
+  A.tsh = P->tsh;
   A.rq_scale = fp16 ? kFp16Scale : 1.0f;
   A.partial = partial;
   A.sw = P->sw;

@@ -114,7 +114,7 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
           if (dir == 0) {
             tile = t / 16; jy = jdy; jx = jdx; l = z / gw;
           } else {
-            tile = z / 16; jy = F - 1 - jdy; jx = F - 1 - jdx; l = t / gw;
+            tile = z / 16; jy = F - 1 - jdy; jx = F - 1 - jdx; l = (t + P->tsh) / gw;
           }
           mark[((size_t)tile * n_off + (size_t)jy * F + jx) * n_l + l] = 1;
           if (refine && refine[col] && low(v) != 0.0f)
@@ -149,10 +149,10 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
         const size_t col = ((size_t)z * F + jdy) * F + jdx;
         for (int j = 0; j < W; ++j) {
           const int t = t0[col] + j;
-          if (t < 0 || t >= g.nt || t / gw != G.l) continue;
+          if (t < 0 || t >= g.nt || (t + P->tsh) / gw != G.l) continue;
           const int lane = 16 * gi + zi;
           const float v = taps[col * W + j];
-          vals[((size_t)c * 64 + lane) * gw + (t - G.l * gw)] = G.layer ? low(v) : v;
+          vals[((size_t)c * 64 + lane) * gw + (t + P->tsh - G.l * gw)] = G.layer ? low(v) : v;
         }
       }
     }
@@ -514,6 +514,43 @@ void free_plan(psoam_plan* P) {
 // diag: switching S'_v = phi_v I over the species (inner plan of the
 // separable form); build_op = false skips the contraction tables and operand
 // buffers (outer plan of the separable form).
+// Widest octet window (8-sample groups of the H^T operand, samples shifted
+// by tsh) that a workgroup of `rows` output rows of H^T stages: per output
+// tile of 16 depths and lateral offset dy, the octet range of the band; per
+// staged row, the union over the rows' dy values.
+static int adj_window_octets(const psoam_geom& g, const int32_t* t0, const float* taps, int W,
+                             int tsh, int rows) {
+  const int F = g.f, n_mt = (g.nz + 15) / 16;
+  std::vector<int> lo((size_t)n_mt * F, 1 << 30), hi((size_t)n_mt * F, -1);
+  for (int z = 0; z < g.nz; ++z)
+    for (int jdy = 0; jdy < F; ++jdy)
+      for (int jdx = 0; jdx < F; ++jdx) {
+        const size_t col = ((size_t)z * F + jdy) * F + jdx;
+        for (int j = 0; j < W; ++j) {
+          const int t = t0[col] + j;
+          if (taps[col * W + j] == 0.0f || t < 0 || t >= g.nt) continue;
+          const size_t key = (size_t)(z / 16) * F + (F - 1 - jdy);
+          lo[key] = std::min(lo[key], (t + tsh) / 8);
+          hi[key] = std::max(hi[key], (t + tsh) / 8);
+        }
+      }
+  int best = 0;
+  for (int tile = 0; tile < n_mt; ++tile)
+    for (int j = 0; j < F + rows - 1; ++j) {
+      int l = 1 << 30, h = -1;
+      for (int r = 0; r < rows; ++r) {
+        const int dy = j - r;
+        if (dy < 0 || dy >= F) continue;
+        const size_t key = (size_t)tile * F + dy;
+        if (hi[key] < 0) continue;
+        l = std::min(l, lo[key]);
+        h = std::max(h, hi[key]);
+      }
+      if (h >= 0) best = std::max(best, h - l + 1);
+    }
+  return best;
+}
+
 static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const float* phi,
                             const int32_t* t0, const float* taps, int32_t sir_w, int32_t prec,
                             hipStream_t stream, int diag, bool build_op, psoam_plan** out) {
@@ -563,7 +600,12 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
   const bool half = prec != PSOAM_FP32;
   const bool split = prec == PSOAM_BF16_SPLIT || prec == PSOAM_FP16_SPLIT;
   P->Lz = half ? (g.nz + 7) / 8 * 8 : g.nz;
-  P->Lt = (g.nt + 15) / 16 * 16;
+  // 16-bit H^T operand: shifting its samples by 4 (the residual epilogue
+  // writes aligned quarters of 8-sample octets, so only 0 and 4 keep them
+  // aligned) can narrow the widest staged octet window of the H^T kernel
+  // by one octet; take it when it does (4-row workgroups)
+  if (half) P->tsh = adj_window_octets(g, t0, taps, sir_w, 4, 4) < adj_window_octets(g, t0, taps, sir_w, 0, 4) ? 4 : 0;
+  P->Lt = (g.nt + 15) / 16 * 16 + (P->tsh ? 16 : 0);
   P->ps_b = (size_t)P->Lz * P->Kp;
   P->ps_r = (size_t)P->Lt * P->Kp;
   (void)hipGetDevice(&P->device);
