@@ -355,6 +355,9 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   int rows = 4;
   if (lds4 > (size_t)kLdsMaxBytes / 2 && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
   if (lds4 > (size_t)kLdsMaxBytes && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
+  // split-operand H^T needs more registers than two waves per SIMD allow, so
+  // a second 4-row workgroup could not share the CU: eight rows instead
+  if (dir == 1 && split && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
   // PSOAM_LDS_ROWS=4 or 8 overrides the choice when it fits (tests cover both)
   if (const char* fr = std::getenv("PSOAM_LDS_ROWS")) {
     if (fr[0] == '8' && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
