@@ -1740,7 +1740,7 @@ __global__ __launch_bounds__(256) void sep_residual_kernel(float* __restrict__ r
 //   mode 2: r = (V in) - p, out = V^T r, FP64 block sums of r^2
 //   mode 3: r = (V in) - p, FP64 block sums of r^2 only
 // `out` may alias `in` (each row is read whole before it is written).
-template <int MODE>
+template <int MODE, bool VEC>
 __global__ __launch_bounds__(256) void eir_rows_kernel(float* out, const float* in,
                                                        const float* __restrict__ pm, EirParams e,
                                                        int nt, int64_t rows,
@@ -1751,40 +1751,93 @@ __global__ __launch_bounds__(256) void eir_rows_kernel(float* out, const float* 
   const int stride = nt + 2 * kMaxEir;
   float* qb = eir_lds + (size_t)w * stride * (MODE >= 2 ? 2 : 1);
   float* rb = qb + stride;
+  // VEC (nt a multiple of 4, 16-byte aligned rows): a lane moves and computes
+  // 4 consecutive samples; the row buffers stay 16-byte aligned (kMaxEir and
+  // stride are multiples of 4)
+  constexpr int E = VEC ? 4 : 1;
+  const int nv = nt / E;
   double ss = 0.0;
   for (int64_t base = (int64_t)blockIdx.x * wpb; base < rows; base += (int64_t)gridDim.x * wpb) {
     const int64_t row = base + w;
     const bool live = row < rows;
     const size_t off = live ? (size_t)row * nt : 0;
-    for (int i = lane; i < stride; i += 64) {
-      const int t = i - kMaxEir;
-      qb[i] = (live && t >= 0 && t < nt) ? in[off + t] : 0.0f;
-      if (MODE >= 2 && (t < 0 || t >= nt)) rb[i] = 0.0f;
+    if constexpr (VEC) {
+      for (int i = lane; i < nv; i += 64) {
+        const f32x4 v = live ? *(const f32x4*)(in + off + 4 * i) : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        *(f32x4*)(qb + kMaxEir + 4 * i) = v;
+      }
+      for (int i = lane; i < kMaxEir; i += 64) {
+        qb[i] = 0.0f;
+        qb[kMaxEir + nt + i] = 0.0f;
+        if (MODE >= 2) {
+          rb[i] = 0.0f;
+          rb[kMaxEir + nt + i] = 0.0f;
+        }
+      }
+    } else {
+      for (int i = lane; i < stride; i += 64) {
+        const int t = i - kMaxEir;
+        qb[i] = (live && t >= 0 && t < nt) ? in[off + t] : 0.0f;
+        if (MODE >= 2 && (t < 0 || t >= nt)) rb[i] = 0.0f;
+      }
     }
     __syncthreads();
     if (MODE <= 1) {
-      for (int t = lane; t < nt; t += 64) {
-        float acc = 0.0f;
+      for (int i = lane; i < nv; i += 64) {
+        float acc[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) acc[u] = 0.0f;
         for (int j = 0; j < e.n; ++j) {
           const int lag = j - e.origin;
-          acc += e.v[j] * qb[kMaxEir + (MODE == 0 ? t - lag : t + lag)];
+          const float* src = qb + kMaxEir + E * i + (MODE == 0 ? -lag : lag);
+#pragma unroll
+          for (int u = 0; u < E; ++u) acc[u] += e.v[j] * src[u];
         }
-        if (live) out[off + t] = acc;
+        if (live) {
+          if constexpr (VEC) *(f32x4*)(out + off + 4 * i) = f32x4{acc[0], acc[1], acc[2], acc[3]};
+          else out[off + i] = acc[0];
+        }
       }
     } else {
-      for (int t = lane; t < nt; t += 64) {
-        float acc = 0.0f;
-        for (int j = 0; j < e.n; ++j) acc += e.v[j] * qb[kMaxEir + t - (j - e.origin)];
-        const float r = acc - ((pm && live) ? pm[off + t] : 0.0f);
-        rb[kMaxEir + t] = r;
-        if (live) ss += (double)r * (double)r;
+      for (int i = lane; i < nv; i += 64) {
+        float acc[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) acc[u] = 0.0f;
+        for (int j = 0; j < e.n; ++j) {
+          const float* src = qb + kMaxEir + E * i - (j - e.origin);
+#pragma unroll
+          for (int u = 0; u < E; ++u) acc[u] += e.v[j] * src[u];
+        }
+        float pv[E];
+        if constexpr (VEC) {
+          const f32x4 q4 = (pm && live) ? *(const f32x4*)(pm + off + 4 * i) : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int u = 0; u < E; ++u) pv[u] = q4[u];
+        } else {
+          pv[0] = (pm && live) ? pm[off + i] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+          const float r = acc[u] - pv[u];
+          rb[kMaxEir + E * i + u] = r;
+          if (live) ss += (double)r * (double)r;
+        }
       }
       if (MODE == 2) {
         __syncthreads();
-        for (int t = lane; t < nt; t += 64) {
-          float acc = 0.0f;
-          for (int j = 0; j < e.n; ++j) acc += e.v[j] * rb[kMaxEir + t + (j - e.origin)];
-          if (live) out[off + t] = acc;
+        for (int i = lane; i < nv; i += 64) {
+          float acc[E];
+#pragma unroll
+          for (int u = 0; u < E; ++u) acc[u] = 0.0f;
+          for (int j = 0; j < e.n; ++j) {
+            const float* src = rb + kMaxEir + E * i + (j - e.origin);
+#pragma unroll
+            for (int u = 0; u < E; ++u) acc[u] += e.v[j] * src[u];
+          }
+          if (live) {
+            if constexpr (VEC) *(f32x4*)(out + off + 4 * i) = f32x4{acc[0], acc[1], acc[2], acc[3]};
+            else out[off + i] = acc[0];
+          }
         }
       }
     }
@@ -1814,22 +1867,27 @@ hipError_t launch_eir_rows(const psoam_plan* P, int mode, float* out, const floa
   const int wpb = eir_waves(nt);
   const size_t lds = sizeof(float) * (size_t)wpb * (nt + 2 * kMaxEir) * (mode >= 2 ? 2 : 1);
   const dim3 grid((unsigned)eir_blocks(P)), block(64 * wpb);
+  auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+  const bool vec = (nt & 3) == 0 && al16(out) && al16(in) && al16(p);
+#define PSOAM_EIR(M)                                                                        \
+  {                                                                                         \
+    if (vec)                                                                                \
+      hipLaunchKernelGGL((eir_rows_kernel<M, true>), grid, block, lds, s, out, in, p, P->eir, nt, \
+                         rows, partial);                                                    \
+    else                                                                                    \
+      hipLaunchKernelGGL((eir_rows_kernel<M, false>), grid, block, lds, s, out, in, p, P->eir, nt, \
+                         rows, partial);                                                    \
+    break;                                                                                  \
+  }
   switch (mode) {
-    case 0:
-      hipLaunchKernelGGL(eir_rows_kernel<0>, grid, block, lds, s, out, in, p, P->eir, nt, rows, partial);
-      break;
-    case 1:
-      hipLaunchKernelGGL(eir_rows_kernel<1>, grid, block, lds, s, out, in, p, P->eir, nt, rows, partial);
-      break;
-    case 2:
-      hipLaunchKernelGGL(eir_rows_kernel<2>, grid, block, lds, s, out, in, p, P->eir, nt, rows, partial);
-      break;
-    case 3:
-      hipLaunchKernelGGL(eir_rows_kernel<3>, grid, block, lds, s, out, in, p, P->eir, nt, rows, partial);
-      break;
+    case 0: PSOAM_EIR(0)
+    case 1: PSOAM_EIR(1)
+    case 2: PSOAM_EIR(2)
+    case 3: PSOAM_EIR(3)
     default:
       return hipErrorInvalidValue;
   }
+#undef PSOAM_EIR
   return hipGetLastError();
 }
 
