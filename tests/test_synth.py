@@ -4,6 +4,7 @@ nonnegative and seeded, and the configurations have the stated sizes."""
 import math
 
 import numpy as np
+import pytest
 
 import synth
 
@@ -71,3 +72,30 @@ def test_config_sizes():
         c = synth.c4_instance(i)
         assert 64 <= c.nx <= 192 and 48 <= c.nz <= 96 and 16 <= c.n_pulses <= 48
         assert c.n_species in (2, 3) and c.nt % 32 == 0 and 256 <= c.nt <= 384
+
+
+def test_factorised_inputs():
+    """Inputs of the factorised operator: the spatial response image is the
+    banded table's beam weight (1 on the axis, symmetric in dx and dy), the
+    impulse response is the pulse sampled at dt with its zero lag at the
+    origin (odd, zero at lag 0, within its 6 s support), and the radius step
+    is c0 dt / pitch."""
+    nz, f = 16, 7
+    spr = synth.spr_table(nz, f)
+    R = (f - 1) // 2
+    assert spr.shape == (nz, f, f) and spr.dtype == np.float32
+    np.testing.assert_array_equal(spr[:, R, R], np.ones(nz, np.float32))
+    np.testing.assert_array_equal(spr, spr[:, ::-1, :])
+    np.testing.assert_array_equal(spr, spr[:, :, ::-1])
+    np.testing.assert_array_equal(spr, np.transpose(spr, (0, 2, 1)))
+    s = synth.beam_sigma_vox(np.arange(nz, dtype=np.float64), nz, f)
+    np.testing.assert_allclose(spr[:, R, R + 2], np.exp(-4.0 / (2 * s * s)), rtol=1e-6)
+    v, o = synth.eir_taps()
+    assert v.dtype == np.float32 and len(v) == 2 * o + 1
+    assert v[o] == 0.0
+    np.testing.assert_array_equal(v[o + 1:], -v[o - 1::-1])
+    lags = (np.arange(len(v)) - o) * synth.DT_S
+    assert np.abs(lags).max() <= synth.BAND_HALF_SIGMAS * synth.pulse_sigma_s()
+    np.testing.assert_allclose(v, synth.pulse(lags).astype(np.float32))
+    dr, zf, tf = synth.shell_geometry(64, 256)
+    assert dr == pytest.approx(synth.C0_M_S * synth.DT_S / synth.PITCH_M) and zf == 31.5 and tf == 128
