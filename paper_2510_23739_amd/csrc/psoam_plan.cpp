@@ -605,9 +605,26 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
   P->Lz = half ? (g.nz + 7) / 8 * 8 : g.nz;
   // 16-bit H^T operand: shifting its samples by 4 (the residual epilogue
   // writes aligned quarters of 8-sample octets, so only 0 and 4 keep them
-  // aligned) can narrow the widest staged octet window of the H^T kernel
-  // by one octet; take it when it does (4-row workgroups)
-  if (half) P->tsh = adj_window_octets(g, t0, taps, sir_w, 4, 4) < adj_window_octets(g, t0, taps, sir_w, 0, 4) ? 4 : 0;
+  // aligned) can narrow the widest staged octet window of the H^T kernel by
+  // one octet.  Per shift, the row count the staged kernel's LDS rule would
+  // pick is predicted (two 4-row workgroups per CU, else one 8-row, else one
+  // 4-row); the shift with the better outcome, then the narrower window, wins.
+  if (half) {
+    const size_t row_bytes = (size_t)(kLdsPos + g.f - 1) * 16 * 8 * sizeof(uint16_t);
+    const size_t meta = 8192;  // generous bound of the per-tile tables
+    auto outcome = [&](int sh, int& width) {
+      const int o4 = adj_window_octets(g, t0, taps, sir_w, sh, 4);
+      const int o8 = adj_window_octets(g, t0, taps, sir_w, sh, 8);
+      const size_t l4 = o4 * row_bytes + meta, l8 = o8 * row_bytes + meta;
+      if (!split && l4 <= (size_t)kLdsMaxBytes / 2) { width = o4; return 3; }
+      if (l8 <= (size_t)kLdsMaxBytes) { width = o8; return 2; }
+      width = o4;
+      return l4 <= (size_t)kLdsMaxBytes ? 1 : 0;
+    };
+    int w0 = 0, w4 = 0;
+    const int s0 = outcome(0, w0), s4 = outcome(4, w4);
+    P->tsh = (s4 > s0 || (s4 == s0 && w4 < w0)) ? 4 : 0;
+  }
   P->Lt = (g.nt + 15) / 16 * 16 + (P->tsh ? 16 : 0);
   P->ps_b = (size_t)P->Lz * P->Kp;
   P->ps_r = (size_t)P->Lt * P->Kp;
