@@ -341,7 +341,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this path runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+                          "(sharding the path across GPUs is not built)"}))
         sys.exit(2)
     import torch
 
