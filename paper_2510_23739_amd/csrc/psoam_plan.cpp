@@ -624,6 +624,8 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
     int w0 = 0, w4 = 0;
     const int s0 = outcome(0, w0), s4 = outcome(4, w4);
     P->tsh = (s4 > s0 || (s4 == s0 && w4 < w0)) ? 4 : 0;
+    // PSOAM_ADJ_SHIFT=0 or 4 overrides the choice (tests cover both)
+    if (const char* e = std::getenv("PSOAM_ADJ_SHIFT")) P->tsh = e[0] == '4' ? 4 : 0;
   }
   P->Lt = (g.nt + 15) / 16 * 16 + (P->tsh ? 16 : 0);
   P->ps_b = (size_t)P->Lz * P->Kp;

@@ -77,6 +77,39 @@ def test_ragged_random_table(prec, kernel, monkeypatch):
     assert e <= TOL_OP[prec]
 
 
+@pytest.mark.parametrize("shift", ["0", "4"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16_split"])
+def test_adjoint_operand_shift(c1, prec, shift, monkeypatch):
+    """The 16-bit H^T operand with its samples stored at offset 0 or 4: the
+    external adjoint (packed from y), and the solver (residual written by
+    H's epilogue), both on the 32x32x16 problem and a ragged one."""
+    torch = torch_cuda()
+    monkeypatch.setenv("PSOAM_ADJ_SHIFT", shift)
+    cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
+    plan = lib_plan(cfg, t0, taps, phi, sp, prec)
+    yr = np.random.default_rng(12).standard_normal(cfg.y_shape).astype(np.float32)
+    g = plan.apply_AT(torch.from_numpy(yr).cuda(), nan_buf(cfg.c_shape)).cpu().numpy()
+    e = oracle.rel_err(g, oracle.apply_AT(yr, S, t0, taps, cfg.nz))
+    p, A, AT, lam_tv, lam_l1 = _c1_problem(c1)
+    alpha1 = 1.0 / (1.01 * oracle.power_iteration(A, AT, v0, 30))
+    c_ref, _ = oracle.fista(p.astype(np.float64), A, AT, alpha1, lam_tv, lam_l1, 6, cfg.k2,
+                            shape_c=cfg.c_shape)
+    c, _ = plan.solve(torch.from_numpy(p).cuda(), lambda_tv=lam_tv, lambda_l1=lam_l1, k1=6,
+                      k2=cfg.k2, alpha1=alpha1)
+    ec = oracle.rel_err(c.cpu().numpy(), c_ref)
+    cfg2, t02, taps2, phi2, sp2 = ragged_cfg(6)
+    S2 = oracle_S(cfg2, phi2, sp2)
+    plan2 = lib_plan(cfg2, t02, taps2, phi2, sp2, prec)
+    y2 = np.random.default_rng(13).standard_normal(cfg2.y_shape).astype(np.float32)
+    g2 = plan2.apply_AT(torch.from_numpy(y2).cuda(), nan_buf(cfg2.c_shape)).cpu().numpy()
+    e2 = oracle.rel_err(g2, oracle.apply_AT(y2, S2, t02, taps2, cfg2.nz))
+    say(f"[parity] adjoint shift {shift} {prec}: A^T {e:.3e}, ragged A^T {e2:.3e}, FISTA(6) c {ec:.3e}")
+    assert e <= TOL_OP[prec] and e2 <= TOL_OP[prec]
+    assert ec <= (1e-3 if prec == "bf16" else 1e-4)
+    plan.close()
+    plan2.close()
+
+
 def test_point_source_fp32(c1):
     """A unit voxel gives the synthesised impulse response times the switching
     curve at every scan of its footprint (checked against the oracle's
