@@ -115,6 +115,7 @@ struct psoam_plan {
   float* d_phi = nullptr;
   float* d_stab = nullptr;   // [Nz][Kp][S] when phi is per depth
   float* d_stab_t = nullptr; // [K][S][Nz]: the same table with depth fastest (per-voxel kernels)
+  float* d_stab_o = nullptr; // [Lz/8][S][Kp][8]: per depth octet, pulses then depths (16-bit S)
   void* d_bq = nullptr;      // H operand (hi)
   void* d_bq_lo = nullptr;
   void* d_rq = nullptr;      // H^T operand (hi)

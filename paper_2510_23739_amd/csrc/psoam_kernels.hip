@@ -90,10 +90,15 @@ __device__ __forceinline__ float coef_at(const SwitchParams& sw, const float* __
 
 // b[k][y][x][z] = sum_s S[k][s] c[s][y][x][z] into the 16-bit octet operand.
 // One thread per (y, x, octet, pulse); pulses beyond K are written as zeros.
+// With `vec` (Nz a multiple of 8, c 16-byte aligned, the per-depth octet
+// table [Lz/8][S][Kp][8] present) a species' octet and its eight
+// coefficients arrive in four 16-byte loads issued together, instead of a
+// chain of guarded scalar loads; the sums are the same, in the same order.
 template <int PREC, bool SPLIT>
 __global__ __launch_bounds__(256) void switch_fwd16(const float* __restrict__ c,
                                                     const float* __restrict__ phi,
                                                     const float* __restrict__ stab,
+                                                    const float* __restrict__ stab_o, int vec,
                                                     SwitchParams sw,
                                                     typename Half<PREC>::E* __restrict__ bq,
                                                     typename Half<PREC>::E* __restrict__ bq_lo,
@@ -103,16 +108,40 @@ __global__ __launch_bounds__(256) void switch_fwd16(const float* __restrict__ c,
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t total = (size_t)ny * nx * zo_n * kp;
   if (tid >= total) return;
-  const int k = (int)(tid % kp);
-  size_t rest = tid / kp;
-  const int zo = (int)(rest % zo_n);
-  rest /= zo_n;
-  const int x = (int)(rest % nx);
-  const int y = (int)(rest / nx);
+  int k, zo, x, y;
+  if (total <= 0xffffffffu) {  // 32-bit index arithmetic where it fits
+    unsigned rest = (unsigned)tid;
+    k = (int)(rest % (unsigned)kp);
+    rest /= (unsigned)kp;
+    zo = (int)(rest % (unsigned)zo_n);
+    rest /= (unsigned)zo_n;
+    x = (int)(rest % (unsigned)nx);
+    y = (int)(rest / (unsigned)nx);
+  } else {
+    size_t rest = tid / kp;
+    k = (int)(tid % kp);
+    zo = (int)(rest % zo_n);
+    rest /= zo_n;
+    x = (int)(rest % nx);
+    y = (int)(rest / nx);
+  }
   float b[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) b[j] = 0.0f;
-  if (k < sw.nk) {
+  if (k < sw.nk && vec) {
+    const size_t col = ((size_t)y * nx + x) * nz + (size_t)zo * 8;
+    const int s0 = sw.diag ? k : 0, s1 = sw.diag ? (k < sw.ns ? k + 1 : k) : sw.ns;
+    for (int s = s0; s < s1; ++s) {
+      const f32x4* cs = (const f32x4*)(c + (size_t)s * ny * nx * nz + col);
+      const f32x4* ws = (const f32x4*)(stab_o + (((size_t)zo * sw.ns + s) * kp + k) * 8);
+      const f32x4 c0 = cs[0], c1 = cs[1], w0 = ws[0], w1 = ws[1];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        b[j] += w0[j] * c0[j];
+        b[4 + j] += w1[j] * c1[j];
+      }
+    }
+  } else if (k < sw.nk) {
     const size_t col = ((size_t)y * nx + x) * nz;
     // diagonal switching: only species k contributes
     const int s0 = sw.diag ? k : 0, s1 = sw.diag ? (k < sw.ns ? k + 1 : k) : sw.ns;
@@ -840,6 +869,7 @@ static inline unsigned blocks_for(size_t n, unsigned bs = 256) {
 hipError_t launch_switch_fwd(const psoam_plan* P, const float* c, hipStream_t s) {
   const auto& g = P->g;
   const float* stab = P->d_stab;
+  const int vec = P->d_stab_o && (g.nz % 8) == 0 && ((uintptr_t)c & 15) == 0;
   switch (P->prec) {
     case PSOAM_FP32: {
       const size_t n = (size_t)g.ny * g.nx * g.nz * P->Kp;
@@ -852,8 +882,9 @@ hipError_t launch_switch_fwd(const psoam_plan* P, const float* c, hipStream_t s)
     using E = Half<PR>::E;                                                                  \
     const size_t n = (size_t)g.ny * g.nx * (P->Lz / 8) * P->Kp;                            \
     hipLaunchKernelGGL((switch_fwd16<PR, SP>), dim3(blocks_for(n)), dim3(256), 0, s, c,     \
-                       P->d_phi, stab, P->sw, (E*)P->d_bq, (E*)P->d_bq_lo, g.ny, g.nx,     \
-                       g.nz, P->Lz / 8, P->Kp, P->Xp, P->R, P->ps_b);                       \
+                       P->d_phi, stab, P->d_stab_o, vec, P->sw, (E*)P->d_bq,               \
+                       (E*)P->d_bq_lo, g.ny, g.nx, g.nz, P->Lz / 8, P->Kp, P->Xp, P->R,    \
+                       P->ps_b);                                                            \
     break;                                                                                  \
   }
     case PSOAM_BF16:

@@ -507,7 +507,7 @@ void free_plan(psoam_plan* P) {
     if (b) (void)hipFree(b);
   free_table(P->fwd);
   free_table(P->adj);
-  void* bufs[] = {P->d_phi, P->d_stab, P->d_stab_t, P->d_bq, P->d_bq_lo, P->d_rq, P->d_rq_lo,
+  void* bufs[] = {P->d_phi, P->d_stab, P->d_stab_t, P->d_stab_o, P->d_bq, P->d_bq_lo, P->d_rq, P->d_rq_lo,
                   P->solve_ws.base, P->r3_ws.base, P->d_partial, P->d_scalars};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -682,6 +682,19 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
           stt[((size_t)k * g.n_species + s) * g.nz + z] = st[((size_t)z * P->Kp + k) * g.n_species + s];
     PLAN_HIP(hipMalloc(&P->d_stab_t, sizeof(float) * stt.size()));
     PLAN_HIP(hipMemcpy(P->d_stab_t, stt.data(), sizeof(float) * stt.size(), hipMemcpyHostToDevice));
+    if (half) {
+      // the 16-bit S kernel's lanes are pulses of one depth octet: each reads
+      // its octet's eight coefficients per species as 32 contiguous bytes
+      const int zo_n = P->Lz / 8;
+      std::vector<float> sto((size_t)zo_n * g.n_species * P->Kp * 8, 0.0f);
+      for (int z = 0; z < g.nz; ++z)
+        for (int k = 0; k < P->Kp; ++k)
+          for (int s = 0; s < g.n_species; ++s)
+            sto[(((size_t)(z / 8) * g.n_species + s) * P->Kp + k) * 8 + (z & 7)] =
+                st[((size_t)z * P->Kp + k) * g.n_species + s];
+      PLAN_HIP(hipMalloc(&P->d_stab_o, sizeof(float) * sto.size()));
+      PLAN_HIP(hipMemcpy(P->d_stab_o, sto.data(), sizeof(float) * sto.size(), hipMemcpyHostToDevice));
+    }
   }
   if (!build_op) {
     PLAN_HIP(hipStreamSynchronize(stream));
