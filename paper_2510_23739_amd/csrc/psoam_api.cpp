@@ -274,8 +274,12 @@ int enqueue_grad(psoam_plan* P, int op, const float* x, const float* p, float* g
   } else if (P->fact) {
     PSOAM_HIP(launch_switch_fwd(P, x, s));
     PSOAM_HIP(launch_band(P, 0, P->d_fq, nullptr, nullptr, s));
-    PSOAM_HIP(launch_eir_rows(P, 2, P->d_fq, P->d_fq, p, nullptr, s));
-    PSOAM_HIP(launch_pack_r(P, P->d_fq, s));
+    if (eir_pack_fits(P, true)) {
+      PSOAM_HIP(launch_eir_pack(P, P->d_fq, p, true, s));
+    } else {
+      PSOAM_HIP(launch_eir_rows(P, 2, P->d_fq, P->d_fq, p, nullptr, s));
+      PSOAM_HIP(launch_pack_r(P, P->d_fq, s));
+    }
     PSOAM_HIP(launch_band(P, 2, g, nullptr, nullptr, s));
   } else {
     PSOAM_HIP(launch_switch_fwd(P, x, s));
@@ -696,8 +700,12 @@ int psoam_apply_AT(const psoam_plan* plan, const float* y, float* c, void* strea
     return PSOAM_OK;
   }
   if (plan->fact) {
-    PSOAM_HIP(launch_eir_rows(plan, 1, plan->d_fq, y, nullptr, nullptr, S(stream)));
-    PSOAM_HIP(launch_pack_r(plan, plan->d_fq, S(stream)));
+    if (eir_pack_fits(plan, false)) {
+      PSOAM_HIP(launch_eir_pack(plan, y, nullptr, false, S(stream)));
+    } else {
+      PSOAM_HIP(launch_eir_rows(plan, 1, plan->d_fq, y, nullptr, nullptr, S(stream)));
+      PSOAM_HIP(launch_pack_r(plan, plan->d_fq, S(stream)));
+    }
     PSOAM_HIP(launch_band(plan, 2, c, nullptr, nullptr, S(stream)));
     return PSOAM_OK;
   }

@@ -243,6 +243,13 @@ size_t unmix_blocks(const psoam_plan* P);
 hipError_t launch_eir_rows(const psoam_plan* P, int mode, float* out, const float* in,
                            const float* p, double* partial, hipStream_t s);
 size_t eir_blocks(const psoam_plan* P);
+// factorised form, the H^T operand in one pass: V^T (V q - p) when resid
+// (p may be null), else V^T q, rounded straight into the 16-bit octet
+// operand (what launch_eir_rows followed by launch_pack_r would leave there).
+// Only for 16-bit plans whose rows fit the kernel's LDS: eir_pack_fits.
+bool eir_pack_fits(const psoam_plan* P, bool resid);
+hipError_t launch_eir_pack(const psoam_plan* P, const float* q, const float* p, bool resid,
+                           hipStream_t s);
 // sum over pulses of the anisotropic TV of (S c)^k into out[0] (FP64)
 hipError_t launch_tvs_sum(const psoam_plan* P, const float* c, double* partial, double* out,
                           hipStream_t s);

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "psoam_internal.h"
 
@@ -1919,6 +1920,214 @@ hipError_t launch_eir_rows(const psoam_plan* P, int mode, float* out, const floa
       return hipErrorInvalidValue;
   }
 #undef PSOAM_EIR
+  return hipGetLastError();
+}
+
+// The factorised H^T operand in one pass: the temporal pass (eq.
+// acoustic-temporal-conv) and its adjoint fused with the rounding and
+// packing of the 16-bit octet operand rq[pos][t/8][k][8] (pack_r16's layout,
+// samples shifted by tsh).  A block takes the 16 pulses kc..kc+15 of one scan
+// position; their rows sit in LDS between zero margins (kEirL samples
+// before, kEirR after, which cover every tap of every sample the block
+// reads; the row stride is odd so the 16 rows fall in different banks).
+//   RESID: r = V q - p (p may be null), then V^T r;  otherwise V^T q.
+// A thread makes 8 consecutive samples from a register window that slides
+// one sample per tap (one LDS read per tap instead of eight); the taps are
+// summed in the order eir_rows_kernel sums them.  The octet of (octet o,
+// pulse a) goes straight to HBM: 16 consecutive threads write the 256
+// contiguous bytes of one octet's 16 pulses.
+constexpr int kEirL = 40, kEirR = 64;
+constexpr size_t kEirPackMaxLds = 128 * 1024;
+__host__ __device__ inline int eir_pack_stride(int nt) { return (nt + kEirL + kEirR) | 1; }
+// the residual form holds two row buffers (46 KB at Nt 256, three blocks per
+// CU), so it runs 8 waves per block to keep 24 waves on a CU, as the
+// one-buffer form does with 4
+__host__ __device__ constexpr int eir_pack_threads(bool resid) { return resid ? 512 : 256; }
+
+template <int PREC, bool SPLIT, bool RESID>
+__global__ __launch_bounds__(512) void eir_pack16(const float* __restrict__ q,
+                                                  const float* __restrict__ pm, EirParams e,
+                                                  typename Half<PREC>::E* __restrict__ rq,
+                                                  typename Half<PREC>::E* __restrict__ rq_lo,
+                                                  int nk, int ny, int nx, int nt, int to_n,
+                                                  int kp, int xp, int r, size_t ps, int tsh) {
+  using H = Half<PREC>;
+  using V = typename H::V;
+  constexpr int NTH = eir_pack_threads(RESID);
+  extern __shared__ float ep_lds[];
+  const int sst = eir_pack_stride(nt);
+  float* qb = ep_lds;
+  float* rb = ep_lds + 16 * sst;
+  const int groups = kp / 16;
+  const int pos = (int)(blockIdx.x / groups);
+  const int kc = (int)(blockIdx.x % groups) * 16;
+  const int y = pos / nx, x = pos - y * nx;
+  const int tid = (int)threadIdx.x;
+  const size_t plane = (size_t)ny * nx * nt;              // pulse stride of the A-scans
+  const size_t col = ((size_t)y * nx + x) * nt;           // this position's row in a pulse
+  // residual units (8 samples of one row) and the measurements of this
+  // thread's first kEirPre units, loaded now so that their latency overlaps
+  // the staging of the rows
+  const int nu = (nt + 7) >> 3;
+  auto load_p = [&](int i, float (&p8)[8]) {
+    const int a = i / nu, t0 = (i - a * nu) * 8;
+    const int k = kc + a;
+    const bool live = pm && i < 16 * nu && k < nk;
+    const float* prow = live ? pm + (size_t)k * plane + col + t0 : pm;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) p8[u] = (live && t0 + u < nt) ? prow[u] : 0.0f;
+  };
+  constexpr int kEirPre = 2;
+  float pre[kEirPre][8];
+  if constexpr (RESID) {
+#pragma unroll
+    for (int m = 0; m < kEirPre; ++m) load_p(tid + m * NTH, pre[m]);
+  }
+  // zero margins: columns [0, kEirL) and [kEirL + nt, sst) of every row
+  const int padn = sst - nt;
+  for (int i = tid; i < 16 * padn; i += NTH) {
+    const int a = i / padn, m = i - a * padn;
+    const int cc = a * sst + (m < kEirL ? m : nt + m);
+    qb[cc] = 0.0f;
+    if constexpr (RESID) rb[cc] = 0.0f;
+  }
+  // the rows, kEirBatch loads in flight per thread before any LDS write
+  constexpr int kEirBatch = 8;
+  const int nin = 16 * nt;
+  for (int base = 0; base < nin; base += NTH * kEirBatch) {
+    float v[kEirBatch];
+#pragma unroll
+    for (int b = 0; b < kEirBatch; ++b) {
+      const int i = base + b * NTH + tid;
+      const int a = i / nt, t = i - a * nt;
+      v[b] = (i < nin && kc + a < nk) ? q[(size_t)(kc + a) * plane + col + t] : 0.0f;
+    }
+#pragma unroll
+    for (int b = 0; b < kEirBatch; ++b) {
+      const int i = base + b * NTH + tid;
+      const int a = i / nt, t = i - a * nt;
+      if (i < nin) qb[a * sst + kEirL + t] = v[b];
+    }
+  }
+  __syncthreads();
+  if constexpr (RESID) {
+    auto unit = [&](int i, const float (&pv)[8]) {
+      const int a = i / nu, t0 = (i - a * nu) * 8;
+      // src[u - j] = q[t0 + u - j + origin]
+      const float* src = qb + a * sst + kEirL + t0 + e.origin;
+      float w[8], acc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        w[u] = src[u];
+        acc[u] = 0.0f;
+      }
+      for (int j = 0; j < e.n; ++j) {
+        if (j > 0) {
+#pragma unroll
+          for (int u = 7; u > 0; --u) w[u] = w[u - 1];
+          w[0] = src[-j];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += e.v[j] * w[u];
+      }
+      float* dst = rb + a * sst + kEirL + t0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (t0 + u < nt) dst[u] = acc[u] - pv[u];
+    };
+    int i = tid;
+#pragma unroll
+    for (int m = 0; m < kEirPre; ++m, i += NTH)
+      if (i < 16 * nu) unit(i, pre[m]);
+    for (; i < 16 * nu; i += NTH) {
+      float pv[8];
+      load_p(i, pv);
+      unit(i, pv);
+    }
+    __syncthreads();
+  }
+  const float* sb = RESID ? rb : qb;
+  const size_t o_pos = ((size_t)(y + r) * xp + (x + r)) * ps;
+  for (int i = tid; i < 16 * to_n; i += NTH) {
+    const int o = i >> 4, a = i & 15;
+    const int t0 = o * 8 - tsh;
+    // src[u + j] = r[t0 + u + j - origin]
+    const float* src = sb + a * sst + kEirL + t0 - e.origin;
+    float w[8], acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      w[u] = src[u];
+      acc[u] = 0.0f;
+    }
+    for (int j = 0; j < e.n; ++j) {
+      if (j > 0) {
+#pragma unroll
+        for (int u = 0; u < 7; ++u) w[u] = w[u + 1];
+        w[7] = src[7 + j];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += e.v[j] * w[u];
+    }
+    V hi, lo;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float v = (t0 + u >= 0 && t0 + u < nt) ? acc[u] * H::scale : 0.0f;
+      hi[u] = (typename H::E)v;
+      lo[u] = (typename H::E)(v - (float)hi[u]);
+    }
+    const size_t off = o_pos + ((size_t)o * kp + kc + a) * 8;
+    *(V*)(rq + off) = hi;
+    if constexpr (SPLIT) *(V*)(rq_lo + off) = lo;
+  }
+}
+
+static size_t eir_pack_lds(const psoam_plan* P, bool resid) {
+  return sizeof(float) * 16 * (size_t)eir_pack_stride(P->g.nt) * (resid ? 2 : 1);
+}
+
+bool eir_pack_fits(const psoam_plan* P, bool resid) {
+  if (!P->fact || P->prec == PSOAM_FP32) return false;
+  // PSOAM_EIR_PACK=0 keeps the two-pass form (row pass, then pack_r16)
+  if (const char* ev = std::getenv("PSOAM_EIR_PACK"))
+    if (ev[0] == '0') return false;
+  return P->g.nt <= kMaxEirNt && eir_pack_lds(P, resid) <= kEirPackMaxLds;
+}
+
+hipError_t launch_eir_pack(const psoam_plan* P, const float* q, const float* p, bool resid,
+                           hipStream_t s) {
+  if (!eir_pack_fits(P, resid)) return hipErrorInvalidValue;
+  const auto& g = P->g;
+  const size_t lds = eir_pack_lds(P, resid);
+  const size_t nb = (size_t)g.ny * g.nx * (P->Kp / 16);
+  if (nb == 0) return hipSuccess;
+#define PSOAM_EP_R(PR, SP, RS)                                                              \
+  {                                                                                         \
+    using E = Half<PR>::E;                                                                  \
+    auto kern = eir_pack16<PR, SP, RS>;                                                     \
+    if (lds > 64 * 1024)                                                                    \
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                (int)lds);                                                  \
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(eir_pack_threads(RS)), lds, s, q, p, \
+                       P->eir,                                                              \
+                       (E*)P->d_rq, (E*)P->d_rq_lo, g.n_pulses, g.ny, g.nx, g.nt, P->Lt / 8, \
+                       P->Kp, P->Xp, P->R, P->ps_r, P->tsh);                                \
+  }
+#define PSOAM_EP(PR, SP)                                                                    \
+  {                                                                                         \
+    if (resid) PSOAM_EP_R(PR, SP, true) else PSOAM_EP_R(PR, SP, false)                      \
+    break;                                                                                  \
+  }
+  switch (P->prec) {
+    case PSOAM_BF16:
+    case PSOAM_BF16_REFINED: PSOAM_EP(PSOAM_BF16, false)
+    case PSOAM_FP16: PSOAM_EP(PSOAM_FP16, false)
+    case PSOAM_BF16_SPLIT: PSOAM_EP(PSOAM_BF16, true)
+    case PSOAM_FP16_SPLIT: PSOAM_EP(PSOAM_FP16, true)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef PSOAM_EP
+#undef PSOAM_EP_R
   return hipGetLastError();
 }
 

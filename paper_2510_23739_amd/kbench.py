@@ -85,6 +85,12 @@ def main():
     if "apply" in what:
         out["apply_A_ms"] = timed(lambda: plan.apply_A(c, y))
         out["apply_AT_ms"] = timed(lambda: plan.apply_AT(y, g))
+    if "solve" in what:
+        # solver iterations at a fixed step; A c stands in for the measurements
+        plan.apply_A(c, y)
+        x = torch.zeros_like(c)
+        out["solve_step_ms"] = timed(lambda: plan.solve(y, c=x, lambda_tv=1e-3, lambda_l1=1e-3,
+                                                        k1=5, k2=cfg.k2, alpha1=1e-3)) / 5
     if "tv" in what:
         out["prox_tv_k20_ms"] = timed(lambda: plan.prox_tv(c, 0.01, 20, x=g))
     if "r3" in what:

@@ -164,6 +164,35 @@ def test_factorised_fista_matches_oracle(prec, tol):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16_split", "fp16_split"])
+@pytest.mark.parametrize("which", ["ragged", "focus_before", "c1"])
+def test_one_pass_adjoint_operand_equals_two_pass(which, prec, monkeypatch):
+    """The H^T operand made in one pass (temporal pass, its adjoint, rounding
+    and packing fused) against the row pass followed by the packing kernel:
+    the external adjoint and the solver's iterates are bitwise equal, for
+    both operand shifts."""
+    torch = torch_cuda()
+    F = _standard(synth.C1) if which == "c1" else _ragged(which)
+    cfg = F.cfg
+    rng = np.random.default_rng(61)
+    y = torch.from_numpy(rng.standard_normal(cfg.y_shape).astype(np.float32)).cuda()
+    p = torch.from_numpy(rng.standard_normal(cfg.y_shape).astype(np.float32)).cuda()
+    for shift in ("0", "4"):
+        monkeypatch.setenv("PSOAM_ADJ_SHIFT", shift)
+        out = {}
+        for one_pass in ("1", "0"):
+            monkeypatch.setenv("PSOAM_EIR_PACK", one_pass)
+            plan = F.plan(prec)
+            g = plan.apply_AT(y, nan_buf(cfg.c_shape))
+            c, _ = plan.solve(p, lambda_tv=0.05, lambda_l1=0.02, k1=4, k2=3, alpha1=1e-3)
+            out[one_pass] = (g.cpu(), c.cpu())
+            plan.close()
+        say(f"[fact] one-pass H^T operand {which} {prec} shift {shift}: "
+            f"max |dg| {float((out['1'][0] - out['0'][0]).abs().max()):.3e}")
+        assert torch.equal(out["1"][0], out["0"][0])
+        assert torch.equal(out["1"][1], out["0"][1])
+
+
 def test_factorised_in_a_batch_matches_one_by_one():
     torch = torch_cuda()
     import paper_2510_23739_amd as pk
