@@ -35,7 +35,7 @@ extern "C" {
 enum {
   PSOAM_OK = 0,
   PSOAM_EINVAL = 1,       /* bad argument: null pointer, size, shape, option */
-  PSOAM_EUNSUPPORTED = 2, /* valid request this build does not implement */
+  PSOAM_EUNSUPPORTED = 2, /* valid request the library does not implement */
   PSOAM_EHIP = 3,         /* a HIP runtime call failed (message has the HIP error) */
   PSOAM_ENOMEM = 4,       /* device allocation failed */
   PSOAM_EDIVERGED = 5     /* a FP64 reduction of the solver was not finite */
