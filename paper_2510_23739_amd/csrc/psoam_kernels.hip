@@ -843,9 +843,10 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   }
 }
 
-// H and the residual form run two waves per SIMD (their LDS tile allows two
-// or three workgroups per CU); the S^T epilogue of H^T needs more registers
-// and its wider staged window allows one workgroup per CU anyway.
+// H and the residual form are held to three waves per SIMD with one-part
+// operands (three 4-row workgroups of ~47 KB share a CU at 31 x 31
+// footprints) and to two with split operands (their second band-block
+// buffer needs the registers).
 template <int PREC, bool SPLIT, int MODE, int ROWS>
 __global__ __launch_bounds__(64 * ROWS) __attribute__((amdgpu_waves_per_eu(!SPLIT ? 3 : 2))) void band16_lds(
     BandArgs A, LdsArgs L) {
