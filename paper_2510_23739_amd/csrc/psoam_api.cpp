@@ -141,11 +141,16 @@ double mu_tv(const psoam_geom& g) {
   return mu;
 }
 
+// pulses of u2 rounded up to its groups of four
+static size_t r3_kv(const psoam_plan* P) {
+  return (size_t)((P->g.n_pulses + 3) / 4 * 4) * P->v_elems();
+}
+
 // floats of one set of duals of the full regulariser: u1 [3][S][V],
-// u2 [3][K][V], u3 [S][V], each 256-byte aligned
+// u2 [3][ceil(K/4)][V][4], u3 [S][V], each 256-byte aligned
 size_t r3_set_floats(const psoam_plan* P) {
   auto al = [](size_t n) { return (n + 63) / 64 * 64; };
-  const size_t sv = P->c_elems(), kv = (size_t)P->g.n_pulses * P->v_elems();
+  const size_t sv = P->c_elems(), kv = r3_kv(P);
   return al(3 * sv) + al(3 * kv) + al(sv);
 }
 
@@ -159,7 +164,7 @@ struct R3Bufs {
 // three dual sets and w carved from a 256-byte aligned block
 R3Bufs r3_carve(const psoam_plan* P, void* base) {
   auto al = [](size_t n) { return (n + 63) / 64 * 64; };
-  const size_t sv = P->c_elems(), kv = (size_t)P->g.n_pulses * P->v_elems();
+  const size_t sv = P->c_elems(), kv = r3_kv(P);
   float* p = (float*)base;
   R3Bufs B;
   for (int i = 0; i < 3; ++i) {

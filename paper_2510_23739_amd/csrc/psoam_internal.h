@@ -212,7 +212,8 @@ hipError_t launch_set_double(double* p, double v, hipStream_t s);
 //   w = z - (grad^T eta1 + S^T grad^T eta2 + eta3)   [clamp_out: max(., 0)]
 //   u1' = clip(eta1 + step0 grad w), u2' = clip(eta2 + step1 grad S w),
 //   u3' = clip(eta3 + step2 w)  at radii theta[0..2]
-// duals u1 [3][S][V], u2 [3][K][V], u3 [S][V]; eta from (current, previous)
+// duals u1 [3][S][V], u2 [3][ceil(K/4)][V][4] (four pulses per 16-byte
+// word), u3 [S][V]; eta from (current, previous)
 hipError_t launch_r3_w(const psoam_plan* P, float* out, const float* z, const float* u1c,
                        const float* u1p, const float* u2c, const float* u2p, const float* u3c,
                        const float* u3p, float beta, int clamp_out, hipStream_t s);

@@ -1461,6 +1461,23 @@ __device__ __forceinline__ float eta3(const float* __restrict__ uc, const float*
   return up ? a + beta * (a - up[i]) : a;
 }
 
+// eta of four pulses at once (u2 is stored in groups of four pulses, see below)
+__device__ __forceinline__ f32x4 eta4(const f32x4* __restrict__ uc, const f32x4* __restrict__ up,
+                                      float beta, int64_t i) {
+  if (!uc) return f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  const f32x4 a = uc[i];
+  if (!up) return a;
+  const f32x4 b = up[i];
+  f32x4 r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) r[q] = a[q] + beta * (a[q] - b[q]);
+  return r;
+}
+
+// u2 layout: [3][ceil(K/4)][V][4], pulse k of direction d at voxel v in float
+// ((d * ceil(K/4) + k / 4) * V + v) * 4 + k % 4, so a thread reads the duals
+// of four pulses with one 16-byte load (consecutive voxels stay consecutive
+// 16-byte words); the padding pulses of the last group are kept at zero.
 // w = z - (grad^T eta1 + S^T grad^T eta2 + eta3); with clamp_out the
 // algorithm's output max(., 0) instead.  One thread per voxel position, all
 // species.
@@ -1483,17 +1500,32 @@ __global__ __launch_bounds__(256) void r3_w_kernel(
   float acc[kMaxSpecies];
 #pragma unroll
   for (int s = 0; s < kMaxSpecies; ++s) acc[s] = 0.0f;
-  // S^T grad^T eta2, pulse by pulse
-#pragma unroll 2
-  for (int k = 0; k < nk; ++k) {
-    float gt = 0.0f;
+  // S^T grad^T eta2, four pulses at a time (summed into acc pulse by pulse)
+  const int nk4 = (nk + 3) >> 2;
+  const f32x4* c4 = (const f32x4*)u2c;
+  const f32x4* p4 = (const f32x4*)u2p;
+  for (int kg = 0; kg < nk4; ++kg) {
+    f32x4 gt = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const int64_t base = ((int64_t)d * nk + k) * vol;
-      if (idx[d] > 0) gt += eta3(u2c, u2p, beta, base + v - st[d]);
-      if (idx[d] < nd[d] - 1) gt -= eta3(u2c, u2p, beta, base + v);
+      const int64_t base = ((int64_t)d * nk4 + kg) * vol;
+      if (idx[d] > 0) {
+        const f32x4 e = eta4(c4, p4, beta, base + v - st[d]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gt[q] += e[q];
+      }
+      if (idx[d] < nd[d] - 1) {
+        const f32x4 e = eta4(c4, p4, beta, base + v);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gt[q] -= e[q];
+      }
     }
-    for (int s = 0; s < ns; ++s) acc[s] += coef_zt(sw, phi, stab, G.nz, col, iz, k, s) * gt;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = kg * 4 + q;
+      if (k < nk)
+        for (int s = 0; s < ns; ++s) acc[s] += coef_zt(sw, phi, stab, G.nz, col, iz, k, s) * gt[q];
+    }
   }
   for (int s = 0; s < ns; ++s) {
     float gt = 0.0f;
@@ -1552,31 +1584,47 @@ __global__ __launch_bounds__(256) void r3_u_kernel(
   const size_t colq[3] = {col0 + (size_t)st[0], col0 + (size_t)st[1], col0};
   const int zq[3] = {iz, iz, iz + 1};
   const int zn = fwd[2] ? iz + 1 : iz;
-#pragma unroll 2
-  for (int k = 0; k < nk; ++k) {
-    float sq[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (stab) {
-      for (int s = 0; s < ns; ++s) {
-        const float c0 = stab[((size_t)k * ns + s) * G.nz + iz];
-        const float c1 = stab[((size_t)k * ns + s) * G.nz + zn];
-        sq[0] += c0 * wv[0][s];
-        sq[1] += c0 * wv[1][s];
-        sq[2] += c0 * wv[2][s];
-        sq[3] += c1 * wv[3][s];
-      }
-    } else {
-      for (int s = 0; s < ns; ++s) {
-        sq[0] += scoef(sw, phi[col0 + iz], k, s) * wv[0][s];
+  // u2 in groups of four pulses (layout above r3_w_kernel)
+  const int nk4 = (nk + 3) >> 2;
+  const f32x4* c4 = (const f32x4*)u2c;
+  const f32x4* p4 = (const f32x4*)u2p;
+  f32x4* o4 = (f32x4*)n2;
+  for (int kg = 0; kg < nk4; ++kg) {
+    float sq[4][4];
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-          if (fwd[d]) sq[d + 1] += scoef(sw, phi[colq[d] + zq[d]], k, s) * wv[d + 1][s];
+    for (int q = 0; q < 4; ++q) {
+      const int k = kg * 4 + q;
+      sq[q][0] = sq[q][1] = sq[q][2] = sq[q][3] = 0.0f;
+      if (k >= nk) continue;
+      if (stab) {
+        for (int s = 0; s < ns; ++s) {
+          const float c0 = stab[((size_t)k * ns + s) * G.nz + iz];
+          const float c1 = stab[((size_t)k * ns + s) * G.nz + zn];
+          sq[q][0] += c0 * wv[0][s];
+          sq[q][1] += c0 * wv[1][s];
+          sq[q][2] += c0 * wv[2][s];
+          sq[q][3] += c1 * wv[3][s];
+        }
+      } else {
+        for (int s = 0; s < ns; ++s) {
+          sq[q][0] += scoef(sw, phi[col0 + iz], k, s) * wv[0][s];
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            if (fwd[d]) sq[q][d + 1] += scoef(sw, phi[colq[d] + zq[d]], k, s) * wv[d + 1][s];
+        }
       }
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const float g = fwd[d] ? sq[d + 1] - sq[0] : 0.0f;
-      const int64_t i = ((int64_t)d * nk + k) * vol + v;
-      n2[i] = fminf(fmaxf(eta3(u2c, u2p, beta, i) + s2 * g, -th2), th2);
+      const int64_t i = ((int64_t)d * nk4 + kg) * vol + v;
+      const f32x4 e = eta4(c4, p4, beta, i);
+      f32x4 r;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float g = fwd[d] ? sq[q][d + 1] - sq[q][0] : 0.0f;
+        r[q] = kg * 4 + q < nk ? fminf(fmaxf(e[q] + s2 * g, -th2), th2) : 0.0f;
+      }
+      o4[i] = r;
     }
   }
 }
