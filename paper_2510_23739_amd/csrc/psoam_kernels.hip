@@ -396,21 +396,26 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
   } else if constexpr (MODE == 1) {
     const int nt = A.nt;
     if (k >= A.nk) return;
-    // the measurements of all NP positions first (one 16-byte load per
-    // position where the lane's four samples are aligned and inside the
-    // A-scan), so their latency is paid once
+    // 16-bit operand (the staged kernels): the measurements of all NP
+    // positions first (one 16-byte load per position where the lane's four
+    // samples are aligned and inside the A-scan), so their latency is paid
+    // once.  The FP32 kernel has no registers to spare for them (its
+    // occupancy would drop) and loads them position by position.
+    constexpr bool kPre = RQ_PREC != PSOAM_FP32;
     const bool vec = A.pmeas && ((uintptr_t)A.pmeas & 15) == 0 && (nt & 3) == 0 && row0 + 3 < nt;
-    f32x4 pv[NP];
+    f32x4 pv[kPre ? NP : 1];
+    if constexpr (kPre) {
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int ix = ix0 + p;
-      const size_t yi = (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
-      if (vec && ix < A.nx) {
-        pv[p] = *(const f32x4*)(A.pmeas + yi);
-      } else {
+      for (int p = 0; p < NP; ++p) {
+        const int ix = ix0 + p;
+        const size_t yi = (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
+        if (vec && ix < A.nx) {
+          pv[p] = *(const f32x4*)(A.pmeas + yi);
+        } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          pv[p][j] = (A.pmeas && ix < A.nx && row0 + j < nt) ? A.pmeas[yi + j] : 0.0f;
+          for (int j = 0; j < 4; ++j)
+            pv[p][j] = (A.pmeas && ix < A.nx && row0 + j < nt) ? A.pmeas[yi + j] : 0.0f;
+        }
       }
     }
 #pragma unroll
@@ -418,12 +423,13 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
       const int ix = ix0 + p;
       if (ix >= A.nx) continue;
       const size_t pos = ((size_t)(iy + A.r) * A.xp + (ix + A.r)) * A.ps_r;
+      const size_t yi = (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
       float rv[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const bool ok = row0 + j < nt;
         float v = acc[p][j] * A.inv_scale;
-        if (A.pmeas && ok) v -= pv[p][j];
+        if (A.pmeas && ok) v -= kPre ? pv[kPre ? p : 0][j] : A.pmeas[yi + j];
         rv[j] = ok ? v : 0.0f;
         ss += (double)rv[j] * (double)rv[j];
       }
