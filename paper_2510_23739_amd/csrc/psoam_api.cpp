@@ -263,8 +263,9 @@ int prepare_p(psoam_plan* P, int op, const float* p, hipStream_t s) {
 
 // g = A^T (A x - p), or A^T A x when p is null.  General form: S and H with
 // the residual in H's epilogue, then H^T with S^T.  Factorised form: the
-// shell sums q = Lambda S x, then V^T (V q - p) row by row in place, then
-// Lambda^T with S^T.  Separable form: h = H of
+// shell sums q = Lambda S x, then V^T (V q - p) written straight into the
+// 16-bit H^T operand (or, for rows too long for that kernel's LDS and for
+// FP32, in place row by row and then packed), then Lambda^T with S^T.  Separable form: h = H of
 // phi x_s over the S species, A^T (A x - p) = phi H^T(G h - T^T p) with
 // G = T^T T (prepare_p has put T^T p in d_q), never forming A x itself.
 int enqueue_grad(psoam_plan* P, int op, const float* x, const float* p, float* g, hipStream_t s) {

@@ -230,6 +230,28 @@ def test_fista_C1_matches_oracle(c1, prec, tol):
     assert oracle.rel_err(c.cpu().numpy(), c_true) < 1.0
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_solve_with_unaligned_measurements(c1, prec):
+    """Measurements at an address that is not 16-byte aligned (a view one
+    float into a buffer): the residual epilogue takes its per-sample loads
+    and the iterates equal those of the aligned call bit for bit."""
+    torch = torch_cuda()
+    cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
+    p, A, AT, lam_tv, lam_l1 = _c1_problem(c1)
+    plan = lib_plan(cfg, t0, taps, phi, sp, prec)
+    pa = torch.from_numpy(p).cuda()
+    buf = torch.zeros(p.size + 1, dtype=torch.float32, device="cuda")
+    pu = buf[1:].view(p.shape)
+    pu.copy_(pa)
+    assert pu.data_ptr() % 16 != 0
+    o = dict(lambda_tv=lam_tv, lambda_l1=lam_l1, k1=5, k2=5, alpha1=1e-3)
+    ca, sa = plan.solve(pa, **o)
+    cu, su = plan.solve(pu, **o)
+    say(f"[parity] unaligned measurements {prec}: max |dc| {float((ca - cu).abs().max()):.3e}")
+    assert torch.equal(ca, cu)
+    plan.close()
+
+
 def test_fista_trace_and_stopping(c1):
     torch = torch_cuda()
     cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
