@@ -2,7 +2,9 @@
 
     python -m paper_2510_23739_amd.build
 
-Objects are compiled in parallel and linked into paper_2510_23739_amd/libpsoam.so.
+Objects are compiled in parallel and linked into paper_2510_23739_amd/libpsoam.so;
+the matrix-core calibration loop of the kernel micro-benchmark goes into
+libpsoam_calib.so beside it.
 """
 from __future__ import annotations
 
@@ -19,6 +21,9 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpsoam.so")
 SOURCES = ["psoam_kernels.hip", "psoam_plan.cpp", "psoam_api.cpp"]
+# the matrix-core calibration loop of the kernel micro-benchmark, a library of its own
+CALIB_LIB = os.path.join(PKG, "libpsoam_calib.so")
+CALIB_SOURCES = ["calib.hip"]
 ARCH = os.environ.get("PSOAM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -46,18 +51,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib: str) -> None:
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = SOURCES + CALIB_SOURCES
+    with cf.ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = list(ex.map(_compile, srcs))
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], CALIB_LIB)
     if verbose:
         print(f"built {LIB}")
+        print(f"built {CALIB_LIB}")
     return LIB
 
 

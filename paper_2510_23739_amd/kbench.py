@@ -67,6 +67,28 @@ def main():
 
     out = {"config": cfg.name, "prec": args.prec, "factorised": args.fact, "stats": plan.stats()}
     what = args.what.split(",")
+    if "mfma" in what:
+        # dense BF16 matrix-core rate of this device: a loop of
+        # v_mfma_f32_16x16x32_bf16 on independent accumulators, 8 blocks per CU
+        import ctypes as C
+        lib = C.CDLL(os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpsoam_calib.so"))
+        lib.psoam_calib_mfma_bf16.restype = C.c_int
+        lib.psoam_calib_mfma_bf16.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        blocks, iters = 8 * cus, 512
+        buf = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+
+        def mfma_loop():
+            rc = lib.psoam_calib_mfma_bf16(C.c_void_p(buf.data_ptr()), blocks, iters,
+                                           C.c_void_p(st.cuda_stream))
+            if rc:
+                raise RuntimeError(f"psoam_calib_mfma_bf16 returned {rc}")
+
+        ms = timed(mfma_loop)
+        flops = blocks * 4 * iters * 8 * 16 * 16 * 32 * 2
+        out["mfma_bf16_cus"] = cus
+        out["mfma_bf16_ms"] = ms
+        out["mfma_bf16_tflops"] = flops / (ms * 1e-3) / 1e12
     if "copy" in what:
         # plain device copy of a known size: calibrates the HBM byte counters
         n = 1 << 28  # 1 GiB of float32

@@ -151,3 +151,17 @@ def test_factorised_validation_before_device_work(lib):
     # a radius step so small that one voxel spans more than 64 samples
     assert call(_lib.Geom(4, 4, 6, 2, 3, 400, 3, 0, 0), sh(dr=0.01, t_focus=200)) == _lib.EUNSUPPORTED
     assert b"wider" in lib.psoam_last_error()
+
+
+def test_calibration_library_is_separate():
+    """The matrix-core calibration loop lives in its own library: built
+    beside libpsoam.so, exporting its one entry point (which rejects bad
+    arguments before any launch), and absent from the reconstruction ABI."""
+    from paper_2510_23739_amd import build
+    assert os.path.exists(build.CALIB_LIB), "libpsoam_calib.so is not built"
+    cal = C.CDLL(build.CALIB_LIB)
+    fn = cal.psoam_calib_mfma_bf16
+    fn.restype = C.c_int
+    fn.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    assert fn(None, 8, 8, None) == 1
+    assert "psoam_calib_mfma_bf16" not in _declared()
