@@ -463,6 +463,14 @@ def main():
         "precisions": per_prec,
         "separable_form": sep,
     }
+    # the launch-shape autotuner on the headline workload (its choice and the
+    # kernel times it measured; the timed plan above uses the built-in rules)
+    if not args.headline_only:
+        log(f"[bench] autotune {args.prec}")
+        t_tune = time.perf_counter()
+        tp = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=args.prec, tune=True)
+        out["autotune"] = dict(tp.tune_report, seconds=time.perf_counter() - t_tune)
+        tp.close()
     fact = None
     if args.headline_only:
         cpu_leg(out, args, torch, pk, cfg, t0, taps, phi, sp, c_true, samples, fact, precs)

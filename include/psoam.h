@@ -345,6 +345,36 @@ int psoam_plan_stats(const psoam_plan* plan, psoam_plan_info* info);
  * equals the matching apply's only after that apply ran on the same input. */
 int psoam_band_only(const psoam_plan* plan, int32_t dir, float* out, void* stream);
 
+/* What psoam_plan_create_tuned chose and measured. */
+typedef struct {
+  int32_t h_rows;        /* output rows per workgroup of the staged H kernel (0: not staged) */
+  int32_t ht_rows;       /* the same for S^T H^T */
+  int32_t ht_shift;      /* sample shift of the 16-bit H^T operand (0 or 4) */
+  int32_t candidates;    /* launch shapes timed (0: nothing to tune, or taken from the cache) */
+  int32_t from_cache;    /* 1 when the choice came from this process's cache */
+  double h_ms, ht_ms;    /* kernel times of the choice (residual form of H; S^T H^T) */
+  double h_ms_default, ht_ms_default;  /* the same for the plan's own rules' choice */
+} psoam_tune_report;
+
+/* psoam_plan_create with the launch shape of the band kernels chosen by
+ * measurement: for a 16-bit plan of the general form it builds the plan the
+ * built-in rules choose and the alternatives that fit the LDS (4 or 8
+ * output rows per workgroup for H and for H^T, operand shift 0 or 4 for
+ * H^T), times each kernel's solver form on `stream` (HIP events, one warm-up
+ * and three timed launches on the zeroed operands), and returns the plan
+ * with the fastest H and the fastest H^T.  Results do not depend on the
+ * choice (the same products are summed in the same order).  The choice is
+ * cached per process, keyed by the geometry, precision and a hash of the
+ * impulse-response table, so a second call with the same inputs only builds
+ * the plan.  FP32 and separable plans have nothing to tune and are built
+ * directly.  For callers who create a plan once and apply it many times:
+ * tuning builds up to six plans (about 0.25 s at 128 x 128 x 64).  `report` may
+ * be null.  Errors as psoam_plan_create; synchronises `stream`. */
+int psoam_plan_create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
+                            const int32_t* sir_t0, const float* sir_taps, int32_t sir_w,
+                            int32_t prec, void* stream, psoam_plan** out,
+                            psoam_tune_report* report);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* psoam_last_error(void);
 

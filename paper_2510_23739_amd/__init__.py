@@ -47,7 +47,9 @@ class Plan:
 
     def __init__(self, nx: int, ny: int, nz: int, n_pulses: int, nt: int, f: int,
                  phi: np.ndarray, species, t0: np.ndarray, taps: np.ndarray,
-                 prec: str = "fp32", stream=None, separable: bool = False):
+                 prec: str = "fp32", stream=None, separable: bool = False, tune: bool = False):
+        """tune: choose the band kernels' launch shape by measurement
+        (psoam_plan_create_tuned); what was chosen is in self.tune_report."""
         lib = load()
         species_a, species_b, species_tau = list(species.a), list(species.b), list(species.tau)
         ns = len(species_a)
@@ -64,12 +66,16 @@ class Plan:
             raise ValueError("impulse-response table shape does not match (nz, f, f)")
         handle = C.c_void_p()
         self._h = None
-        check(lib.psoam_plan_create(C.byref(self.geom), C.byref(sp),
-                                    phi.ctypes.data_as(C.c_void_p),
-                                    self._t0.ctypes.data_as(C.c_void_p),
-                                    self._taps.ctypes.data_as(C.c_void_p),
-                                    int(self._taps.shape[3]), PREC[prec], _stream(stream),
-                                    C.byref(handle)))
+        args = (C.byref(self.geom), C.byref(sp), phi.ctypes.data_as(C.c_void_p),
+                self._t0.ctypes.data_as(C.c_void_p), self._taps.ctypes.data_as(C.c_void_p),
+                int(self._taps.shape[3]), PREC[prec], _stream(stream), C.byref(handle))
+        self.tune_report = None
+        if tune:
+            rep = _lib.TuneReport()
+            check(lib.psoam_plan_create_tuned(*args, C.byref(rep)))
+            self.tune_report = {name: getattr(rep, name) for name, _ in _lib.TuneReport._fields_}
+        else:
+            check(lib.psoam_plan_create(*args))
         self._h = handle
         self.prec = prec
         self.c_shape = (ns, ny, nx, nz)
@@ -139,9 +145,10 @@ class Plan:
         return self
 
     @classmethod
-    def from_config(cls, cfg, phi, species, t0, taps, prec="fp32", stream=None, separable=False):
+    def from_config(cls, cfg, phi, species, t0, taps, prec="fp32", stream=None, separable=False,
+                    tune=False):
         return cls(cfg.nx, cfg.ny, cfg.nz, cfg.n_pulses, cfg.nt, cfg.f, phi, species, t0, taps,
-                   prec=prec, stream=stream, separable=separable)
+                   prec=prec, stream=stream, separable=separable, tune=tune)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -46,10 +46,21 @@ class PlanInfo(C.Structure):
                 ("lds_bytes", C.c_int64 * 2), ("lds_rows", C.c_int32 * 2)]
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("h_rows", C.c_int32), ("ht_rows", C.c_int32), ("ht_shift", C.c_int32),
+                ("candidates", C.c_int32), ("from_cache", C.c_int32),
+                ("h_ms", C.c_double), ("ht_ms", C.c_double),
+                ("h_ms_default", C.c_double), ("ht_ms_default", C.c_double)]
+
+
 EXPORTS = {
     "psoam_plan_create": (C.c_int, [C.POINTER(Geom), C.POINTER(Species), C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
+    "psoam_plan_create_tuned": (C.c_int, [C.POINTER(Geom), C.POINTER(Species), C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                          C.c_void_p, C.POINTER(C.c_void_p),
+                                          C.POINTER(TuneReport)]),
     "psoam_plan_destroy": (C.c_int, [C.c_void_p]),
     "psoam_plan_create_acoustic": (C.c_int, [C.POINTER(Geom), C.c_void_p, C.c_void_p, C.c_int32,
                                              C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),

@@ -4,9 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -656,12 +660,197 @@ int solve_batch_graph(std::vector<BatchItem>& items, hipStream_t caller) {
 
 using namespace psoam;
 
+namespace psoam {
+namespace {
+
+// ---- launch-shape autotuner (psoam_plan_create_tuned) ---------------------
+// The choice: rows per staged workgroup of H and of H^T, and the H^T operand
+// shift.  Measured per process and cached by geometry, precision and a hash
+// of the impulse-response table.
+struct Shape {
+  int h_rows = 0, ht_rows = 0, tsh = 0;
+  bool operator==(const Shape& o) const {
+    return h_rows == o.h_rows && ht_rows == o.ht_rows && tsh == o.tsh;
+  }
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, Shape> g_tune_cache;
+
+std::string tune_key(const psoam_geom& g, int32_t sir_w, int32_t prec, const int32_t* t0,
+                     const float* taps) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the table bytes
+  auto mix = [&h](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  const size_t ntab = (size_t)g.nz * g.f * g.f;
+  mix(t0, ntab * sizeof(int32_t));
+  mix(taps, ntab * (size_t)sir_w * sizeof(float));
+  char buf[200];
+  std::snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %d %d %d %016llx", g.nx, g.ny, g.nz,
+                g.n_species, g.n_pulses, g.nt, g.f, g.phi_per_voxel, sir_w, prec,
+                (unsigned long long)h);
+  return buf;
+}
+
+Shape shape_of(const psoam_plan* P) {
+  Shape s;
+  s.h_rows = P->fwd.lds_ok ? P->fwd.rows : 0;
+  s.ht_rows = P->adj.lds_ok ? P->adj.rows : 0;
+  s.tsh = P->tsh;
+  return s;
+}
+
+// average ms of the band kernel of direction dir in the solver's form
+// (dir 0: H with the residual epilogue, dir 1: S^T H^T), one warm-up launch
+int time_band(psoam_plan* P, int dir, hipStream_t s, double* ms) {
+  SolveBufs B;
+  if (int rc = ensure_solve_ws(P, B)) return rc;
+  auto launch = [&]() {
+    return dir == 0 ? launch_band(P, 1, nullptr, nullptr, P->d_partial, s)
+                    : launch_band(P, 2, B.g, nullptr, nullptr, s);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  constexpr int kReps = 3;
+  for (int i = 0; i < kReps && e == hipSuccess; ++i) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "autotune: timing launch");
+  *ms = (double)t / kReps;
+  return PSOAM_OK;
+}
+
+// a plan built with the given launch shape (0 entries: the plan's own rules)
+int build_shaped(const psoam_geom* g, const psoam_species* sp, const float* phi,
+                 const int32_t* t0, const float* taps, int32_t sir_w, int32_t prec,
+                 hipStream_t s, const Shape& want, psoam_plan** out) {
+  set_tune_choice(want.h_rows, want.ht_rows, want.tsh);
+  const int rc = create_plan(g, sp, phi, t0, taps, sir_w, prec, s, out);
+  clear_tune_choice();
+  return rc;
+}
+
+int create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
+                 const int32_t* t0, const float* taps, int32_t sir_w, int32_t prec,
+                 hipStream_t s, psoam_plan** out, psoam_tune_report* rep) {
+  psoam_tune_report r{};
+  auto done = [&](psoam_plan* P) {
+    const Shape got = shape_of(P);
+    r.h_rows = got.h_rows;
+    r.ht_rows = got.ht_rows;
+    r.ht_shift = got.tsh;
+    if (rep) *rep = r;
+    *out = P;
+    return PSOAM_OK;
+  };
+  if (!out) return fail(PSOAM_EINVAL, "plan_create_tuned: out is NULL");
+  *out = nullptr;
+  if (!g || !sp || !phi || !t0 || !taps) return fail(PSOAM_EINVAL, "plan_create_tuned: NULL argument");
+  psoam_plan* P = nullptr;
+  if (g->separable != 0 || prec == PSOAM_FP32) {
+    if (int rc = create_plan(g, sp, phi, t0, taps, sir_w, prec, s, &P)) return rc;
+    return done(P);
+  }
+  if (sir_w < 1 || sir_w > 64 || g->nz <= 0 || g->f <= 0)
+    return create_plan(g, sp, phi, t0, taps, sir_w, prec, s, out);  // its own errors
+  const std::string key = tune_key(*g, sir_w, prec, t0, taps);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      const Shape want = it->second;
+      if (int rc = build_shaped(g, sp, phi, t0, taps, sir_w, prec, s, want, &P)) return rc;
+      r.from_cache = 1;
+      return done(P);
+    }
+  }
+  // the plan's own choice, timed
+  if (int rc = create_plan(g, sp, phi, t0, taps, sir_w, prec, s, &P)) return rc;
+  const Shape base = shape_of(P);
+  double h_best = 0.0, ht_best = 0.0;
+  int rc = PSOAM_OK;
+  if (base.h_rows) rc = time_band(P, 0, s, &h_best);
+  if (rc == PSOAM_OK && base.ht_rows) rc = time_band(P, 1, s, &ht_best);
+  if (rc != PSOAM_OK) {
+    free_plan(P);
+    return rc;
+  }
+  r.candidates = 1;
+  r.h_ms_default = h_best;
+  r.ht_ms_default = ht_best;
+  Shape best = base;
+  // alternatives: the other row count for H; the other row counts and
+  // shifts for H^T (each timed on the direction it changes)
+  std::vector<std::pair<Shape, int>> alts;
+  if (base.h_rows) alts.push_back({Shape{base.h_rows == 4 ? 8 : 4, base.ht_rows, base.tsh}, 0});
+  if (base.ht_rows)
+    for (int rows : {4, 8})
+      for (int tsh : {0, 4})
+        if (rows != base.ht_rows || tsh != base.tsh) alts.push_back({Shape{base.h_rows, rows, tsh}, 1});
+  for (const auto& a : alts) {
+    psoam_plan* Q = nullptr;
+    if ((rc = build_shaped(g, sp, phi, t0, taps, sir_w, prec, s, a.first, &Q))) break;
+    const Shape got = shape_of(Q);
+    double ms = 0.0;
+    if (got == a.first) {  // it fitted
+      rc = time_band(Q, a.second, s, &ms);
+      ++r.candidates;
+    }
+    free_plan(Q);
+    if (rc != PSOAM_OK) break;
+    if (!(got == a.first)) continue;
+    if (a.second == 0 && ms < h_best) {
+      h_best = ms;
+      best.h_rows = a.first.h_rows;
+    }
+    if (a.second == 1 && ms < ht_best) {
+      ht_best = ms;
+      best.ht_rows = a.first.ht_rows;
+      best.tsh = a.first.tsh;
+    }
+  }
+  if (rc != PSOAM_OK) {
+    free_plan(P);
+    return rc;
+  }
+  r.h_ms = h_best;
+  r.ht_ms = ht_best;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  if (best == base) return done(P);
+  free_plan(P);
+  P = nullptr;
+  if ((rc = build_shaped(g, sp, phi, t0, taps, sir_w, prec, s, best, &P))) return rc;
+  return done(P);
+}
+
+}  // namespace
+}  // namespace psoam
+
 extern "C" {
 
 int psoam_plan_create(const psoam_geom* g, const psoam_species* sp, const float* phi,
                       const int32_t* sir_t0, const float* sir_taps, int32_t sir_w,
                       int32_t prec, void* stream, psoam_plan** out) {
   return create_plan(g, sp, phi, sir_t0, sir_taps, sir_w, prec, S(stream), out);
+}
+
+int psoam_plan_create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
+                            const int32_t* sir_t0, const float* sir_taps, int32_t sir_w,
+                            int32_t prec, void* stream, psoam_plan** out,
+                            psoam_tune_report* report) {
+  return create_tuned(g, sp, phi, sir_t0, sir_taps, sir_w, prec, S(stream), out, report);
 }
 
 int psoam_plan_destroy(psoam_plan* plan) {

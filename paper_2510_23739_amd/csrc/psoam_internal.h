@@ -154,6 +154,14 @@ struct psoam_plan {
 
 namespace psoam {
 
+// Launch-shape choice for the next plan built on this thread (the
+// autotuner's lever): output rows per staged workgroup for H (rows_fwd) and
+// H^T (rows_adj), 4 or 8, and the H^T operand shift, 0 or 4; any other value
+// leaves that choice to the plan's own rules.  A choice that does not fit
+// the LDS is ignored.
+void set_tune_choice(int rows_fwd, int rows_adj, int tsh);
+void clear_tune_choice();
+
 // thread-local error message
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);

@@ -20,6 +20,14 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// launch-shape choice of the autotuner for the plan being built (0: the
+// plan's own rules)
+struct TuneChoice {
+  int rows[2] = {0, 0};
+  int tsh = -1;
+};
+thread_local TuneChoice g_tune;
+
 inline uint16_t to_bf16(float f) {
   // round to nearest even, NaN preserved
   uint32_t u;
@@ -58,6 +66,14 @@ struct Group {
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+void set_tune_choice(int rows_fwd, int rows_adj, int tsh) {
+  g_tune.rows[0] = rows_fwd;
+  g_tune.rows[1] = rows_adj;
+  g_tune.tsh = tsh;
+}
+
+void clear_tune_choice() { g_tune = TuneChoice(); }
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
@@ -363,6 +379,9 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
     if (fr[0] == '8' && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
     if (fr[0] == '4' && lds4 <= (size_t)kLdsMaxBytes) rows = 4;
   }
+  // the autotuner's choice, when it fits
+  if (g_tune.rows[dir] == 8 && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
+  if (g_tune.rows[dir] == 4 && lds4 <= (size_t)kLdsMaxBytes) rows = 4;
   std::vector<uint32_t>& win = rows == 8 ? win8 : win4;
   T.rows = rows;
   T.max_oct = rows == 8 ? mo8 : mo4;
@@ -626,6 +645,7 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
     P->tsh = (s4 > s0 || (s4 == s0 && w4 < w0)) ? 4 : 0;
     // PSOAM_ADJ_SHIFT=0 or 4 overrides the choice (tests cover both)
     if (const char* e = std::getenv("PSOAM_ADJ_SHIFT")) P->tsh = e[0] == '4' ? 4 : 0;
+    if (g_tune.tsh == 0 || g_tune.tsh == 4) P->tsh = g_tune.tsh;  // the autotuner's choice
   }
   P->Lt = (g.nt + 15) / 16 * 16 + (P->tsh ? 16 : 0);
   P->ps_b = (size_t)P->Lz * P->Kp;

@@ -107,6 +107,14 @@ def main():
     if "apply" in what:
         out["apply_A_ms"] = timed(lambda: plan.apply_A(c, y))
         out["apply_AT_ms"] = timed(lambda: plan.apply_AT(y, g))
+    if "tune" in what and not args.fact:
+        # the launch-shape autotuner on this workload: wall time and choice
+        import time
+        t_0 = time.perf_counter()
+        tp = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=args.prec, tune=True)
+        out["tune_s"] = time.perf_counter() - t_0
+        out["tune_report"] = tp.tune_report
+        tp.close()
     if "solve" in what:
         # solver iterations at a fixed step; A c stands in for the measurements
         plan.apply_A(c, y)

@@ -165,3 +165,29 @@ def test_calibration_library_is_separate():
     fn.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
     assert fn(None, 8, 8, None) == 1
     assert "psoam_calib_mfma_bf16" not in _declared()
+
+
+def test_tuned_creation_validates_before_device_work(lib):
+    from paper_2510_23739_amd import _lib
+    import numpy as np
+    out = C.c_void_p(1)
+    rep = _lib.TuneReport()
+    sp = _lib.Species()
+    for s in range(2):
+        sp.tau[s] = 2.0
+    assert lib.psoam_plan_create_tuned(None, C.byref(sp), None, None, None, 4, 1, None,
+                                       C.byref(out), C.byref(rep)) == _lib.EINVAL
+    assert out.value is None
+    phi = np.ones(4, np.float32)
+    t0 = np.zeros((4, 3, 3), np.int32)
+    taps = np.zeros((4, 3, 3, 4), np.float32)
+    args = lambda gg, prec=1, o=C.byref(out): (
+        C.byref(gg), C.byref(sp), phi.ctypes.data_as(C.c_void_p),
+        t0.ctypes.data_as(C.c_void_p), taps.ctypes.data_as(C.c_void_p), 4, prec, None, o,
+        C.byref(rep))
+    g = _lib.Geom(4, 4, 4, 2, 3, 8, 3, 0)
+    assert lib.psoam_plan_create_tuned(*args(g, o=None)) == _lib.EINVAL
+    assert b"out is NULL" in lib.psoam_last_error()
+    assert lib.psoam_plan_create_tuned(*args(_lib.Geom(4, 4, 4, 2, 3, 8, 2, 0))) == _lib.EINVAL
+    assert b"odd" in lib.psoam_last_error()
+    assert lib.psoam_plan_create_tuned(*args(g, prec=7)) == _lib.EUNSUPPORTED
