@@ -1192,13 +1192,14 @@ __device__ __forceinline__ float gradT_at(const float* __restrict__ uc, const fl
 // plane that component's difference needs; w is formed on the tile plus the
 // forward halo; the new duals are written for the tile.  Global traffic is
 // about u_j, u_{j-1} (3 components each), z in and u_{j+1} out per voxel.
-constexpr int kTvY = 4, kTvX = 8, kTvZ = 32;
+constexpr int kTvY = 8, kTvX = 8, kTvZ = 32;
+constexpr int kTvThreads = 512;  // 8 waves per 2048-voxel tile
 template <int Y, int X, int Z>
 struct Dims3 {
   static constexpr int y = Y, x = X, z = Z;
 };
 
-__global__ __launch_bounds__(256) void tv_step_kernel(float* __restrict__ un,
+__global__ __launch_bounds__(kTvThreads) void tv_step_kernel(float* __restrict__ un,
                                                       const float* __restrict__ zin,
                                                       const float* __restrict__ uc,
                                                       const float* __restrict__ up, float beta,
@@ -1228,13 +1229,13 @@ __global__ __launch_bounds__(256) void tv_step_kernel(float* __restrict__ un,
   auto stage = [&](float* dst, int d, auto dims, int gy0, int gx0, int gz0) {
     constexpr int NY_ = decltype(dims)::y, NX_ = decltype(dims)::x, NZ_ = decltype(dims)::z;
     constexpr int CNT = NY_ * NX_ * NZ_;
-    constexpr int IT = (CNT + 255) / 256;
+    constexpr int IT = (CNT + kTvThreads - 1) / kTvThreads;
     const float* c = uc ? uc + d * G.sv : nullptr;
     const float* pr = up ? up + d * G.sv : nullptr;
     float a[IT], b[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const int i = tid + it * 256;
+      const int i = tid + it * kTvThreads;
       const int lz = i % NZ_, r = i / NZ_;
       const int lx = r % NX_, ly = r / NX_;
       const int gy = gy0 + ly, gx = gx0 + lx, gz = gz0 + lz;
@@ -1248,7 +1249,7 @@ __global__ __launch_bounds__(256) void tv_step_kernel(float* __restrict__ un,
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const int i = tid + it * 256;
+      const int i = tid + it * kTvThreads;
       if (i < CNT) dst[i] = pr ? a[it] + beta * (a[it] - b[it]) : a[it];
     }
   };
@@ -1257,11 +1258,11 @@ __global__ __launch_bounds__(256) void tv_step_kernel(float* __restrict__ un,
   stage(s_ez, 2, Dims3<EY, EX, EZ + 1>{}, y0, x0, z0 - 1);
   __syncthreads();
   // w on the tile and its forward halo (the z loads first, then the sums)
-  constexpr int WIT = (EY * EX * EZ + 255) / 256;
+  constexpr int WIT = (EY * EX * EZ + kTvThreads - 1) / kTvThreads;
   float zv[WIT];
 #pragma unroll
   for (int it = 0; it < WIT; ++it) {
-    const int i = tid + it * 256;
+    const int i = tid + it * kTvThreads;
     const int lz = i % EZ, r = i / EZ;
     const int lx = r % EX, ly = r / EX;
     const int gy = y0 + ly, gx = x0 + lx, gz = z0 + lz;
@@ -1271,7 +1272,7 @@ __global__ __launch_bounds__(256) void tv_step_kernel(float* __restrict__ un,
   }
 #pragma unroll
   for (int it = 0; it < WIT; ++it) {
-    const int i = tid + it * 256;
+    const int i = tid + it * kTvThreads;
     if (i >= EY * EX * EZ) break;
     const int lz = i % EZ, r = i / EZ;
     const int lx = r % EX, ly = r / EX;
@@ -1291,7 +1292,7 @@ __global__ __launch_bounds__(256) void tv_step_kernel(float* __restrict__ un,
   }
   __syncthreads();
   // new duals on the tile
-  for (int i = tid; i < kTvY * kTvX * kTvZ; i += 256) {
+  for (int i = tid; i < kTvY * kTvX * kTvZ; i += kTvThreads) {
     const int lz = i % kTvZ, r = i / kTvZ;
     const int lx = r % kTvX, ly = r / kTvX;
     const int gy = y0 + ly, gx = x0 + lx, gz = z0 + lz;
@@ -1342,7 +1343,7 @@ hipError_t launch_tv_step(const psoam_plan* P, float* u_next, const float* z, co
   const size_t nb = (size_t)P->g.n_species * ((G.ny + kTvY - 1) / kTvY) *
                     ((G.nx + kTvX - 1) / kTvX) * ((G.nz + kTvZ - 1) / kTvZ);
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(tv_step_kernel, dim3((unsigned)nb), dim3(256), 0, s, u_next, z, u_cur,
+  hipLaunchKernelGGL(tv_step_kernel, dim3((unsigned)nb), dim3(kTvThreads), 0, s, u_next, z, u_cur,
                      u_prev, beta, inv_mu, theta, G);
   return hipGetLastError();
 }
