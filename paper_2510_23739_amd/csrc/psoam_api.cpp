@@ -540,23 +540,21 @@ int enqueue_iteration(BatchItem& it, hipStream_t s) {
 struct BatchStreams {
   std::vector<hipStream_t> ss;
   std::vector<hipEvent_t> ev;
-  hipStream_t cs = nullptr;
   hipEvent_t e_main = nullptr;
   ~BatchStreams() {
     for (hipStream_t x : ss)
       if (x) (void)hipStreamDestroy(x);
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
-    if (cs) (void)hipStreamDestroy(cs);
     if (e_main) (void)hipEventDestroy(e_main);
   }
 };
 
 // Problems on their own streams (default priority): the power iterations run
-// concurrently; then pairs of outer iterations of every active problem are
-// captured into one graph (one branch per problem) and replayed — a pair
-// brings the c_k / c_{k+1} buffers back to their roles, so one graph serves
-// every replay; a final odd iteration runs eagerly.
+// concurrently; then each problem's pair of outer iterations is captured into
+// a graph on its stream and replayed there — a pair brings the c_k / c_{k+1}
+// buffers back to their roles, so one graph serves every replay; a final odd
+// iteration runs eagerly.
 int solve_batch_graph(std::vector<BatchItem>& items, hipStream_t caller) {
   const int n = (int)items.size();
   BatchStreams bs;
@@ -566,7 +564,6 @@ int solve_batch_graph(std::vector<BatchItem>& items, hipStream_t caller) {
     PSOAM_HIP(hipStreamCreateWithFlags(&bs.ss[i], hipStreamNonBlocking));
     PSOAM_HIP(hipEventCreateWithFlags(&bs.ev[i], hipEventDisableTiming));
   }
-  PSOAM_HIP(hipStreamCreateWithFlags(&bs.cs, hipStreamNonBlocking));
   PSOAM_HIP(hipEventCreateWithFlags(&bs.e_main, hipEventDisableTiming));
   PSOAM_HIP(hipEventRecord(bs.e_main, caller));
   for (int i = 0; i < n; ++i) PSOAM_HIP(hipStreamWaitEvent(bs.ss[i], bs.e_main, 0));
@@ -588,51 +585,38 @@ int solve_batch_graph(std::vector<BatchItem>& items, hipStream_t caller) {
     PSOAM_HIP(launch_set_double(it.P->d_scalars + 8, 1.0, bs.ss[i]));
     if (int rc = prepare_p(it.P, kOpA, it.p, bs.ss[i])) return rc;
     it.remaining = it.o->k1;
-    PSOAM_HIP(hipEventRecord(bs.ev[i], bs.ss[i]));
-    PSOAM_HIP(hipStreamWaitEvent(bs.cs, bs.ev[i], 0));
   }
-  // phase 2: captured pairs of iterations
-  for (;;) {
-    int r = 1 << 30;
-    for (const BatchItem& it : items)
-      if (it.remaining >= 2) r = std::min(r, it.remaining / 2);
-    if (r == (1 << 30)) break;
+  // phase 2: each problem's pairs of iterations captured into a graph of its
+  // own and replayed on its own stream, so the problems' kernels can overlap
+  // (one's HBM-bound TV steps beside another's matrix-core contractions)
+  for (int i = 0; i < n; ++i) {
+    BatchItem& it = items[i];
+    const int pairs = it.remaining / 2;
+    if (pairs == 0) continue;
     hipGraph_t graph = nullptr;
-    PSOAM_HIP(hipStreamBeginCapture(bs.cs, hipStreamCaptureModeRelaxed));
-    int rc = PSOAM_OK;
-    hipError_t he = hipEventRecord(bs.e_main, bs.cs);
-    for (int i = 0; i < n && rc == PSOAM_OK && he == hipSuccess; ++i) {
-      BatchItem& it = items[i];
-      if (it.remaining < 2) continue;
-      he = hipStreamWaitEvent(bs.ss[i], bs.e_main, 0);
-      if (he == hipSuccess) rc = enqueue_iteration(it, bs.ss[i]);
-      if (rc == PSOAM_OK && he == hipSuccess) rc = enqueue_iteration(it, bs.ss[i]);
-      if (rc == PSOAM_OK && he == hipSuccess) he = hipEventRecord(bs.ev[i], bs.ss[i]);
-      if (rc == PSOAM_OK && he == hipSuccess) he = hipStreamWaitEvent(bs.cs, bs.ev[i], 0);
-    }
-    const hipError_t he_end = hipStreamEndCapture(bs.cs, &graph);
-    if (rc != PSOAM_OK || he != hipSuccess || he_end != hipSuccess) {
+    PSOAM_HIP(hipStreamBeginCapture(bs.ss[i], hipStreamCaptureModeRelaxed));
+    int rc = enqueue_iteration(it, bs.ss[i]);
+    if (rc == PSOAM_OK) rc = enqueue_iteration(it, bs.ss[i]);
+    const hipError_t he_end = hipStreamEndCapture(bs.ss[i], &graph);
+    if (rc != PSOAM_OK || he_end != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
       if (rc != PSOAM_OK) return rc;
-      return fail(PSOAM_EHIP, std::string("solve_batch: graph capture: ") +
-                                  hipGetErrorString(he != hipSuccess ? he : he_end));
+      return fail(PSOAM_EHIP, std::string("solve_batch: graph capture: ") + hipGetErrorString(he_end));
     }
     hipGraphExec_t exec = nullptr;
     const hipError_t hi = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (hi != hipSuccess) return fail(PSOAM_EHIP, std::string("solve_batch: graph instantiate: ") + hipGetErrorString(hi));
     hipError_t hl = hipSuccess;
-    for (int k = 0; k < r && hl == hipSuccess; ++k) hl = hipGraphLaunch(exec, bs.cs);
+    for (int k = 0; k < pairs && hl == hipSuccess; ++k) hl = hipGraphLaunch(exec, bs.ss[i]);
+    // the executable graph may be destroyed once its launches are enqueued
     (void)hipGraphExecDestroy(exec);
     if (hl != hipSuccess) return fail(PSOAM_EHIP, std::string("solve_batch: graph launch: ") + hipGetErrorString(hl));
-    for (BatchItem& it : items)
-      if (it.remaining >= 2) it.remaining -= 2 * r;
+    it.remaining -= 2 * pairs;
   }
   // odd last iterations, results, join the caller's stream
-  PSOAM_HIP(hipEventRecord(bs.e_main, bs.cs));
   for (int i = 0; i < n; ++i) {
     BatchItem& it = items[i];
-    PSOAM_HIP(hipStreamWaitEvent(bs.ss[i], bs.e_main, 0));
     if (it.remaining == 1)
       if (int rc = enqueue_iteration(it, bs.ss[i])) return rc;
     it.stats.iterations = it.o->k1;
