@@ -89,6 +89,7 @@ class Plan:
         method): its "concentrations" are the pulse volumes b [K][Ny][Nx][Nz]."""
         self = cls.__new__(cls)
         self._h = None
+        self.tune_report = None
         self.geom = _lib.Geom(nx, ny, nz, n_pulses, n_pulses, nt, f, 0, 0)
         self._t0 = np.ascontiguousarray(t0, dtype=np.int32)
         self._taps = np.ascontiguousarray(taps, dtype=np.float32)
@@ -117,6 +118,7 @@ class Plan:
         psoam_plan_create_factorised)."""
         self = cls.__new__(cls)
         self._h = None
+        self.tune_report = None
         species_a, species_b, species_tau = list(species.a), list(species.b), list(species.tau)
         ns = len(species_a)
         phi = np.ascontiguousarray(phi, dtype=np.float32)
