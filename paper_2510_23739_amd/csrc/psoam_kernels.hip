@@ -835,16 +835,22 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
           for (int i = 0; i < kRunMax; ++i) {
             if (i < m) {
               if (i > 0) R[(kLdsPos - i) & (kLdsPos - 1)] = *(const V*)(sh + base - i * 128);
+              // position 0 takes the column just read from LDS, so it goes
+              // last: the other fifteen products cover the read's latency
               if (SPLIT && pass == 0) {
 #pragma unroll
-                for (int p = 0; p < kLdsPos; ++p) {
+                for (int q = 1; q <= kLdsPos; ++q) {
+                  const int p = q & (kLdsPos - 1);
                   const int w = (p - i) & (kLdsPos - 1);
                   acc[p] = H::mma(ab[i], R[w], acc[p]);
                   acc[p] = H::mma(al[i], R[w], acc[p]);
                 }
               } else {
 #pragma unroll
-                for (int p = 0; p < kLdsPos; ++p) acc[p] = H::mma(ab[i], R[(p - i) & (kLdsPos - 1)], acc[p]);
+                for (int q = 1; q <= kLdsPos; ++q) {
+                  const int p = q & (kLdsPos - 1);
+                  acc[p] = H::mma(ab[i], R[(p - i) & (kLdsPos - 1)], acc[p]);
+                }
               }
             }
             // slot i is free: load the next run's block i into it
