@@ -82,7 +82,7 @@ typedef struct {
                               up to rounding.  0: general form. */
 } psoam_geom;
 
-/* Photo-physics of the species (Sec. 2.1.1, eqs. epsilon, final-H):
+/* Photo-physics of the species (Sec. 2.1.2, eqs. epsilon, final-H):
  *   S_v[k][s] = phi_v * (a[s] + b[s] * exp(-k * phi_v^gamma / tau[s]))
  * a = OFF-state extinction, b = ON minus OFF extinction, tau = switching
  * time constant in pulses; gamma = 1 is the fluence-dependent rate of the
@@ -100,7 +100,7 @@ typedef struct psoam_plan psoam_plan;
  * into matrix-core tiles for both H and its adjoint, and allocates the
  * padded operand buffers (zeroed borders) the kernels read.
  *
- * The acoustic operator of one pulse (Sec. 2.1.3, eqs. q-above-1d,
+ * The acoustic operator of one pulse (Sec. 2.1.4, eqs. q-above-1d,
  * q-below-1d, acoustic-temporal-conv; discretised in Sec. 2.2.3):
  *   y[k][iy][ix][t] = sum_{jdy,jdx in [0,F)} sum_z h[z][jdy][jdx][t] *
  *                     b[k][iy+jdy-R][ix+jdx-R][z],   b = S c,

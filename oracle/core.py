@@ -71,19 +71,21 @@ def _s_at(S: np.ndarray, ny: int, nx: int) -> str:
 
 
 def apply_S(c: np.ndarray, S: np.ndarray) -> np.ndarray:
-    """b[k][v] = sum_s S_v[k][s] c[s][v]   (block-diagonal S, one block per voxel)."""
+    """b[k][v] = sum_s S_v[k][s] c[s][v]   (block-diagonal S, one block per voxel).
+    Returned C-contiguous (einsum leaves the pulse axis fastest, which sends
+    every later matrix product down numpy's strided path)."""
     sub = _s_at(S, c.shape[1], c.shape[2])
-    return np.einsum(f"{sub},syxz->kyxz", S, np.asarray(c, dtype=np.float64))
+    return np.ascontiguousarray(np.einsum(f"{sub},syxz->kyxz", S, np.asarray(c, dtype=np.float64)))
 
 
 def apply_ST(bh: np.ndarray, S: np.ndarray) -> np.ndarray:
-    """Transpose of apply_S: c[s][v] = sum_k S_v[k][s] bh[k][v]."""
+    """Transpose of apply_S: c[s][v] = sum_k S_v[k][s] bh[k][v] (C-contiguous)."""
     sub = _s_at(S, bh.shape[1], bh.shape[2])
-    return np.einsum(f"{sub},kyxz->syxz", S, np.asarray(bh, dtype=np.float64))
+    return np.ascontiguousarray(np.einsum(f"{sub},kyxz->syxz", S, np.asarray(bh, dtype=np.float64)))
 
 
 # ----------------------------------------------------------------------------
-# acoustic operator H  (Sec. 2.1.3 eqs. q-above-1d, q-below-1d,
+# acoustic operator H  (Sec. 2.1.4 eqs. q-above-1d, q-below-1d,
 # acoustic-temporal-conv; Sec. 2.2.3 eqs. acoustic-discrete-single,
 # acoustic-full-forward)
 # ----------------------------------------------------------------------------

@@ -285,8 +285,16 @@ def two_step(acoustic: Plan, species: Plan, p, nu1: float, nu2: float, nu3: floa
 
 
 def solve_batch(plans: Sequence[Plan], ps, cs, opts: Sequence[dict], stream=None):
-    """Run psoam_solve_batch over several plans; returns a list of stats dicts."""
+    """Run psoam_solve_batch over several plans; returns a list of stats dicts.
+    ps[i] and cs[i] must be contiguous float32 device tensors of plans[i]'s
+    measurement and concentration shapes (checked here, before any call)."""
     n = len(plans)
+    if not (len(ps) == n and len(cs) == n and len(opts) == n):
+        raise ValueError(f"solve_batch: {n} plans but {len(ps)} measurements, {len(cs)} "
+                         f"concentration tensors and {len(opts)} option sets")
+    for i in range(n):
+        _check_f32(ps[i], plans[i].y_shape, f"p[{i}]")
+        _check_f32(cs[i], plans[i].c_shape, f"c[{i}]")
     hs = (C.c_void_p * n)(*[pl.handle.value for pl in plans])
     pp = (C.c_void_p * n)(*[p.data_ptr() for p in ps])
     cc = (C.c_void_p * n)(*[c.data_ptr() for c in cs])
@@ -304,9 +312,13 @@ def solve_batch(plans: Sequence[Plan], ps, cs, opts: Sequence[dict], stream=None
 
 
 def prox_l1(z, thresh: float, nonneg: bool = True, x=None, stream=None):
+    """x = soft threshold of z (max(z - thresh, 0) when nonneg); z and x are
+    contiguous float32 device tensors of one shape (x may be z)."""
     torch = _torch()
+    _check_f32(z, tuple(z.shape), "z")
     if x is None:
         x = torch.empty_like(z)
+    _check_f32(x, tuple(z.shape), "x")
     check(load().psoam_prox_l1(_ptr(x), _ptr(z), int(z.numel()), float(thresh),
                                1 if nonneg else 0, _stream(stream)))
     return x

@@ -2,7 +2,7 @@
 //
 //  switch_fwd*  b = S c           photo-switching matrix per voxel (eq. Sij-detailed)
 //  band16/32    y = H b, r = H b - p, or c = S^T H^T r
-//               (acoustic operator, Sec. 2.1.3 / 2.2.3; block-diagonal over
+//               (acoustic operator, Sec. 2.1.4 / 2.2.3; block-diagonal over
 //               pulses as W_tot, eq. acoustic-full-forward)
 //  pack_r*      y -> padded operand of H^T
 //  tv_*         one step of the dual iteration of the TV prox (Alg. alg:prox-inner)

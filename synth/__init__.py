@@ -12,7 +12,7 @@ returns, and neither side imports the other.
 Paper context (arXiv 2510.23739):
   * the acoustic model integrates the initial pressure over a semicircle
     around the focal spot weighted by the transducer's spatial response, then
-    convolves with the electrical impulse response (Sec. 2.1.3, eqs.
+    convolves with the electrical impulse response (Sec. 2.1.4, eqs.
     q-above-1d, q-below-1d, acoustic-temporal-conv).  Here that response is
     synthesised per voxel offset as  w(dx,dy,z) * g'(t*dt - tau(dx,dy,z)),
     a Gaussian beam times a derivative-of-Gaussian pulse at the signed
@@ -20,7 +20,7 @@ Paper context (arXiv 2510.23739):
   * photo-physics constants follow Table "tab:photophysics" (extinction
     coefficients of species A and B, in 1/(uM mm));
   * the fluence map is the depth profile exp(-mu_eff z) standing in for the
-    diffusion solve of Sec. 2.1.2 (precomputed once, as in the paper).
+    diffusion solve of Sec. 2.1.3 (precomputed once, as in the paper).
 """
 from __future__ import annotations
 

@@ -191,3 +191,26 @@ def test_tuned_creation_validates_before_device_work(lib):
     assert lib.psoam_plan_create_tuned(*args(_lib.Geom(4, 4, 4, 2, 3, 8, 2, 0))) == _lib.EINVAL
     assert b"odd" in lib.psoam_last_error()
     assert lib.psoam_plan_create_tuned(*args(g, prec=7)) == _lib.EUNSUPPORTED
+
+
+def test_binding_checks_batch_and_l1_arguments():
+    """solve_batch and prox_l1 check every tensor's shape, dtype, device and
+    layout (and the batch's list lengths) before anything reaches the library."""
+    import types
+
+    import torch
+
+    import paper_2510_23739_amd as pk
+    plan = types.SimpleNamespace(y_shape=(2, 3, 3, 8), c_shape=(1, 3, 3, 4))
+    p = torch.zeros(plan.y_shape)
+    c = torch.zeros(plan.c_shape)
+    with pytest.raises(ValueError, match="plans but"):
+        pk.solve_batch([plan, plan], [p], [c, c], [{}, {}])
+    with pytest.raises(ValueError, match="plans but"):
+        pk.solve_batch([plan], [p], [c], [{}, {}])
+    with pytest.raises(ValueError, match="CUDA"):     # host tensors
+        pk.solve_batch([plan], [p], [c], [{}])
+    with pytest.raises(ValueError, match="CUDA"):
+        pk.prox_l1(torch.zeros(8), 0.1)
+    with pytest.raises(ValueError, match="CUDA"):     # float64
+        pk.prox_l1(torch.zeros(8, dtype=torch.float64), 0.1)
