@@ -18,7 +18,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_common import nan_buf, oracle_S, say, torch_cuda
+from gpu_common import TOL_OP, nan_buf, oracle_S, say, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -28,8 +28,6 @@ PRECS = ["fp32", "bf16", "fp16", "bf16_split", "fp16_split", "bf16_refined"]
 # the same format, ~16 bits); FP32 multiplies by 1 and adds zeros exactly
 UNIT = {"fp32": 1e-7, "bf16": 2.0 ** -8, "fp16": 2.0 ** -11, "bf16_split": 2.0 ** -16,
         "fp16_split": 2.0 ** -16, "bf16_refined": 2.0 ** -8}
-TOL_OP = {"fp32": 1e-5, "bf16": 8e-3, "fp16": 1.5e-3, "bf16_split": 2e-5, "fp16_split": 2e-5,
-          "bf16_refined": 8e-3}
 
 
 def _plan(nx, ny, nz, k, nt, f, phi, sp, t0, taps, prec):
