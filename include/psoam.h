@@ -159,6 +159,21 @@ size_t psoam_prox_tv_ws_bytes(const psoam_plan* plan);
 int psoam_prox_tv(const psoam_plan* plan, float* x, const float* z, float theta,
                   int32_t n_inner, int32_t nonneg, void* ws, void* stream);
 
+/* psoam_prox_tv for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same dual iteration and result, bit for bit, with its three dual
+ * buffers in a static device array of the library instead of a workspace.
+ * Limit: S*Ny*Nx*Nz <= 3728256 species-voxels (the array holds 128 MiB on
+ * every GPU the library runs on, until the process ends); larger grids get
+ * EINVAL and use psoam_prox_tv.  The call allocates nothing; its first call
+ * on a device looks up the array's device address (hipGetSymbolAddress).
+ * The current device must be the plan's (EINVAL otherwise).  Every call on
+ * a GPU shares that GPU's array: calls that overlap in time on one GPU (two
+ * streams, two threads, two plans) race and must be ordered by the caller.
+ * Arguments and other errors as psoam_prox_tv. */
+int psoam_prox_tv_noalloc(const psoam_plan* plan, float* x, const float* z, float theta,
+                          int32_t n_inner, int32_t nonneg, void* stream);
+
 /* Bytes of workspace psoam_prox_r3 needs for this plan's grid and pulses. */
 size_t psoam_prox_r3_ws_bytes(const psoam_plan* plan);
 

@@ -214,6 +214,19 @@ class Plan:
                                    1 if nonneg else 0, _ptr(ws), _stream(stream)))
         return x
 
+    def prox_tv_noalloc(self, z, theta: float, n_inner: int, nonneg: bool = False, x=None,
+                        stream=None):
+        """prox_tv without a workspace (psoam_prox_tv_noalloc: the duals live in
+        the library's static device array).  Pass x to allocate nothing here."""
+        torch = _torch()
+        _check_f32(z, self.c_shape, "z")
+        if x is None:
+            x = torch.empty_like(z)
+        _check_f32(x, self.c_shape, "x")
+        check(load().psoam_prox_tv_noalloc(self.handle, _ptr(x), _ptr(z), float(theta),
+                                           int(n_inner), 1 if nonneg else 0, _stream(stream)))
+        return x
+
     def prox_r3(self, z, theta_tv: float, theta_tvs: float, theta_l1: float, n_inner: int,
                 x=None, ws=None, stream=None):
         """Prox of the full regulariser (TV of c, TV of S c, l1, x >= 0)."""

@@ -80,6 +80,8 @@ EXPORTS = {
                                 C.c_float, C.c_int32, C.c_void_p, C.c_void_p]),
     "psoam_prox_tv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_int32,
                                 C.c_int32, C.c_void_p, C.c_void_p]),
+    "psoam_prox_tv_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_int32,
+                                        C.c_int32, C.c_void_p]),
     "psoam_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts),
                               C.POINTER(SolveStats), C.c_void_p]),
     "psoam_solve_batch": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),

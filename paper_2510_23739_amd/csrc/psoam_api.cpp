@@ -642,6 +642,44 @@ int solve_batch_graph(std::vector<BatchItem>& items, hipStream_t caller) {
 }  // namespace
 }  // namespace psoam
 
+// ---- the TV prox without a workspace (for callers that cannot allocate) ----
+namespace psoam {
+namespace {
+// Dual buffers of psoam_prox_tv_noalloc: three sets of [3][S][Ny][Nx][Nz]
+// floats, each set 256-byte aligned.  Every GPU the library runs on holds
+// this array (128 MiB) until the process ends.  In host code its name is a
+// host-side stand-in: the device address comes from hipGetSymbolAddress,
+// taken once per device (noalloc_scratch) and used everywhere instead.
+constexpr size_t kNoAllocFloats = (size_t)32 << 20;
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+float* g_noalloc_ptr[kNoAllocDevices] = {};
+
+inline size_t noalloc_set_floats(size_t sv) { return (3 * sv + 63) / 64 * 64; }
+
+// device address of `scratch` on the current device (looked up on the
+// device's first call; hipGetSymbolAddress allocates nothing)
+int noalloc_scratch(int plan_device, float** out) {
+  int dev = -1;
+  PSOAM_HIP(hipGetDevice(&dev));
+  if (dev != plan_device)
+    return fail(PSOAM_EINVAL, "prox_tv_noalloc: the current device is not the plan's device");
+  if (dev < 0 || dev >= kNoAllocDevices)
+    return fail(PSOAM_EUNSUPPORTED, "prox_tv_noalloc: device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    PSOAM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(PSOAM_EHIP, "prox_tv_noalloc: no device address for the dual buffer");
+    g_noalloc_ptr[dev] = (float*)p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return PSOAM_OK;
+}
+}  // namespace
+}  // namespace psoam
+
 using namespace psoam;
 
 namespace psoam {
@@ -1043,6 +1081,28 @@ int psoam_band_only(const psoam_plan* plan, int32_t dir, float* out, void* strea
   if (plan->inner) plan = plan->inner;  // the contraction of the separable form (S columns)
   PSOAM_HIP(launch_band(plan, dir == 0 ? 0 : 2, out, nullptr, nullptr, S(stream)));
   return PSOAM_OK;
+}
+
+int psoam_prox_tv_noalloc(const psoam_plan* plan, float* x, const float* z, float theta,
+                          int32_t n_inner, int32_t nonneg, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!x || !z) return fail(PSOAM_EINVAL, "prox_tv_noalloc: NULL argument");
+  if (!(theta >= 0.0f) || !std::isfinite(theta))
+    return fail(PSOAM_EINVAL, "prox_tv_noalloc: theta must be finite and >= 0");
+  if (n_inner < 0) return fail(PSOAM_EINVAL, "prox_tv_noalloc: n_inner < 0");
+  const size_t sv = plan->c_elems();
+  const size_t set = noalloc_set_floats(sv);
+  if (3 * set > kNoAllocFloats)
+    return fail(PSOAM_EINVAL, "prox_tv_noalloc: S*Ny*Nx*Nz = " + std::to_string(sv) +
+                                  " exceeds the static dual buffer (at most 3728256 "
+                                  "species-voxels); use psoam_prox_tv with a workspace");
+  float* base = nullptr;
+  if (int rc = noalloc_scratch(plan->device, &base)) return rc;
+  float* u[3] = {base, base + set, base + 2 * set};
+  // the dual iteration writes every dual it reads (the first step starts from
+  // u = 0 without reading memory), so the buffer needs no clearing
+  return tv_prox_core(plan, x, z, theta, n_inner, nonneg ? 1 : 0, 0.0f, u, nullptr, nullptr,
+                      false, nullptr, S(stream));
 }
 
 const char* psoam_last_error(void) { return last_error_cstr(); }
