@@ -45,6 +45,15 @@ enum {
  * float32 matrix cores; BF16/FP16 round both operands to 16 bits and
  * accumulate in float32; the _SPLIT forms add the low-order parts of both
  * operands (three products per tile) for about 16 significant bits.
+ * FP16 operands are written times a power of two chosen on the device for
+ * every operand, from an FP32 max-abs reduction of what is converted (the
+ * switched concentrations, the A-scans of an adjoint) or from a bound that
+ * holds for every element (the solver's residual: max over t of the sum of
+ * |h| times the largest switched value, plus max |p|), so that the largest
+ * value lands at or below 2^14: inputs in any units neither overflow FP16
+ * nor lose precision to its subnormal range (values down to 2^-28 of the
+ * largest keep 11 significant bits).  Inputs with an infinite element give
+ * non-finite results, as in FP32.
  * BF16 rounds the impulse-response table with error feedback along dy (for
  * each dx, sample and depth, the rounding error of an entry is added to the
  * next entry inside the band before it is rounded), so that the table's

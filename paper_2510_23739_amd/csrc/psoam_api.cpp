@@ -259,7 +259,10 @@ int copy_scalars(const psoam_plan* P, double* host, int n, hipStream_t s) {
 enum Op { kOpA = 0, kOpUnmix = 1 };
 
 int prepare_p(psoam_plan* P, int op, const float* p, hipStream_t s) {
-  if (op != kOpA || !P->inner) return PSOAM_OK;
+  if (op != kOpA) return PSOAM_OK;
+  // FP16 residual operand: its bound takes max |p| of this solve
+  PSOAM_HIP(launch_f16_pmax(P, p, s));
+  if (!P->inner) return PSOAM_OK;
   PSOAM_HIP(launch_sep_contract(P, P->d_q, p, s));
   PSOAM_HIP(launch_dot(p, p, (int64_t)P->y_elems(), P->d_partial, P->d_scalars + 9, s));
   return PSOAM_OK;
@@ -346,6 +349,8 @@ int enqueue_power(psoam_plan* P, int op, SolveBufs& B, const psoam_solve_opts* o
   const int64_t sv = (int64_t)P->c_elems();
   float* v = B.zb;
   float* w = B.g;
+  // the power iteration's residual form of H has no measurements (max |p| = 0)
+  if (op == kOpA) PSOAM_HIP(launch_f16_pmax(P, nullptr, s));
   if (o->v0) {
     PSOAM_HIP(hipMemcpyAsync(w, o->v0, sizeof(float) * sv, hipMemcpyDeviceToDevice, s));
   } else {

@@ -28,7 +28,7 @@ constexpr int kWaveLanes = 64;
 constexpr int kPosPerWave = 8;       // scan/voxel positions owned by one wave
 constexpr int kPadX = 16;            // Nx is padded up to a multiple of this
 constexpr int kWavesPerBlock = 4;    // consecutive output tiles of one position block
-constexpr float kFp16Scale = 256.0f; // FP16 operands carry this power-of-two scale
+constexpr float kFp16Scale = 256.0f; // FP16 operand scale when no per-call scale is given
 constexpr int kLdsPos = 16;          // staged kernel: positions per wave
 constexpr int kLdsMaxBytes = 160 * 1024;
 constexpr int kRunMax = 4;           // longest sliding run (chunks) of the staged kernel
@@ -146,6 +146,17 @@ struct psoam_plan {
   int fact = 0;
   psoam::EirParams eir{};
   float* d_fq = nullptr;      // [K][Ny][Nx][Nt]: shell sums q = Lambda S c (and V^T r)
+  // FP16 operands (FP16 plans with operands, else null): power-of-two scales
+  // chosen on the device for every operand written, from FP32 max-abs
+  // reductions and bounds that hold for every element, so no operand
+  // overflows FP16 whatever the units of c and p:
+  //   [0] s_b, [1] 1/s_b (H operand), [2] s_r, [3] 1/s_r (H^T operand),
+  //   [4] max |x| of the last switching input, [5] max |p| of the solve
+  float* d_f16 = nullptr;
+  unsigned* d_f16acc = nullptr;  // [2] float bits of running maxima, zero between uses
+  double srow = 0.0;  // max over voxels and pulses of sum_s |S_v[k][s]|
+  double hrow = 0.0;  // max over output samples of the sum of |h| over (z, dy, dx)
+  double eir_l1 = 0.0;  // sum_j |v[j]| (factorised form)
   size_t h_elems() const { return (size_t)g.n_species * g.ny * g.nx * g.nt; }
   size_t y_elems() const { return (size_t)g.n_pulses * g.ny * g.nx * g.nt; }
   size_t c_elems() const { return (size_t)g.n_species * g.ny * g.nx * g.nz; }
@@ -216,6 +227,11 @@ size_t reduce_blocks(int64_t n);
 hipError_t launch_momentum_dev(float* xi, const float* c_next, const float* c_prev, double* tst,
                                int literal, int64_t n, hipStream_t s);
 hipError_t launch_set_double(double* p, double v, hipStream_t s);
+// FP16 operand scales (no-ops for other plans).  launch_f16_pmax records
+// max |p| of a solve's measurements (p null: 0) for the residual operand's
+// bound; the switching and pack launchers and the residual form of H set
+// their own scales.
+hipError_t launch_f16_pmax(const psoam_plan* P, const float* p, hipStream_t s);
 // full regulariser with the TV(S c) term (stacked dual iteration):
 //   w = z - (grad^T eta1 + S^T grad^T eta2 + eta3)   [clamp_out: max(., 0)]
 //   u1' = clip(eta1 + step0 grad w), u2' = clip(eta2 + step1 grad S w),

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void switch_fwd16(const float* __restrict__ c,
                                                     const float* __restrict__ phi,
                                                     const float* __restrict__ stab,
                                                     const float* __restrict__ stab_o, int vec,
-                                                    SwitchParams sw,
+                                                    const float* __restrict__ f16, SwitchParams sw,
                                                     typename Half<PREC>::E* __restrict__ bq,
                                                     typename Half<PREC>::E* __restrict__ bq_lo,
                                                     int ny, int nx, int nz, int zo_n, int kp,
@@ -155,10 +155,12 @@ __global__ __launch_bounds__(256) void switch_fwd16(const float* __restrict__ c,
       }
     }
   }
+  // operand scale: the per-call power of two of FP16 plans (1 for BF16)
+  const float sc = f16 ? f16[0] : H::scale;
   typename H::V hi, lo;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const float v = b[j] * H::scale;
+    const float v = b[j] * sc;
     hi[j] = (typename H::E)v;
     lo[j] = (typename H::E)(v - (float)hi[j]);
   }
@@ -205,9 +207,10 @@ __global__ __launch_bounds__(256) void pack_r16(const float* __restrict__ yin,
                                                 typename Half<PREC>::E* __restrict__ rq_lo,
                                                 int nk, int ny, int nx, int nt, int to_n,
                                                 int kp, int xp, int r, size_t ps, int vec4,
-                                                int tsh) {
+                                                int tsh, const float* __restrict__ f16) {
   using H = Half<PREC>;
   using V = typename H::V;
+  const float sc = f16 ? f16[2] : H::scale;   // operand scale (FP16: per call)
   __shared__ V t_hi[256];
   __shared__ V t_lo[SPLIT ? 256 : 1];
   const int pos = blockIdx.x;
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(256) void pack_r16(const float* __restrict__ yin,
           }
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            const float w = v[j] * H::scale;
+            const float w = v[j] * sc;
             hi[j] = (typename H::E)w;
             lo[j] = (typename H::E)(w - (float)hi[j]);
           }
@@ -306,6 +309,7 @@ struct BandArgs {
   size_t ps;
   int nk, kp;
   float inv_scale;
+  const float* f16;  // FP16 plans: per-call operand scales (s_b, 1/s_b, s_r, 1/s_r), else null
   // epilogue
   float* out;
   const float* pmeas;
@@ -376,6 +380,9 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
   const int g = lane >> 4, n = lane & 15;
   const int row0 = mtile * 16 + 4 * g;
   const int k = kbase + n;
+  // undoing the operand's scale: 1/s_b after H, 1/s_r after H^T (FP16 plans
+  // take both from the device, chosen per call; the others use inv_scale)
+  const float ib = A.f16 ? A.f16[MODE == 2 ? 3 : 1] : A.inv_scale;
   if constexpr (MODE == 0) {
     const int nt = A.nt;
     if (k >= A.nk) return;
@@ -384,7 +391,7 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
       const int ix = ix0 + p;
       if (ix >= A.nx) continue;
       float* yo = A.out + (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
-      const f32x4 v = acc[p] * A.inv_scale;
+      const f32x4 v = acc[p] * ib;
       if ((nt & 3) == 0 && row0 + 3 < nt) {
         *(f32x4*)yo = v;
       } else {
@@ -428,7 +435,7 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const bool ok = row0 + j < nt;
-        float v = acc[p][j] * A.inv_scale;
+        float v = acc[p][j] * ib;
         if (A.pmeas && ok) v -= kPre ? pv[kPre ? p : 0][j] : A.pmeas[yi + j];
         rv[j] = ok ? v : 0.0f;
         ss += (double)rv[j] * (double)rv[j];
@@ -440,9 +447,10 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
       } else {
         using H = Half<RQ_PREC>;
         typename H::V4 hi, lo;
+        const float rqs = A.f16 ? A.f16[2] : A.rq_scale;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const float v = rv[j] * A.rq_scale;
+          const float v = rv[j] * rqs;
           hi[j] = (typename H::E)v;
           lo[j] = (typename H::E)(v - (float)hi[j]);
         }
@@ -475,7 +483,7 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int z = row0 + j;
-          if (z < nz) co[j] = coef_at(A.sw, A.phi, A.stab, A.kp, col, z, k, k) * (acc[p][j] * A.inv_scale);
+          if (z < nz) co[j] = coef_at(A.sw, A.phi, A.stab, A.kp, col, z, k, k) * (acc[p][j] * ib);
         }
       }
       return;
@@ -492,7 +500,7 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int z = row0 + j;
-          cz[j] = (kok && z < nz) ? A.stab[((size_t)z * A.kp + k) * A.sw.ns + s] * A.inv_scale : 0.0f;
+          cz[j] = (kok && z < nz) ? A.stab[((size_t)z * A.kp + k) * A.sw.ns + s] * ib : 0.0f;
         }
 #pragma unroll
         for (int p = 0; p < NP; ++p)
@@ -507,7 +515,7 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int z = row0 + j;
-            x[p][j] = (kok && z < nz) ? scoef(A.sw, A.phi[col + z], k, s) * (acc[p][j] * A.inv_scale) : 0.0f;
+            x[p][j] = (kok && z < nz) ? scoef(A.sw, A.phi[col + z], k, s) * (acc[p][j] * ib) : 0.0f;
           }
         }
       }
@@ -890,6 +898,92 @@ __global__ __launch_bounds__(64 * ROWS) __attribute__((amdgpu_waves_per_eu(SPLIT
 }
 
 // --------------------------------------------------------------------------
+// FP16 operand scales.  Every FP16 operand is written times a power of two
+// chosen on the device right before, from an FP32 max-abs reduction of what
+// is converted (or a bound that holds for every element of it), so that the
+// largest value lands at or below 2^14: nothing overflows FP16's 65504 and
+// the precision of every value down to 2^-28 of the largest is the format's.
+// A power-of-two scale is exact, so results do not depend on it except where
+// a fixed scale would have overflowed or left the normal range.
+// --------------------------------------------------------------------------
+
+// running max |x| into acc (float bits: nonnegative floats order as unsigned
+// integers); NaN inputs are skipped, an infinite one gives scale 1
+__global__ __launch_bounds__(256) void f16_amax_kernel(const float* __restrict__ x, int64_t n,
+                                                       unsigned* acc) {
+  __shared__ float sm[4];
+  float m = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    m = fmaxf(m, fabsf(x[i]));
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(sm[0], sm[1]), fmaxf(sm[2], sm[3]));
+    atomicMax(acc, __float_as_uint(m));
+  }
+}
+
+// one thread: mode 0 sets s_b from acc[0] * c1 (and keeps the max as st[4]);
+// mode 1 sets s_r from acc[1] * c1; mode 2 keeps acc[1] as max |p| (st[5]);
+// mode 3 sets s_r from the bound c1 st[4] + c2 st[5].  The accumulator read
+// is cleared for its next use.
+__global__ void f16_scale_kernel(float* st, unsigned* acc, int mode, float c1, float c2) {
+  auto pow2 = [](float bound) {
+    if (!(bound > 0.0f) || !isfinite(bound)) return 1.0f;
+    int e = 14 - (int)ceilf(log2f(bound));
+    e = e < -100 ? -100 : (e > 100 ? 100 : e);
+    return ldexpf(1.0f, e);
+  };
+  float sc = 1.0f;
+  int slot = 2;
+  if (mode == 0) {
+    const float a = __uint_as_float(acc[0]);
+    acc[0] = 0u;
+    st[4] = a;
+    sc = pow2(a * c1);
+    slot = 0;
+  } else if (mode == 1) {
+    const float a = __uint_as_float(acc[1]);
+    acc[1] = 0u;
+    sc = pow2(a * c1);
+  } else if (mode == 2) {
+    st[5] = __uint_as_float(acc[1]);
+    acc[1] = 0u;
+    return;
+  } else {
+    sc = pow2(c1 * st[4] + c2 * st[5]);
+  }
+  st[slot] = sc;
+  st[slot + 1] = 1.0f / sc;
+}
+
+static hipError_t f16_amax(const psoam_plan* P, const float* x, int64_t n, int slot,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t want = (n + 255) / 256;
+  const unsigned nb = (unsigned)std::min<int64_t>(want, 2048);
+  hipLaunchKernelGGL(f16_amax_kernel, dim3(nb), dim3(256), 0, s, x, n, P->d_f16acc + slot);
+  return hipGetLastError();
+}
+
+static hipError_t f16_scale(const psoam_plan* P, int mode, double c1, double c2, hipStream_t s) {
+  hipLaunchKernelGGL(f16_scale_kernel, dim3(1), dim3(1), 0, s, P->d_f16, P->d_f16acc, mode,
+                     (float)c1, (float)c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_f16_pmax(const psoam_plan* P, const float* p, hipStream_t s) {
+  if (!P->d_f16) return hipSuccess;
+  if (p) {
+    const hipError_t e = f16_amax(P, p, (int64_t)P->y_elems(), 1, s);
+    if (e != hipSuccess) return e;
+  }
+  return f16_scale(P, 2, 0.0, 0.0, s);
+}
+
+// --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
 static inline unsigned blocks_for(size_t n, unsigned bs = 256) {
@@ -899,6 +993,12 @@ static inline unsigned blocks_for(size_t n, unsigned bs = 256) {
 hipError_t launch_switch_fwd(const psoam_plan* P, const float* c, hipStream_t s) {
   const auto& g = P->g;
   const float* stab = P->d_stab;
+  if (P->d_f16) {
+    // |b_k| <= sum_s |S_v[k][s]| |c_s| <= srow max |c|
+    hipError_t e = f16_amax(P, c, (int64_t)P->c_elems(), 0, s);
+    if (e == hipSuccess) e = f16_scale(P, 0, P->srow, 0.0, s);
+    if (e != hipSuccess) return e;
+  }
   const int vec = P->d_stab_o && (g.nz % 8) == 0 && ((uintptr_t)c & 15) == 0;
   switch (P->prec) {
     case PSOAM_FP32: {
@@ -912,7 +1012,7 @@ hipError_t launch_switch_fwd(const psoam_plan* P, const float* c, hipStream_t s)
     using E = Half<PR>::E;                                                                  \
     const size_t n = (size_t)g.ny * g.nx * (P->Lz / 8) * P->Kp;                            \
     hipLaunchKernelGGL((switch_fwd16<PR, SP>), dim3(blocks_for(n)), dim3(256), 0, s, c,     \
-                       P->d_phi, stab, P->d_stab_o, vec, P->sw, (E*)P->d_bq,               \
+                       P->d_phi, stab, P->d_stab_o, vec, P->d_f16, P->sw, (E*)P->d_bq,     \
                        (E*)P->d_bq_lo, g.ny, g.nx, g.nz, P->Lz / 8, P->Kp, P->Xp, P->R,    \
                        P->ps_b);                                                            \
     break;                                                                                  \
@@ -931,6 +1031,11 @@ hipError_t launch_switch_fwd(const psoam_plan* P, const float* c, hipStream_t s)
 
 hipError_t launch_pack_r(const psoam_plan* P, const float* y, hipStream_t s) {
   const auto& g = P->g;
+  if (P->d_f16) {
+    hipError_t e = f16_amax(P, y, (int64_t)P->y_elems(), 1, s);
+    if (e == hipSuccess) e = f16_scale(P, 1, 1.0, 0.0, s);
+    if (e != hipSuccess) return e;
+  }
   // 16-byte loads of the A-scans when every octet starts 16-byte aligned
   const int vec4 = ((uintptr_t)y & 15) == 0 && (g.nt & 3) == 0;
   switch (P->prec) {
@@ -944,7 +1049,7 @@ hipError_t launch_pack_r(const psoam_plan* P, const float* y, hipStream_t s) {
     const size_t n = (size_t)g.ny * g.nx;                                                   \
     hipLaunchKernelGGL((pack_r16<PR, SP>), dim3((unsigned)n), dim3(256), 0, s, y,           \
                        (E*)P->d_rq, (E*)P->d_rq_lo, g.n_pulses, g.ny, g.nx, g.nt, P->Lt / 8, \
-                       P->Kp, P->Xp, P->R, P->ps_r, vec4, P->tsh);                          \
+                       P->Kp, P->Xp, P->R, P->ps_r, vec4, P->tsh, P->d_f16);                \
     break;                                                                                  \
   }
     case PSOAM_BF16:
@@ -1099,6 +1204,12 @@ hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* p
   A.nk = P->g.n_pulses;
   A.kp = P->Kp;
   A.inv_scale = fp16 ? 1.0f / kFp16Scale : 1.0f;
+  A.f16 = P->d_f16;
+  if (mode == 1 && P->d_f16) {
+    // residual r = H b - p: |r| <= hrow max |b| + max |p| with max |b| <= srow max |x|
+    const hipError_t e = f16_scale(P, 3, P->hrow * P->srow, 1.0, s);
+    if (e != hipSuccess) return e;
+  }
   A.out = out;
   A.pmeas = pmeas;
   A.rq = P->d_rq;
@@ -2028,9 +2139,11 @@ __global__ __launch_bounds__(512) void eir_pack16(const float* __restrict__ q,
                                                   typename Half<PREC>::E* __restrict__ rq,
                                                   typename Half<PREC>::E* __restrict__ rq_lo,
                                                   int nk, int ny, int nx, int nt, int to_n,
-                                                  int kp, int xp, int r, size_t ps, int tsh) {
+                                                  int kp, int xp, int r, size_t ps, int tsh,
+                                                  const float* __restrict__ f16) {
   using H = Half<PREC>;
   using V = typename H::V;
+  const float sc = f16 ? f16[2] : H::scale;   // operand scale (FP16: per call)
   constexpr int NTH = eir_pack_threads(RESID);
   extern __shared__ float ep_lds[];
   const int sst = eir_pack_stride(nt);
@@ -2149,7 +2262,7 @@ __global__ __launch_bounds__(512) void eir_pack16(const float* __restrict__ q,
     V hi, lo;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const float v = (t0 + u >= 0 && t0 + u < nt) ? acc[u] * H::scale : 0.0f;
+      const float v = (t0 + u >= 0 && t0 + u < nt) ? acc[u] * sc : 0.0f;
       hi[u] = (typename H::E)v;
       lo[u] = (typename H::E)(v - (float)hi[u]);
     }
@@ -2174,6 +2287,19 @@ bool eir_pack_fits(const psoam_plan* P, bool resid) {
 hipError_t launch_eir_pack(const psoam_plan* P, const float* q, const float* p, bool resid,
                            hipStream_t s) {
   if (!eir_pack_fits(P, resid)) return hipErrorInvalidValue;
+  if (P->d_f16) {
+    // V^T (V q - p) with q = Lambda S x: bound l1 (l1 hrow srow max|x| + max|p|),
+    // l1 = sum |v|; the adjoint's V^T y: l1 max|y|
+    const double l1 = P->eir_l1;
+    hipError_t e = hipSuccess;
+    if (resid) {
+      e = f16_scale(P, 3, l1 * l1 * P->hrow * P->srow, l1, s);
+    } else {
+      e = f16_amax(P, q, (int64_t)P->y_elems(), 1, s);
+      if (e == hipSuccess) e = f16_scale(P, 1, l1, 0.0, s);
+    }
+    if (e != hipSuccess) return e;
+  }
   const auto& g = P->g;
   const size_t lds = eir_pack_lds(P, resid);
   const size_t nb = (size_t)g.ny * g.nx * (P->Kp / 16);
@@ -2188,7 +2314,7 @@ hipError_t launch_eir_pack(const psoam_plan* P, const float* q, const float* p, 
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(eir_pack_threads(RS)), lds, s, q, p, \
                        P->eir,                                                              \
                        (E*)P->d_rq, (E*)P->d_rq_lo, g.n_pulses, g.ny, g.nx, g.nt, P->Lt / 8, \
-                       P->Kp, P->Xp, P->R, P->ps_r, P->tsh);                                \
+                       P->Kp, P->Xp, P->R, P->ps_r, P->tsh, P->d_f16);                      \
   }
 #define PSOAM_EP(PR, SP)                                                                    \
   {                                                                                         \

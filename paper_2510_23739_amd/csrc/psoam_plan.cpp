@@ -117,6 +117,7 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   // low-order BF16 part of a band value (second layer of the refined form)
   auto low = [](float v) { return v - from_bf16(to_bf16(v)); };
   size_t useful = 0;
+  std::vector<double> rowsum(dir == 0 ? g.nt : 0, 0.0);  // sum of |h| per output sample
   for (int z = 0; z < g.nz; ++z)
     for (int jdy = 0; jdy < F; ++jdy)
       for (int jdx = 0; jdx < F; ++jdx) {
@@ -126,6 +127,7 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
           const int t = t0[col] + j;
           if (v == 0.0f || t < 0 || t >= g.nt) continue;
           ++useful;
+          if (dir == 0) rowsum[t] += std::fabs((double)v);
           int tile, jy, jx, l;
           if (dir == 0) {
             tile = t / 16; jy = jdy; jx = jdx; l = z / gw;
@@ -140,6 +142,13 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   T.n_mtiles = n_mt;
   T.m_rows = out_len;
   T.useful_macs = useful;
+  if (dir == 0) {
+    // largest row sum of |h| (FP16 rounding of the table can add 2^-11 of it;
+    // the operand scales keep a factor of four of headroom)
+    double m = 0.0;
+    for (double r : rowsum) m = std::max(m, r);
+    P->hrow = m;
+  }
 
   // band values of one group into lane-major chunk storage
   auto fill = [&](std::vector<float>& vals, int c, int gi, const Group& G, int tile) {
@@ -527,7 +536,8 @@ void free_plan(psoam_plan* P) {
   free_table(P->fwd);
   free_table(P->adj);
   void* bufs[] = {P->d_phi, P->d_stab, P->d_stab_t, P->d_stab_o, P->d_bq, P->d_bq_lo, P->d_rq, P->d_rq_lo,
-                  P->solve_ws.base, P->r3_ws.base, P->d_partial, P->d_scalars};
+                  P->solve_ws.base, P->r3_ws.base, P->d_partial, P->d_scalars, P->d_f16,
+                  P->d_f16acc};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete P;
@@ -676,8 +686,22 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
     double m = 0.0;  // S'_v = phi_v I
     for (size_t i = 0; i < nphi; ++i) m = std::max(m, (double)phi[i] * (double)phi[i]);
     P->smax2 = m;
+    P->srow = std::sqrt(m);
   } else {
     P->smax2 = switching_norm2(g, sp, phi, nphi);
+    // largest row sum of |S_v| (bound of the switched operand per unit of c)
+    double m = 0.0;
+    for (size_t i = 0; i < nphi; ++i) {
+      const double ph = phi[i];
+      const double pg = sp->gamma == 0.0 ? 1.0 : std::pow(ph, sp->gamma);
+      for (int k = 0; k < g.n_pulses; ++k) {
+        double row = 0.0;
+        for (int sidx = 0; sidx < g.n_species; ++sidx)
+          row += std::fabs(ph * (sp->a[sidx] + sp->b[sidx] * std::exp(-(double)k * pg / sp->tau[sidx])));
+        m = std::max(m, row);
+      }
+    }
+    P->srow = m;
   }
   PLAN_HIP(hipMalloc(&P->d_phi, sizeof(float) * nphi));
   PLAN_HIP(hipMemcpy(P->d_phi, phi, sizeof(float) * nphi, hipMemcpyHostToDevice));
@@ -728,6 +752,13 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
   PLAN_HIP(hipMalloc(&P->d_rq, P->rq_bytes));
   PLAN_HIP(hipMemsetAsync(P->d_bq, 0, P->bq_bytes, stream));
   PLAN_HIP(hipMemsetAsync(P->d_rq, 0, P->rq_bytes, stream));
+  if (prec == PSOAM_FP16 || prec == PSOAM_FP16_SPLIT) {
+    const float init[8] = {kFp16Scale, 1.0f / kFp16Scale, kFp16Scale, 1.0f / kFp16Scale, 0, 0, 0, 0};
+    PLAN_HIP(hipMalloc(&P->d_f16, sizeof(init)));
+    PLAN_HIP(hipMemcpy(P->d_f16, init, sizeof(init), hipMemcpyHostToDevice));
+    PLAN_HIP(hipMalloc(&P->d_f16acc, 4 * sizeof(unsigned)));
+    PLAN_HIP(hipMemset(P->d_f16acc, 0, 4 * sizeof(unsigned)));
+  }
   if (split) {
     PLAN_HIP(hipMalloc(&P->d_bq_lo, P->bq_bytes));
     PLAN_HIP(hipMalloc(&P->d_rq_lo, P->rq_bytes));
@@ -948,6 +979,8 @@ int create_plan_factorised(const psoam_geom* gp, const psoam_species* sp, const 
   P->eir.n = sh->n_eir;
   P->eir.origin = sh->eir_origin;
   for (int j = 0; j < sh->n_eir; ++j) P->eir.v[j] = eir[j];
+  P->eir_l1 = 0.0;
+  for (int j = 0; j < sh->n_eir; ++j) P->eir_l1 += std::fabs((double)eir[j]);
   hipError_t e = hipMalloc(&P->d_fq, sizeof(float) * P->y_elems());
   if (e != hipSuccess) {
     free_plan(P);
