@@ -85,6 +85,7 @@ struct BandTable {
   int n_runs = 0;
   int max_runs = 0;            // most runs of one output tile (LDS run table)
   int* d_rinfo = nullptr;      // [n_runs * 2] run length, first chunk
+  int loadw = 0;               // > 0: loader waves beside the contracting ones (staged H)
 };
 
 // LDS bytes of the staged kernel's per-tile tables: row windows (F + rows - 1),

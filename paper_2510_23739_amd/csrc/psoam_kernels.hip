@@ -676,8 +676,18 @@ struct LdsArgs {
   int la_bytes;      // bytes of la (and la_lo), including kRunMax zero chunks at the end
 };
 
-template <int PREC, bool SPLIT, int MODE, int ROWS>
+// LOADW > 0 (one-part operands, one workgroup per CU): LOADW loader waves
+// beside the ROWS contracting waves.  The loaders hold the next staged row in
+// registers (up to kLoadItems 16-byte items per thread) while the other waves
+// contract the current one, and write it to LDS between two barriers, so the
+// row's load latency is hidden behind the matrix cores instead of stalling
+// every wave of the workgroup; the loads sit on the loaders' own memory
+// counters, so the contracting waves' waits for band blocks never wait for
+// them.  kLoadItems * 64 * LOADW must cover the widest window (plan time).
+constexpr int kLoadItems = 25;
+template <int PREC, bool SPLIT, int MODE, int ROWS, int LOADW>
 __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs& L) {
+  static_assert(LOADW == 0 || !SPLIT, "loader waves stage one-part operands");
   using H = Half<PREC>;
   using E = typename H::E;
   using V = typename H::V;
@@ -707,13 +717,17 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   }
   const int xb = pos % L.nxb;
   const int yb = pos / L.nxb;
-  constexpr int NT = 64 * ROWS;
+  constexpr int NTALL = 64 * (ROWS + LOADW);             // threads of the workgroup
+  constexpr int NT = 64 * (LOADW > 0 ? LOADW : ROWS);    // threads that stage rows
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, n = lane & 15;
   const int iy0 = yb * ROWS, ix0 = xb * kLdsPos;
   const int iy = iy0 + wave;
-  const bool row_ok = iy < A.ny;
+  const bool loader = LOADW > 0 && wave >= ROWS;          // uniform per wave
+  const bool row_ok = !loader && iy < A.ny;
+  // this thread's index among the staging threads
+  const int st_id = (int)threadIdx.x - (LOADW > 0 ? 64 * ROWS : 0);
   const int F = L.f;
   const int XW = kLdsPos + F - 1;
   const int nwin = F + ROWS - 1;
@@ -723,12 +737,12 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   const E* qlo = (const E*)A.q_lo;
   {
     const int nw = L.f + ROWS - 1;
-    for (int i = (int)threadIdx.x; i < nw; i += NT) s_win[i] = L.win[mtile * nw + i];
+    for (int i = (int)threadIdx.x; i < nw; i += NTALL) s_win[i] = L.win[mtile * nw + i];
     const int rt0 = L.lstart[mtile * L.f];
-    for (int i = (int)threadIdx.x; i <= L.f; i += NT) s_lstart[i] = L.lstart[mtile * L.f + i] - rt0;
+    for (int i = (int)threadIdx.x; i <= L.f; i += NTALL) s_lstart[i] = L.lstart[mtile * L.f + i] - rt0;
     const int nrun = L.lstart[(mtile + 1) * L.f] - rt0;
-    for (int i = (int)threadIdx.x; i < 4 * nrun; i += NT) s_rgrp[i] = L.lgrp[4 * rt0 + i];
-    for (int i = (int)threadIdx.x; i < 2 * nrun; i += NT) s_rinfo[i] = L.rinfo[2 * rt0 + i];
+    for (int i = (int)threadIdx.x; i < 4 * nrun; i += NTALL) s_rgrp[i] = L.lgrp[4 * rt0 + i];
+    for (int i = (int)threadIdx.x; i < 2 * nrun; i += NTALL) s_rinfo[i] = L.rinfo[2 * rt0 + i];
     __syncthreads();
   }
   double ss = 0.0;
@@ -758,66 +772,115 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
     for (int i = 0; i < kRunMax; ++i) load_run(cb0, ab, al, i);
   }
   __builtin_amdgcn_s_waitcnt(kVmcnt0);
+  // Staging: thread t loads items t, t+NT, ... of the row, where item
+  // it = (oi*XW + xi)*16 + nn is one 16-byte octet of pulse nn at column xi
+  // of octet oi; nn = t%16 is fixed and (xi, oi) advance by NT/16 columns
+  // per step.  Without loader waves every thread stages, kStageBatch loads in
+  // flight before their LDS writes.  The split forms stage the high and the
+  // low operand rows in two passes over the window (the same LDS tile):
+  // pass 0 adds hi(H) hi(q) + lo(H) hi(q), pass 1 adds hi(H) lo(q).
+  const int t16 = st_id >> 4;
+  const int tnn = st_id & 15;
+  const int ps = (int)A.ps;
+  const int row_bytes = A.xp * ps * (int)sizeof(E);
+  const int dwrap = -XW * ps + A.kp * 8;
+  // issue the loads of items u0*NT + t, (u0+1)*NT + t, ... of staged row jr
+  // of pulse block pb_r (all unconditional: an item past the window still
+  // lies inside the padded row, and its value is never written to LDS)
+  auto issue = [&](V* tmp, int cnt, int u0, int jr, int pb_r, int pass_r) {
+    const int obase_r = (int)(s_win[jr] >> 16);
+    const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((pass_r ? qlo : q) + (size_t)(iy0 + jr) * A.xp * A.ps), (short)0, row_bytes, kBufWord3);
+    int r2 = u0 * (NT / 16) + t16;
+    int xi = r2 % XW, oi = r2 / XW;
+    int off = (ix0 + xi) * ps + ((obase_r + oi) * A.kp + pb_r * 16 + tnn) * 8;
+#pragma unroll
+    for (int u = 0; u < cnt; ++u) {
+      const int ob = off * (int)sizeof(E);
+      tmp[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rq, ob, 0, 0));
+      // advance by NT/16 columns; XW >= 16 and NT/16 <= 32, so at most
+      // two wraps into the next octet (selects, no branches)
+      xi += NT / 16;
+      off += (NT / 16) * ps;
+      const bool w1 = xi >= XW;
+      xi = w1 ? xi - XW : xi;
+      off = w1 ? off + dwrap : off;
+      if constexpr (NT / 16 > 16) {
+        const bool w2 = xi >= XW;
+        xi = w2 ? xi - XW : xi;
+        off = w2 ? off + dwrap : off;
+      }
+    }
+  };
+  // a staged row is skipped when its window is empty or it lies past the
+  // padded grid (uniform over the block)
+  auto staged = [&](int jr) { return (s_win[jr] & 0xffffu) != 0 && iy0 + jr < L.yp; };
+  auto row_from = [&](int jr) {
+    for (int k2 = jr; k2 < nwin; ++k2)
+      if (staged(k2)) return k2;
+    return nwin;
+  };
+  if constexpr (LOADW > 0) {
+    if (loader) {
+      // The loader waves' own loop: the same staged rows, the same two
+      // barriers per row as the contracting waves' loop below.  A row is
+      // written to LDS between the barriers; the next row (or the next pulse
+      // block's first) is then loaded while the other waves contract.
+      V pf[kLoadItems];
+      {
+        const int j0 = row_from(0);
+        if (j0 < nwin) issue(pf, kLoadItems, 0, j0, 0, 0);
+      }
+      for (int pb = 0; pb < nb_n; ++pb)
+        for (int j = 0; j < nwin; ++j) {
+          if (!staged(j)) continue;
+          __syncthreads();  // the previous row's contractions are done with LDS
+          const int items = (int)(s_win[j] & 0xffffu) * XW * 16;
+          __builtin_amdgcn_s_waitcnt(kVmcnt0);  // row j has arrived
+#pragma unroll
+          for (int u = 0; u < kLoadItems; ++u) {
+            const int it = u * NT + st_id;
+            if (it < items) *(V*)(sh + it * 8) = pf[u];
+          }
+          __syncthreads();
+          // next in staging order: a later row of this block, else the next
+          // block's first row
+          int jn = row_from(j + 1), pbn = pb;
+          if (jn == nwin) {
+            jn = row_from(0);
+            pbn = pb + 1;
+          }
+          if (jn < nwin && pbn < nb_n) issue(pf, kLoadItems, 0, jn, pbn, 0);
+        }
+      return;
+    }
+  }
   for (int pb = 0; pb < nb_n; ++pb) {
     f32x4 acc[kLdsPos];
     zero_acc(acc);
-    // Staging: thread t loads items t, t+NT, ... of the row, where item
-    // it = (oi*XW + xi)*16 + nn is one 16-byte octet of pulse nn at column xi
-    // of octet oi; nn = t%16 is fixed and (xi, oi) advance by NT/16 columns
-    // per step.  kStageBatch loads are in flight before their LDS writes.
-    // The split forms stage the high and the low operand rows in two passes
-    // over the window (the same LDS tile): pass 0 adds hi(H) hi(q) +
-    // lo(H) hi(q), pass 1 adds hi(H) lo(q).
-    const int t16 = (int)threadIdx.x >> 4;
-    const int tnn = (int)threadIdx.x & 15;
     for (int pass = 0; pass < (SPLIT ? 2 : 1); ++pass)
     for (int j = 0; j < nwin; ++j) {
       const uint32_t wj = s_win[j];
       const int ocnt = (int)(wj & 0xffffu), obase = (int)(wj >> 16);
-      if (ocnt == 0 || iy0 + j >= L.yp) continue;  // uniform over the block
+      if (!staged(j)) continue;
       __syncthreads();  // the previous row's contractions are done with LDS
-      const int items = ocnt * XW * 16;
-      // Buffer loads from this staged row: all issued unconditionally (an
-      // item past the window still lies inside the padded row, and its value
-      // is never written to LDS), so one wait covers the batch.
-      const int ps = (int)A.ps;
-      const int row_bytes = A.xp * ps * (int)sizeof(E);
-      const int dwrap = -XW * ps + A.kp * 8;
-      const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)((pass ? qlo : q) + (size_t)(iy0 + j) * A.xp * A.ps), (short)0, row_bytes, kBufWord3);
-      constexpr int NPRE = kStageBatch;
-      for (int u0 = 0; u0 * NT < items; u0 += NPRE) {
-        V tmp[NPRE];
-        int r2 = u0 * (NT / 16) + t16;
-        int xi = r2 % XW, oi = r2 / XW;
-        int off = (ix0 + xi) * ps + ((obase + oi) * A.kp + pb * 16 + tnn) * 8;
+      if constexpr (LOADW == 0) {
+        const int items = ocnt * XW * 16;
+        constexpr int NPRE = kStageBatch;
+        for (int u0 = 0; u0 * NT < items; u0 += NPRE) {
+          V tmp[NPRE];
+          issue(tmp, NPRE, u0, j, pb, pass);
+          // all of the batch has landed (the writes below are conditional, and
+          // a load left pending on a skipped path would stall the run loop)
+          __builtin_amdgcn_s_waitcnt(kVmcnt0);
 #pragma unroll
-        for (int u = 0; u < NPRE; ++u) {
-          const int ob = off * (int)sizeof(E);
-          tmp[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rq, ob, 0, 0));
-          // advance by NT/16 columns; XW >= 16 and NT/16 <= 32, so at most
-          // two wraps into the next octet (selects, no branches)
-          xi += NT / 16;
-          off += (NT / 16) * ps;
-          const bool w1 = xi >= XW;
-          xi = w1 ? xi - XW : xi;
-          off = w1 ? off + dwrap : off;
-          if constexpr (NT / 16 > 16) {
-            const bool w2 = xi >= XW;
-            xi = w2 ? xi - XW : xi;
-            off = w2 ? off + dwrap : off;
+          for (int u = 0; u < NPRE; ++u) {
+            const int it = (u0 + u) * NT + (int)threadIdx.x;
+            if (it < items) *(V*)(sh + it * 8) = tmp[u];
           }
         }
-        // all of the batch has landed (the writes below are conditional, and
-        // a load left pending on a skipped path would stall the run loop)
-        __builtin_amdgcn_s_waitcnt(kVmcnt0);
-#pragma unroll
-        for (int u = 0; u < NPRE; ++u) {
-          const int it = (u0 + u) * NT + (int)threadIdx.x;
-          if (it < items) *(V*)(sh + it * 8) = tmp[u];
-        }
       }
-      __syncthreads();
+      __syncthreads();  // row j is in LDS
       const int dy = j - wave;
       if (row_ok && dy >= 0 && dy < F) {
         // Runs of this (tile, dy).  Within a run the four groups keep their
@@ -875,26 +938,27 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   }
   if constexpr (MODE == 1) {
     ss = wave_sum(ss);
-    if (lane == 0) A.partial[(size_t)b * ROWS + wave] = ss;
+    if (lane == 0 && !loader) A.partial[(size_t)b * ROWS + wave] = ss;
   }
 }
 
 // H and the residual form are held to three waves per SIMD with one-part
 // operands (three 4-row workgroups of ~47 KB share a CU at 31 x 31
 // footprints) and to two with split operands (their second band-block
-// buffer needs the registers).
-template <int PREC, bool SPLIT, int MODE, int ROWS>
-__global__ __launch_bounds__(64 * ROWS) __attribute__((amdgpu_waves_per_eu(!SPLIT ? 3 : 2))) void band16_lds(
+// buffer needs the registers) or with the row prefetch (one 8-row
+// workgroup per CU: its 256 registers hold the prefetched row).
+template <int PREC, bool SPLIT, int MODE, int ROWS, int LOADW>
+__global__ __launch_bounds__(64 * (ROWS + LOADW)) __attribute__((amdgpu_waves_per_eu(!SPLIT ? 3 : 2))) void band16_lds(
     BandArgs A, LdsArgs L) {
-  band16_lds_body<PREC, SPLIT, MODE, ROWS>(A, L);
+  band16_lds_body<PREC, SPLIT, MODE, ROWS, LOADW>(A, L);
 }
 
 // H^T with one-part operands is held to two waves per SIMD (256 registers)
 // so that two 4-row workgroups can share a CU when their staged window fits
-template <int PREC, bool SPLIT, int ROWS>
-__global__ __launch_bounds__(64 * ROWS) __attribute__((amdgpu_waves_per_eu(SPLIT ? 1 : 2))) void band16_lds_adj(
+template <int PREC, bool SPLIT, int ROWS, int LOADW>
+__global__ __launch_bounds__(64 * (ROWS + LOADW)) __attribute__((amdgpu_waves_per_eu(SPLIT ? 1 : 2))) void band16_lds_adj(
     BandArgs A, LdsArgs L) {
-  band16_lds_body<PREC, SPLIT, 2, ROWS>(A, L);
+  band16_lds_body<PREC, SPLIT, 2, ROWS, LOADW>(A, L);
 }
 
 // --------------------------------------------------------------------------
@@ -1106,27 +1170,48 @@ static hipError_t launch_band_lds(const psoam_plan* P, const BandTable& T, BandA
   L.lds_elems = (int)(T.lds_bytes / sizeof(uint16_t));
   L.meta_off = (int)((T.lds_bytes + 15) / 16 * 16);
   const size_t lds = L.meta_off + lds_meta_bytes(P->F, T.rows, T.max_runs);
-#define PSOAM_LDS_R(PR, SP, R)                                                              \
+#define PSOAM_LDS_K(PR, SP, R, PF)                                                          \
   {                                                                                         \
     if constexpr (MODE == 2) {                                                              \
-      auto kern = band16_lds_adj<PR, SP, R>;                                                \
+      auto kern = band16_lds_adj<PR, SP, R, PF>;                                            \
       if (lds > 64 * 1024)                                                                  \
         (void)hipFuncSetAttribute((const void*)kern,                                        \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
-      hipLaunchKernelGGL(kern, grid, dim3(64 * R), lds, s, A, L);                           \
+      hipLaunchKernelGGL(kern, grid, dim3(64 * (R + PF)), lds, s, A, L);                    \
     } else {                                                                                \
-      auto kern = band16_lds<PR, SP, MODE, R>;                                              \
+      auto kern = band16_lds<PR, SP, MODE, R, PF>;                                          \
       if (lds > 64 * 1024)                                                                  \
         (void)hipFuncSetAttribute((const void*)kern,                                        \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
-      hipLaunchKernelGGL(kern, grid, dim3(64 * R), lds, s, A, L);                           \
+      hipLaunchKernelGGL(kern, grid, dim3(64 * (R + PF)), lds, s, A, L);                    \
     }                                                                                       \
   }
+#define PSOAM_LDS_R(PR, SP, R) PSOAM_LDS_K(PR, SP, R, 0)
 #define PSOAM_LDS(PR, SP)                                                                   \
   {                                                                                         \
     if (T.rows == 8) PSOAM_LDS_R(PR, SP, 8) else PSOAM_LDS_R(PR, SP, 4)                     \
     break;                                                                                  \
   }
+  // one-part operands, one 8-row workgroup per CU: four loader waves beside
+  // the eight contracting ones (H and its residual form)
+#define PSOAM_LDS_PF(PR)                                                                    \
+  {                                                                                         \
+    PSOAM_LDS_K(PR, false, 8, 4)                                                            \
+    break;                                                                                  \
+  }
+  if constexpr (MODE != 2) {
+  if (T.loadw > 0 && T.rows == 8) {
+    switch (P->prec) {
+      case PSOAM_BF16:
+      case PSOAM_BF16_REFINED: PSOAM_LDS_PF(PSOAM_BF16)
+      case PSOAM_FP16: PSOAM_LDS_PF(PSOAM_FP16)
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  }
+#undef PSOAM_LDS_PF
   switch (P->prec) {
     case PSOAM_BF16:
     case PSOAM_BF16_REFINED: PSOAM_LDS(PSOAM_BF16, false)
@@ -1138,6 +1223,7 @@ static hipError_t launch_band_lds(const psoam_plan* P, const BandTable& T, BandA
   }
 #undef PSOAM_LDS
 #undef PSOAM_LDS_R
+#undef PSOAM_LDS_K
   return hipGetLastError();
 }
 

@@ -395,6 +395,24 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   T.rows = rows;
   T.max_oct = rows == 8 ? mo8 : mo4;
   T.lds_bytes = (size_t)T.max_oct * XW * 16 * 8 * sizeof(uint16_t);
+  // Loader waves: with one 8-row workgroup per CU (LDS above half a CU's)
+  // nothing else hides the staging latency, so four more waves load the next
+  // row into registers during the current row's contractions (H and its
+  // residual form, one-part operands; 25 items per loader thread must cover
+  // the widest window).
+  T.loadw = 0;
+  {
+    const size_t items = (size_t)T.max_oct * XW * 16;
+    const bool able = rows == 8 && !split && dir == 0 && items <= (size_t)25 * 256;
+    const bool alone = lds8 > (size_t)kLdsMaxBytes / 2;
+    T.loadw = (able && alone) ? 4 : 0;
+    // PSOAM_LDS_LOADW=0 keeps the plain staging, =1 takes the loader waves
+    // wherever they can run (tests and A/B timing run both)
+    if (const char* e = std::getenv("PSOAM_LDS_LOADW")) {
+      if (e[0] == '0') T.loadw = 0;
+      if (e[0] == '1' && able) T.loadw = 4;
+    }
+  }
   // PSOAM_BAND_GLOBAL=1 keeps the plan on the global-operand kernel (tests cover both)
   const char* force_global = std::getenv("PSOAM_BAND_GLOBAL");
   T.lds_ok = n_l < 0xffff && F < 0xffff && (rows == 8 ? lds8 : lds4) <= (size_t)kLdsMaxBytes &&

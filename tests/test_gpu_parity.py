@@ -49,14 +49,17 @@ def test_apply_A_and_AT_C1(c1, prec):
                                          ("fp16", "lds"), ("bf16", "global"),
                                          ("bf16_split", "global"), ("bf16", "lds8"),
                                          ("fp16_split", "lds8"), ("bf16_refined", "lds"),
-                                         ("bf16_refined", "global"), ("bf16_refined", "lds8")])
+                                         ("bf16_refined", "global"), ("bf16_refined", "lds8"),
+                                         ("bf16", "lds8load"), ("fp16", "lds8load"),
+                                         ("bf16_refined", "lds8load")])
 def test_ragged_random_table(prec, kernel, monkeypatch):
     """Sizes off every tile boundary, per-voxel fluence with the fluence-
     dependent rate, asymmetric random band running off both ends; both the
     LDS-staged and the global-operand band kernels."""
     torch = torch_cuda()
     monkeypatch.setenv("PSOAM_BAND_GLOBAL", "1" if kernel == "global" else "0")
-    monkeypatch.setenv("PSOAM_LDS_ROWS", "8" if kernel == "lds8" else "4")
+    monkeypatch.setenv("PSOAM_LDS_ROWS", "8" if kernel.startswith("lds8") else "4")
+    monkeypatch.setenv("PSOAM_LDS_LOADW", "1" if kernel == "lds8load" else "0")
     cfg, t0, taps, phi, sp = ragged_cfg(3)
     say(f"[parity] ragged prec={prec}")
     S = oracle_S(cfg, phi, sp)
@@ -301,3 +304,32 @@ def test_autograd_backward_is_adjoint(c1):
     an = float((c.grad.double() * d.double()).sum())
     say(f"[parity] finite difference {fd:.8e} analytic {an:.8e}")
     assert fd == pytest.approx(an, rel=1e-5)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_loader_waves_change_nothing(c1, prec, monkeypatch):
+    """The staged H kernel with four loader waves (the next row loaded during
+    the current row's contractions) against the same kernel staging its rows
+    itself: the same LDS tiles and the same products in the same order, so
+    A, the residual form inside the solver and the solve's iterates are equal
+    bit for bit (8-row workgroups on the 32x32x16 grid and a ragged one)."""
+    torch = torch_cuda()
+    cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
+    p, A, AT, lam_tv, lam_l1 = _c1_problem(c1)
+    cfg2, t02, taps2, phi2, sp2 = ragged_cfg(9)
+    monkeypatch.setenv("PSOAM_LDS_ROWS", "8")
+    out = {}
+    for lw in ("0", "1"):
+        monkeypatch.setenv("PSOAM_LDS_LOADW", lw)
+        plan = lib_plan(cfg, t0, taps, phi, sp, prec)
+        plan2 = lib_plan(cfg2, t02, taps2, phi2, sp2, prec)
+        c2 = np.random.default_rng(5).standard_normal(cfg2.c_shape).astype(np.float32)
+        out[lw] = (plan.apply_A(torch.from_numpy(c_true).cuda()),
+                   plan.solve(torch.from_numpy(p).cuda(), lambda_tv=lam_tv, lambda_l1=lam_l1,
+                              k1=4, k2=5, alpha1=1e-3)[0],
+                   plan2.apply_A(torch.from_numpy(c2).cuda()))
+        plan.close()
+        plan2.close()
+    for a, b in zip(out["0"], out["1"]):
+        assert torch.equal(a, b)
+    say(f"[parity] loader waves {prec}: A, solve and ragged A bitwise equal")
