@@ -223,6 +223,17 @@ typedef struct {
                               reg-tv-l1-one); > 0 selects the full
                               regulariser's prox (psoam_prox_r3; warm_inner
                               does not apply to it) */
+  int32_t device_stop;     /* 0: the stopping tests and the trace read FP64
+                              scalars on the host every iteration (the solve
+                              synchronises per iteration); 1: they run on the
+                              device: a one-thread kernel after each
+                              iteration takes the same decisions in the same
+                              FP64 arithmetic and sets a device flag that
+                              every later kernel of the solve checks first
+                              (and returns), so the iterations are enqueued
+                              without host reads (and psoam_solve_batch
+                              captures them into graphs); the trace is
+                              copied to the host at the end */
 } psoam_solve_opts;
 
 typedef struct {
@@ -244,7 +255,7 @@ typedef struct {
  * p: device [K][Ny][Nx][Nt]; c: device [S][Ny][Nx][Nz], initial guess on
  * entry (zeros for the paper's start), result on exit.  st: host, may be
  * NULL.  Synchronises the stream when it needs host scalars (power
- * iteration result, stopping tests, trace) and at exit.
+ * iteration result, stopping tests and trace unless device_stop) and at exit.
  * EINVAL: bad options; EDIVERGED: non-finite reduction (c holds the last
  * finite iterate). */
 int psoam_solve(const psoam_plan* plan, const float* p, float* c, const psoam_solve_opts* o,
@@ -328,13 +339,15 @@ int psoam_unmix(const psoam_plan* plan, const float* b, float* c, const psoam_so
  * (Alg. alg:prox-outer per problem).  Arrays of length n; opts/st arrays
  * too (st may be NULL).  Same result per problem as psoam_solve.
  * Execution: every problem runs on a stream of its own (default priority);
- * the power iterations run concurrently, then pairs of outer iterations of
- * all problems are captured into one HIP graph (one branch per problem, the
- * FISTA step state kept on the device) and replayed; an odd last iteration
- * runs uncaptured.  Problems whose options need host decisions inside the
- * loop (eps1 > 0, eps2 > 0, a trace, warm_inner, k1 < 2), and every problem
- * when a plan appears twice in the batch (plans own their operand buffers),
- * are solved one after another on the caller's stream instead.  The call
+ * the power iterations run concurrently, then each problem's pairs of outer
+ * iterations are captured into a HIP graph (the FISTA step state kept on the
+ * device) and replayed on its stream; an odd last iteration runs uncaptured.
+ * Stopping tests and traces run inside the captured iterations when the
+ * problem sets device_stop (its kernels return at once after its test
+ * fires).  Problems that need host decisions inside the loop (eps1 > 0,
+ * eps2 > 0 or a trace without device_stop), warm_inner, k1 < 2, and every
+ * problem when a plan appears twice in the batch (plans own their operand
+ * buffers), are solved one after another on the caller's stream instead.  The call
  * synchronises the streams it creates; results are ordered before later
  * work on `stream`.  EINVAL: bad arguments (checked for all problems before
  * any work); EHIP: stream, event or graph call failed; EDIVERGED as for

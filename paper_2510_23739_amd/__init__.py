@@ -244,24 +244,26 @@ class Plan:
 
     def solve(self, p, c=None, lambda_tv=0.0, lambda_l1=0.0, k1=100, k2=20, eps1=0.0, eps2=0.0,
               alpha1=0.0, n_power=30, literal_momentum=False, warm_inner=False, v0=None,
-              trace: bool = False, stream=None, lambda_tvs=0.0):
-        """Returns (c, stats dict[, trace list])."""
+              trace: bool = False, stream=None, lambda_tvs=0.0, device_stop: bool = False):
+        """Returns (c, stats dict[, trace list]).  device_stop: the stopping
+        tests run on the device (no host read per iteration)."""
         _check_f32(p, self.y_shape, "p")
         return self._iterate("psoam_solve", p, c, lambda_tv, lambda_l1, k1, k2, eps1, eps2,
                              alpha1, n_power, literal_momentum, warm_inner, v0, trace, stream,
-                             lambda_tvs)
+                             lambda_tvs, device_stop)
 
     def unmix(self, b, c=None, lambda_tv=0.0, lambda_l1=0.0, k1=100, k2=20, eps1=0.0, eps2=0.0,
               alpha1=0.0, n_power=30, literal_momentum=False, v0=None, trace: bool = False,
-              stream=None):
+              stream=None, device_stop: bool = False):
         """Unmixing step of the two-step method (psoam_unmix): c from pulse
         volumes b [K][Ny][Nx][Nz].  Returns (c, stats dict[, trace list])."""
         _check_f32(b, self.b_shape, "b")
         return self._iterate("psoam_unmix", b, c, lambda_tv, lambda_l1, k1, k2, eps1, eps2,
-                             alpha1, n_power, literal_momentum, False, v0, trace, stream, 0.0)
+                             alpha1, n_power, literal_momentum, False, v0, trace, stream, 0.0,
+                             device_stop)
 
     def _iterate(self, fn, p, c, lambda_tv, lambda_l1, k1, k2, eps1, eps2, alpha1, n_power,
-                 literal_momentum, warm_inner, v0, trace, stream, lambda_tvs):
+                 literal_momentum, warm_inner, v0, trace, stream, lambda_tvs, device_stop):
         torch = _torch()
         if c is None:
             c = torch.zeros(self.c_shape, dtype=torch.float32, device=p.device)
@@ -273,7 +275,7 @@ class Plan:
                            float(eps2), float(alpha1), int(n_power), int(bool(literal_momentum)),
                            int(bool(warm_inner)), C.c_void_p(v0.data_ptr()) if v0 is not None else None,
                            C.cast(tr, C.POINTER(C.c_double)) if tr is not None else None,
-                           float(lambda_tvs))
+                           float(lambda_tvs), int(bool(device_stop)))
         st = _lib.SolveStats()
         check(getattr(load(), fn)(self.handle, _ptr(p), _ptr(c), C.byref(o), C.byref(st),
                                   _stream(stream)))
@@ -317,11 +319,12 @@ def solve_batch(plans: Sequence[Plan], ps, cs, opts: Sequence[dict], stream=None
                                int(d.get("k1", 100)), int(d.get("k2", 20)),
                                float(d.get("eps1", 0.0)), float(d.get("eps2", 0.0)),
                                float(d.get("alpha1", 0.0)), int(d.get("n_power", 30)), 0, 0,
-                               None, None, float(d.get("lambda_tvs", 0.0)))
+                               None, None, float(d.get("lambda_tvs", 0.0)),
+                               int(bool(d.get("device_stop", False))))
     st = (_lib.SolveStats * n)()
     check(load().psoam_solve_batch(n, hs, pp, cc, oo, st, _stream(stream)))
     return [dict(iterations=s.iterations, status=s.status, alpha1=s.alpha1,
-                 lambda_max=s.lambda_max) for s in st]
+                 lambda_max=s.lambda_max, objective=s.objective) for s in st]
 
 
 def prox_l1(z, thresh: float, nonneg: bool = True, x=None, stream=None):

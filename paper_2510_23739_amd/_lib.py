@@ -32,7 +32,8 @@ class SolveOpts(C.Structure):
                 ("k1", C.c_int32), ("k2", C.c_int32),
                 ("eps1", C.c_double), ("eps2", C.c_double), ("alpha1", C.c_double),
                 ("n_power", C.c_int32), ("literal_momentum", C.c_int32), ("warm_inner", C.c_int32),
-                ("v0", C.c_void_p), ("trace", C.POINTER(C.c_double)), ("lambda_tvs", C.c_double)]
+                ("v0", C.c_void_p), ("trace", C.POINTER(C.c_double)), ("lambda_tvs", C.c_double),
+                ("device_stop", C.c_int32)]
 
 
 class SolveStats(C.Structure):

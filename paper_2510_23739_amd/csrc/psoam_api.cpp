@@ -10,6 +10,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -81,6 +82,7 @@ int ensure_solve_ws(psoam_plan* P, SolveBufs& B) {
     P->n_partial = np;
   }
   if (!P->d_scalars) PSOAM_HIP(hipMalloc(&P->d_scalars, sizeof(double) * 16));
+  if (!P->d_ctl) PSOAM_HIP(hipMalloc(&P->d_ctl, sizeof(int) * 4));
   auto align = [](char* p) { return (float*)(((uintptr_t)p + 255) & ~(uintptr_t)255); };
   char* p = (char*)P->solve_ws.base;
   float** slots[] = {&B.cprev, &B.cnext, &B.xi, &B.g, &B.zb, &B.u[0], &B.u[1], &B.u[2], &B.w};
@@ -92,6 +94,27 @@ int ensure_solve_ws(psoam_plan* P, SolveBufs& B) {
   }
   return PSOAM_OK;
 }
+
+// device objective trace of at least n doubles (device stopping tests)
+int ensure_trace(psoam_plan* P, size_t n) {
+  if (P->n_trace < n) {
+    if (P->d_trace) PSOAM_HIP(hipFree(P->d_trace));
+    P->d_trace = nullptr;
+    P->n_trace = 0;
+    PSOAM_HIP(hipMalloc(&P->d_trace, sizeof(double) * n));
+    P->n_trace = n;
+  }
+  return PSOAM_OK;
+}
+
+// Kernels launched on this thread while a guard lives check the solve's stop
+// flag (device stopping tests) and return at once once it is set.
+struct GateGuard {
+  explicit GateGuard(const int* g) { set_gate(g); }
+  ~GateGuard() { set_gate(nullptr); }
+  GateGuard(const GateGuard&) = delete;
+  GateGuard& operator=(const GateGuard&) = delete;
+};
 
 // x = prox of theta*TV at z by n_inner dual steps (u buffers given), then the
 // final map (mode 0 plain, 1 max(.,0), 2 max(. - th1, 0)).  u_start: dual
@@ -424,6 +447,18 @@ int solve_one(psoam_plan* P, int op, const float* p, float* c, const psoam_solve
   const float* u_warm = nullptr;
   float* uw[3] = {B.u[0], B.u[1], B.u[2]};
   if ((rc = prepare_p(P, op, p, s))) return rc;
+  // device stopping tests: no host read inside the loop; every kernel of
+  // an iteration after the one whose test fires returns at once
+  const bool dev = o->device_stop != 0;
+  float* const a0 = B.cprev;
+  float* const a1 = B.cnext;
+  StopTest tst{o->eps1, o->eps2, o->lambda_tv, o->lambda_l1, o->lambda_tvs, need_obj ? 1 : 0,
+               (op == kOpA && P->inner) ? 1 : 0, r3 ? 1 : 0};
+  if (dev) {
+    if (o->trace && (rc = ensure_trace(P, (size_t)std::max(o->k1, 1)))) return rc;
+    PSOAM_HIP(launch_stop_init(P->d_ctl, P->d_scalars, s));
+  }
+  std::unique_ptr<GateGuard> gate(dev ? new GateGuard(P->d_ctl) : nullptr);
   for (int k = 0; k < o->k1; ++k) {
     // gradient A^T (A xi - p)
     if ((rc = enqueue_grad(P, op, B.xi, p, B.g, s))) return rc;
@@ -457,6 +492,11 @@ int solve_one(psoam_plan* P, int op, const float* p, float* c, const psoam_solve
     }
     std::swap(B.cprev, B.cnext);  // cprev = c_{k+1}
     stats.iterations = k + 1;
+    if (dev) {
+      if (need_obj && (rc = objective_terms(P, op, B.cprev, p, r3, B.w, s))) return rc;
+      PSOAM_HIP(launch_stop_test(P->d_ctl, P->d_scalars, o->trace ? P->d_trace : nullptr, tst, s));
+      continue;
+    }
     bool stop = false;
     if (need_obj || o->eps2 > 0.0) {
       if (need_obj) {
@@ -490,10 +530,25 @@ int solve_one(psoam_plan* P, int op, const float* p, float* c, const psoam_solve
     }
     if (stop) break;
   }
-  PSOAM_HIP(hipMemcpyAsync(c, B.cprev, sizeof(float) * sv, hipMemcpyDeviceToDevice, s));
+  gate.reset();
+  if (dev) {
+    PSOAM_HIP(launch_select_copy(c, a0, a1, P->d_ctl, sv, s));
+  } else {
+    PSOAM_HIP(hipMemcpyAsync(c, B.cprev, sizeof(float) * sv, hipMemcpyDeviceToDevice, s));
+  }
   PSOAM_HIP(launch_dot(c, c, sv, P->d_partial, P->d_scalars + 0, s));
-  rc = copy_scalars(P, hs, 1, s);
+  rc = copy_scalars(P, hs, 13, s);
   if (rc) return rc;
+  if (dev) {
+    int ctl[4];
+    PSOAM_HIP(hipMemcpy(ctl, P->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost));
+    stats.iterations = o->k1 > 0 ? ctl[1] : 0;
+    if (ctl[2]) stats.status = PSOAM_EDIVERGED;
+    if (need_obj && stats.iterations > 0) stats.objective = hs[12];
+    if (o->trace && stats.iterations > 0)
+      PSOAM_HIP(hipMemcpy(o->trace, P->d_trace, sizeof(double) * stats.iterations,
+                          hipMemcpyDeviceToHost));
+  }
   if (!std::isfinite(hs[0])) stats.status = PSOAM_EDIVERGED;
   if (st) *st = stats;
   if (stats.status != PSOAM_OK) return fail(PSOAM_EDIVERGED, "solve: iterate became non-finite");
@@ -513,6 +568,12 @@ struct BatchItem {
   R3Bufs RB;
   double alpha1;
   int remaining;
+  // device stopping tests (device_stop with eps1, eps2 or a trace)
+  bool dev = false;
+  bool need_obj = false;
+  float* a0 = nullptr;  // the iterate buffers' initial roles (c_k, c_{k+1})
+  float* a1 = nullptr;
+  StopTest tst{};
 };
 
 // One outer iteration with the step state t_k on the device (d_scalars[8])
@@ -523,6 +584,7 @@ int enqueue_iteration(BatchItem& it, hipStream_t s) {
   const int64_t sv = (int64_t)P->c_elems();
   SolveBufs& B = it.B;
   const psoam_solve_opts* o = it.o;
+  std::unique_ptr<GateGuard> gate(it.dev ? new GateGuard(P->d_ctl) : nullptr);
   const bool literal = o->literal_momentum != 0;
   const float th_tv = (float)(it.alpha1 * o->lambda_tv);
   const float th_l1 = (float)(it.alpha1 * o->lambda_l1);
@@ -536,8 +598,20 @@ int enqueue_iteration(BatchItem& it, hipStream_t s) {
                                    literal, nullptr, s)) {
     return rc;
   }
-  PSOAM_HIP(launch_momentum_dev(B.xi, B.cnext, B.cprev, P->d_scalars + 8, literal ? 1 : 0, sv, s));
+  const bool eps2 = it.dev && o->eps2 > 0.0;
+  PSOAM_HIP(launch_momentum_dev(B.xi, B.cnext, B.cprev, P->d_scalars + 8, literal ? 1 : 0, sv,
+                                eps2 ? P->d_partial : nullptr, s));
+  if (eps2) {
+    const size_t nb = reduce_blocks(sv);
+    PSOAM_HIP(launch_sum_partials(P->d_partial, nb, P->d_scalars + 2, s));
+    PSOAM_HIP(launch_sum_partials(P->d_partial + nb, nb, P->d_scalars + 3, s));
+  }
   std::swap(B.cprev, B.cnext);  // cprev = c_{k+1}
+  if (it.dev) {
+    if (it.need_obj)
+      if (int rc = objective_terms(P, kOpA, B.cprev, it.p, o->lambda_tvs > 0.0, B.w, s)) return rc;
+    PSOAM_HIP(launch_stop_test(P->d_ctl, P->d_scalars, o->trace ? P->d_trace : nullptr, it.tst, s));
+  }
   return PSOAM_OK;
 }
 
@@ -590,6 +664,13 @@ int solve_batch_graph(std::vector<BatchItem>& items, hipStream_t caller) {
     PSOAM_HIP(launch_set_double(it.P->d_scalars + 8, 1.0, bs.ss[i]));
     if (int rc = prepare_p(it.P, kOpA, it.p, bs.ss[i])) return rc;
     it.remaining = it.o->k1;
+    it.a0 = it.B.cprev;
+    it.a1 = it.B.cnext;
+    if (it.dev) {
+      if (it.o->trace)
+        if (int rc = ensure_trace(it.P, (size_t)std::max(it.o->k1, 1))) return rc;
+      PSOAM_HIP(launch_stop_init(it.P->d_ctl, it.P->d_scalars, bs.ss[i]));
+    }
   }
   // phase 2: each problem's pairs of iterations captured into a graph of its
   // own and replayed on its own stream, so the problems' kernels can overlap
@@ -626,15 +707,29 @@ int solve_batch_graph(std::vector<BatchItem>& items, hipStream_t caller) {
       if (int rc = enqueue_iteration(it, bs.ss[i])) return rc;
     it.stats.iterations = it.o->k1;
     const int64_t sv = (int64_t)it.P->c_elems();
-    PSOAM_HIP(hipMemcpyAsync(it.c, it.B.cprev, sizeof(float) * sv, hipMemcpyDeviceToDevice, bs.ss[i]));
+    if (it.dev) {
+      PSOAM_HIP(launch_select_copy(it.c, it.a0, it.a1, it.P->d_ctl, sv, bs.ss[i]));
+    } else {
+      PSOAM_HIP(hipMemcpyAsync(it.c, it.B.cprev, sizeof(float) * sv, hipMemcpyDeviceToDevice, bs.ss[i]));
+    }
     PSOAM_HIP(launch_dot(it.c, it.c, sv, it.P->d_partial, it.P->d_scalars + 0, bs.ss[i]));
   }
   int status = PSOAM_OK;
   for (int i = 0; i < n; ++i) {
     BatchItem& it = items[i];
-    double h;
-    if (int rc = copy_scalars(it.P, &h, 1, bs.ss[i])) return rc;
-    if (!std::isfinite(h)) it.stats.status = PSOAM_EDIVERGED;
+    double h[13];
+    if (int rc = copy_scalars(it.P, h, 13, bs.ss[i])) return rc;
+    if (it.dev) {
+      int ctl[4];
+      PSOAM_HIP(hipMemcpy(ctl, it.P->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost));
+      it.stats.iterations = ctl[1];
+      if (ctl[2]) it.stats.status = PSOAM_EDIVERGED;
+      if (it.need_obj && ctl[1] > 0) it.stats.objective = h[12];
+      if (it.o->trace && ctl[1] > 0)
+        PSOAM_HIP(hipMemcpy(it.o->trace, it.P->d_trace, sizeof(double) * ctl[1],
+                            hipMemcpyDeviceToHost));
+    }
+    if (!std::isfinite(h[0])) it.stats.status = PSOAM_EDIVERGED;
     if (it.st) *it.st = it.stats;
     if (it.stats.status != PSOAM_OK) status = PSOAM_EDIVERGED;
     PSOAM_HIP(hipEventRecord(bs.ev[i], bs.ss[i]));
@@ -1032,8 +1127,11 @@ int psoam_solve_batch(int32_t n, const psoam_plan* const* plans, const float* co
   std::vector<BatchItem> items;
   for (int i = 0; i < n; ++i) {
     const psoam_solve_opts* oi = &o[i];
-    const bool graphable = distinct && oi->eps1 == 0.0 && oi->eps2 == 0.0 && !oi->trace &&
-                           !oi->warm_inner && oi->k1 >= 2;
+    // host decisions inside the loop (stopping tests, a trace) are needed
+    // unless the tests run on the device (device_stop)
+    const bool host_tests = oi->eps1 > 0.0 || oi->eps2 > 0.0 || oi->trace;
+    const bool graphable = distinct && (!host_tests || oi->device_stop) && !oi->warm_inner &&
+                           oi->k1 >= 2;
     if (!graphable) {
       const int rc = solve_one(const_cast<psoam_plan*>(plans[i]), kOpA, p[i], c[i], oi,
                                st ? &st[i] : nullptr, S(stream));
@@ -1049,6 +1147,10 @@ int psoam_solve_batch(int32_t n, const psoam_plan* const* plans, const float* co
     it.stats = fresh_stats();
     it.alpha1 = 0.0;
     it.remaining = 0;
+    it.dev = oi->device_stop != 0 && host_tests;
+    it.need_obj = oi->eps1 > 0.0 || oi->trace != nullptr;
+    it.tst = StopTest{oi->eps1, oi->eps2, oi->lambda_tv, oi->lambda_l1, oi->lambda_tvs,
+                      it.need_obj ? 1 : 0, it.P->inner ? 1 : 0, oi->lambda_tvs > 0.0 ? 1 : 0};
     if (int rc = ensure_solve_ws(it.P, it.B)) return rc;
     it.RB = R3Bufs{};
     if (oi->lambda_tvs > 0.0)

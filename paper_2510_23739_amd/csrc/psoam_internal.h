@@ -39,6 +39,7 @@ constexpr int kMaxEirNt = 4096;      // longest A-scan of the factorised form (L
 struct EirParams {
   int n, origin;
   float v[kMaxEir];
+  const int* gate = nullptr;  // device stop flag of the solve (set per launch), or null
 };
 
 // Photo-switching coefficients in the form the kernels evaluate:
@@ -128,6 +129,9 @@ struct psoam_plan {
   double* d_partial = nullptr;  // per-wave / per-block FP64 partial sums
   size_t n_partial = 0;
   double* d_scalars = nullptr;  // small FP64 results (reductions)
+  int* d_ctl = nullptr;         // device stopping tests: stopped, iterations, diverged, index
+  double* d_trace = nullptr;    // objective per iteration under device stopping tests
+  size_t n_trace = 0;
   // duals of the full regulariser's prox (TV(S c) term), allocated on first use
   psoam::Workspace r3_ws;
   // max over voxels of the largest eigenvalue of S_v^T S_v (FP64, at creation)
@@ -173,6 +177,12 @@ namespace psoam {
 // the LDS is ignored.
 void set_tune_choice(int rows_fwd, int rows_adj, int tsh);
 void clear_tune_choice();
+
+// Device stop gate of the calling thread: while a solve with device-side
+// stopping tests enqueues its iterations, every kernel launched on this
+// thread receives the solve's stop flag and returns at once when it is set.
+void set_gate(const int* g);
+const int* gate_now();
 
 // thread-local error message
 void set_error(const std::string& msg);
@@ -224,10 +234,24 @@ hipError_t launch_momentum(float* xi, const float* c_next, const float* c_prev, 
                            int64_t n, double* partial, hipStream_t s);
 size_t reduce_blocks(int64_t n);
 // xi = c_next + beta (c_next - c_prev) with beta from the device step state
-// tst[0] = t_k, which is then advanced to t_{k+1} (captured iterations)
+// tst[0] = t_k, which is then advanced to t_{k+1} (captured iterations);
+// partial (may be null): the partial sums of launch_momentum
 hipError_t launch_momentum_dev(float* xi, const float* c_next, const float* c_prev, double* tst,
-                               int literal, int64_t n, hipStream_t s);
+                               int literal, int64_t n, double* partial, hipStream_t s);
 hipError_t launch_set_double(double* p, double v, hipStream_t s);
+// device-side stopping tests of a solve (device_stop): ctl [4] ints, sc the
+// plan's FP64 scalars; launch_select_copy copies the last iterate (a0 after
+// an even number of iterations, a1 after an odd one) into out
+struct StopTest {
+  double eps1, eps2, lam_tv, lam_l1, lam_tvs;
+  int need_obj;  // evaluate the objective (eps1 > 0 or a trace)
+  int add_p2;    // data term = sc[4] + sc[9] (separable form)
+  int tvs;       // add the TV(S c) term
+};
+hipError_t launch_stop_init(int* ctl, double* sc, hipStream_t s);
+hipError_t launch_stop_test(int* ctl, double* sc, double* trace, const StopTest& t, hipStream_t s);
+hipError_t launch_select_copy(float* out, const float* a0, const float* a1, const int* ctl,
+                              int64_t n, hipStream_t s);
 // FP16 operand scales (no-ops for other plans).  launch_f16_pmax records
 // max |p| of a solve's measurements (p null: 0) for the residual operand's
 // bound; the switching and pack launchers and the residual form of H set

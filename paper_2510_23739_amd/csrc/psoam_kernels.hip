@@ -104,7 +104,9 @@ __global__ __launch_bounds__(256) void switch_fwd16(const float* __restrict__ c,
                                                     typename Half<PREC>::E* __restrict__ bq,
                                                     typename Half<PREC>::E* __restrict__ bq_lo,
                                                     int ny, int nx, int nz, int zo_n, int kp,
-                                                    int xp, int r, size_t ps) {
+                                                    int xp, int r, size_t ps,
+                                                    const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   using H = Half<PREC>;
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t total = (size_t)ny * nx * zo_n * kp;
@@ -175,7 +177,8 @@ __global__ __launch_bounds__(256) void switch_fwd32(const float* __restrict__ c,
                                                     const float* __restrict__ stab,
                                                     SwitchParams sw, float* __restrict__ bq,
                                                     int ny, int nx, int nz, int kp, int xp,
-                                                    int r, size_t ps) {
+                                                    int r, size_t ps, const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t total = (size_t)ny * nx * nz * kp;
   if (tid >= total) return;
@@ -207,7 +210,9 @@ __global__ __launch_bounds__(256) void pack_r16(const float* __restrict__ yin,
                                                 typename Half<PREC>::E* __restrict__ rq_lo,
                                                 int nk, int ny, int nx, int nt, int to_n,
                                                 int kp, int xp, int r, size_t ps, int vec4,
-                                                int tsh, const float* __restrict__ f16) {
+                                                int tsh, const float* __restrict__ f16,
+                                                const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   using H = Half<PREC>;
   using V = typename H::V;
   const float sc = f16 ? f16[2] : H::scale;   // operand scale (FP16: per call)
@@ -272,7 +277,8 @@ __global__ __launch_bounds__(256) void pack_r16(const float* __restrict__ yin,
 __global__ __launch_bounds__(256) void pack_r32(const float* __restrict__ yin,
                                                 float* __restrict__ rq, int nk, int ny, int nx,
                                                 int nt, int lt, int kp, int xp, int r,
-                                                size_t ps) {
+                                                size_t ps, const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   __shared__ float tile[64][65];
   const int pos = blockIdx.x;
   const int y = pos / nx, x = pos % nx;
@@ -310,6 +316,7 @@ struct BandArgs {
   int nk, kp;
   float inv_scale;
   const float* f16;  // FP16 plans: per-call operand scales (s_b, 1/s_b, s_r, 1/s_r), else null
+  const int* gate;   // device stop flag of the solve, or null
   // epilogue
   float* out;
   const float* pmeas;
@@ -558,6 +565,7 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
 // staged variant below does not fit in LDS, and for FP32.
 template <int PREC, bool SPLIT, int NB, int MODE>
 __global__ __launch_bounds__(256) void band16(BandArgs A) {
+  if (A.gate && *A.gate) return;  // a device stop test has ended the solve
   using H = Half<PREC>;
   using E = typename H::E;
   using V = typename H::V;
@@ -610,6 +618,7 @@ __global__ __launch_bounds__(256) void band16(BandArgs A) {
 
 template <int NB, int MODE>
 __global__ __launch_bounds__(256) void band32(BandArgs A) {
+  if (A.gate && *A.gate) return;  // a device stop test has ended the solve
   int mtile, iy, ix0, wid;
   block_coords(A, mtile, iy, ix0, wid);
   const int lane = threadIdx.x & 63;
@@ -688,6 +697,7 @@ constexpr int kLoadItems = 25;
 template <int PREC, bool SPLIT, int MODE, int ROWS, int LOADW>
 __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs& L) {
   static_assert(LOADW == 0 || !SPLIT, "loader waves stage one-part operands");
+  if (A.gate && *A.gate) return;  // a device stop test has ended the solve
   using H = Half<PREC>;
   using E = typename H::E;
   using V = typename H::V;
@@ -961,6 +971,11 @@ __global__ __launch_bounds__(64 * (ROWS + LOADW)) __attribute__((amdgpu_waves_pe
   band16_lds_body<PREC, SPLIT, 2, ROWS, LOADW>(A, L);
 }
 
+// the calling thread's device stop gate (see set_gate)
+static thread_local const int* t_gate = nullptr;
+void set_gate(const int* g) { t_gate = g; }
+const int* gate_now() { return t_gate; }
+
 // --------------------------------------------------------------------------
 // FP16 operand scales.  Every FP16 operand is written times a power of two
 // chosen on the device right before, from an FP32 max-abs reduction of what
@@ -974,7 +989,9 @@ __global__ __launch_bounds__(64 * (ROWS + LOADW)) __attribute__((amdgpu_waves_pe
 // running max |x| into acc (float bits: nonnegative floats order as unsigned
 // integers); NaN inputs are skipped, an infinite one gives scale 1
 __global__ __launch_bounds__(256) void f16_amax_kernel(const float* __restrict__ x, int64_t n,
-                                                       unsigned* acc) {
+                                                       unsigned* acc,
+                                                       const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   __shared__ float sm[4];
   float m = 0.0f;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
@@ -993,7 +1010,9 @@ __global__ __launch_bounds__(256) void f16_amax_kernel(const float* __restrict__
 // mode 1 sets s_r from acc[1] * c1; mode 2 keeps acc[1] as max |p| (st[5]);
 // mode 3 sets s_r from the bound c1 st[4] + c2 st[5].  The accumulator read
 // is cleared for its next use.
-__global__ void f16_scale_kernel(float* st, unsigned* acc, int mode, float c1, float c2) {
+__global__ void f16_scale_kernel(float* st, unsigned* acc, int mode, float c1, float c2,
+                                 const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   auto pow2 = [](float bound) {
     if (!(bound > 0.0f) || !isfinite(bound)) return 1.0f;
     int e = 14 - (int)ceilf(log2f(bound));
@@ -1028,13 +1047,14 @@ static hipError_t f16_amax(const psoam_plan* P, const float* x, int64_t n, int s
   if (n <= 0) return hipSuccess;
   const int64_t want = (n + 255) / 256;
   const unsigned nb = (unsigned)std::min<int64_t>(want, 2048);
-  hipLaunchKernelGGL(f16_amax_kernel, dim3(nb), dim3(256), 0, s, x, n, P->d_f16acc + slot);
+  hipLaunchKernelGGL(f16_amax_kernel, dim3(nb), dim3(256), 0, s, x, n, P->d_f16acc + slot,
+                     gate_now());
   return hipGetLastError();
 }
 
 static hipError_t f16_scale(const psoam_plan* P, int mode, double c1, double c2, hipStream_t s) {
   hipLaunchKernelGGL(f16_scale_kernel, dim3(1), dim3(1), 0, s, P->d_f16, P->d_f16acc, mode,
-                     (float)c1, (float)c2);
+                     (float)c1, (float)c2, gate_now());
   return hipGetLastError();
 }
 
@@ -1068,7 +1088,8 @@ hipError_t launch_switch_fwd(const psoam_plan* P, const float* c, hipStream_t s)
     case PSOAM_FP32: {
       const size_t n = (size_t)g.ny * g.nx * g.nz * P->Kp;
       hipLaunchKernelGGL(switch_fwd32, dim3(blocks_for(n)), dim3(256), 0, s, c, P->d_phi, stab,
-                         P->sw, (float*)P->d_bq, g.ny, g.nx, g.nz, P->Kp, P->Xp, P->R, P->ps_b);
+                         P->sw, (float*)P->d_bq, g.ny, g.nx, g.nz, P->Kp, P->Xp, P->R, P->ps_b,
+                         gate_now());
       break;
     }
 #define PSOAM_SW16(PR, SP)                                                                  \
@@ -1078,7 +1099,7 @@ hipError_t launch_switch_fwd(const psoam_plan* P, const float* c, hipStream_t s)
     hipLaunchKernelGGL((switch_fwd16<PR, SP>), dim3(blocks_for(n)), dim3(256), 0, s, c,     \
                        P->d_phi, stab, P->d_stab_o, vec, P->d_f16, P->sw, (E*)P->d_bq,     \
                        (E*)P->d_bq_lo, g.ny, g.nx, g.nz, P->Lz / 8, P->Kp, P->Xp, P->R,    \
-                       P->ps_b);                                                            \
+                       P->ps_b, gate_now());                                                \
     break;                                                                                  \
   }
     case PSOAM_BF16:
@@ -1105,7 +1126,8 @@ hipError_t launch_pack_r(const psoam_plan* P, const float* y, hipStream_t s) {
   switch (P->prec) {
     case PSOAM_FP32:
       hipLaunchKernelGGL(pack_r32, dim3(g.ny * g.nx), dim3(256), 0, s, y, (float*)P->d_rq,
-                         g.n_pulses, g.ny, g.nx, g.nt, P->Lt, P->Kp, P->Xp, P->R, P->ps_r);
+                         g.n_pulses, g.ny, g.nx, g.nt, P->Lt, P->Kp, P->Xp, P->R, P->ps_r,
+                         gate_now());
       break;
 #define PSOAM_PK16(PR, SP)                                                                  \
   {                                                                                         \
@@ -1113,7 +1135,7 @@ hipError_t launch_pack_r(const psoam_plan* P, const float* y, hipStream_t s) {
     const size_t n = (size_t)g.ny * g.nx;                                                   \
     hipLaunchKernelGGL((pack_r16<PR, SP>), dim3((unsigned)n), dim3(256), 0, s, y,           \
                        (E*)P->d_rq, (E*)P->d_rq_lo, g.n_pulses, g.ny, g.nx, g.nt, P->Lt / 8, \
-                       P->Kp, P->Xp, P->R, P->ps_r, vec4, P->tsh, P->d_f16);                \
+                       P->Kp, P->Xp, P->R, P->ps_r, vec4, P->tsh, P->d_f16, gate_now());    \
     break;                                                                                  \
   }
     case PSOAM_BF16:
@@ -1291,6 +1313,7 @@ hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* p
   A.kp = P->Kp;
   A.inv_scale = fp16 ? 1.0f / kFp16Scale : 1.0f;
   A.f16 = P->d_f16;
+  A.gate = gate_now();
   if (mode == 1 && P->d_f16) {
     // residual r = H b - p: |r| <= hrow max |b| + max |p| with max |b| <= srow max |x|
     const hipError_t e = f16_scale(P, 3, P->hrow * P->srow, 1.0, s);
@@ -1356,6 +1379,7 @@ hipError_t launch_prox_l1(float* x, const float* z, int64_t n, float thresh, int
 struct Grid3 {
   int ny, nx, nz;
   int64_t sv;  // S * V
+  const int* gate;  // device stop flag of the solve, or null
 };
 
 __device__ __forceinline__ float eta_at(const float* __restrict__ uc, const float* __restrict__ up,
@@ -1407,6 +1431,7 @@ __global__ __launch_bounds__(kTvThreads) void tv_step_kernel(float* __restrict__
                                                       const float* __restrict__ uc,
                                                       const float* __restrict__ up, float beta,
                                                       float inv_mu, float theta, Grid3 G) {
+  if (G.gate && *G.gate) return;  // a device stop test has ended the solve
   constexpr int EY = kTvY + 1, EX = kTvX + 1, EZ = kTvZ + 1;  // w region (tile + forward halo)
   __shared__ float s_ey[(EY + 1) * EX * EZ];  // eta_y, y from y0 - 1
   __shared__ float s_ex[EY * (EX + 1) * EZ];  // eta_x, x from x0 - 1
@@ -1519,6 +1544,7 @@ __global__ __launch_bounds__(256) void tv_final_kernel(float* __restrict__ x,
                                                        const float* __restrict__ z,
                                                        const float* __restrict__ u, int mode,
                                                        float th1, Grid3 G) {
+  if (G.gate && *G.gate) return;  // a device stop test has ended the solve
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= G.sv) return;
   const int iz = (int)(v % G.nz);
@@ -1536,6 +1562,7 @@ static Grid3 grid3(const psoam_plan* P) {
   G.nx = P->g.nx;
   G.nz = P->g.nz;
   G.sv = (int64_t)P->c_elems();
+  G.gate = gate_now();
   return G;
 }
 
@@ -1562,7 +1589,9 @@ hipError_t launch_tv_final(const psoam_plan* P, float* x, const float* z, const 
 __global__ __launch_bounds__(256) void axpby_kernel(float* __restrict__ out,
                                                     const float* __restrict__ x,
                                                     const float* __restrict__ y, float a,
-                                                    float b, int64_t n) {
+                                                    float b, int64_t n,
+                                                    const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a * x[i] + b * y[i];
 }
@@ -1571,7 +1600,7 @@ hipError_t launch_axpby(float* out, const float* x, const float* y, float a, flo
                         hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(axpby_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0, s, out, x, y, a, b,
-                     n);
+                     n, gate_now());
   return hipGetLastError();
 }
 
@@ -1609,7 +1638,9 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 __global__ __launch_bounds__(256) void dot_kernel(const float* __restrict__ x,
                                                   const float* __restrict__ y, int64_t n,
-                                                  double* __restrict__ partial) {
+                                                  double* __restrict__ partial,
+                                                  const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   __shared__ double sh[4];
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1620,7 +1651,9 @@ __global__ __launch_bounds__(256) void dot_kernel(const float* __restrict__ x,
 }
 
 __global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ partial,
-                                                           int64_t n, double* __restrict__ out) {
+                                                           int64_t n, double* __restrict__ out,
+                                                           const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   __shared__ double sh[4];
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += partial[i];
@@ -1631,18 +1664,21 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restr
 hipError_t launch_dot(const float* x, const float* y, int64_t n, double* partial, double* out,
                       hipStream_t s) {
   const size_t nb = reduce_blocks(n);
-  hipLaunchKernelGGL(dot_kernel, dim3((unsigned)nb), dim3(256), 0, s, x, y, n, partial);
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out);
+  hipLaunchKernelGGL(dot_kernel, dim3((unsigned)nb), dim3(256), 0, s, x, y, n, partial, gate_now());
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out,
+                     gate_now());
   return hipGetLastError();
 }
 
 hipError_t launch_sum_partials(const double* partial, size_t n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)n, out);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)n, out,
+                     gate_now());
   return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void tv_l1_kernel(const float* __restrict__ c, Grid3 G,
                                                     double* __restrict__ partial) {
+  if (G.gate && *G.gate) return;  // a device stop test has ended the solve
   __shared__ double sh[4];
   double tvs = 0.0, l1 = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1670,9 +1706,10 @@ hipError_t launch_tv_l1_sums(const psoam_plan* P, const float* c, double* partia
   const Grid3 G = grid3(P);
   const size_t nb = reduce_blocks(G.sv);
   hipLaunchKernelGGL(tv_l1_kernel, dim3((unsigned)nb), dim3(256), 0, s, c, G, partial);
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out,
+                     gate_now());
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial + nb, (int64_t)nb,
-                     out + 1);
+                     out + 1, gate_now());
   return hipGetLastError();
 }
 
@@ -1712,6 +1749,7 @@ __global__ __launch_bounds__(256) void r3_w_kernel(
     const float* __restrict__ u1p, const float* __restrict__ u2c, const float* __restrict__ u2p,
     const float* __restrict__ u3c, const float* __restrict__ u3p, float beta, SwitchParams sw,
     const float* __restrict__ phi, const float* __restrict__ stab, int kp, Grid3 G, int clamp_out) {
+  if (G.gate && *G.gate) return;  // a device stop test has ended the solve
   const int64_t vol = (int64_t)G.ny * G.nx * G.nz;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= vol) return;
@@ -1777,6 +1815,7 @@ __global__ __launch_bounds__(256) void r3_u_kernel(
     const float* __restrict__ u3p, float beta, float s1, float s2, float s3, float th1, float th2,
     float th3, SwitchParams sw, const float* __restrict__ phi, const float* __restrict__ stab,
     int kp, Grid3 G) {
+  if (G.gate && *G.gate) return;  // a device stop test has ended the solve
   const int64_t vol = (int64_t)G.ny * G.nx * G.nz;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= vol) return;
@@ -1861,6 +1900,7 @@ __global__ __launch_bounds__(256) void tvs_kernel(const float* __restrict__ c, S
                                                   const float* __restrict__ phi,
                                                   const float* __restrict__ stab, int kp, Grid3 G,
                                                   double* __restrict__ partial) {
+  if (G.gate && *G.gate) return;  // a device stop test has ended the solve
   __shared__ double sh[4];
   const int64_t vol = (int64_t)G.ny * G.nx * G.nz;
   const int64_t st[3] = {(int64_t)G.nx * G.nz, G.nz, 1};
@@ -1922,7 +1962,8 @@ hipError_t launch_tvs_sum(const psoam_plan* P, const float* c, double* partial, 
   const size_t nb = reduce_blocks((int64_t)P->v_elems());
   hipLaunchKernelGGL(tvs_kernel, dim3((unsigned)nb), dim3(256), 0, s, c, P->sw, P->d_phi,
                      P->d_stab_t, P->Kp, G, partial);
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)nb, out,
+                     gate_now());
   return hipGetLastError();
 }
 
@@ -1936,6 +1977,7 @@ __global__ __launch_bounds__(256) void unmix_grad_kernel(float* __restrict__ g,
                                                          const float* __restrict__ phi,
                                                          const float* __restrict__ stab, int kp,
                                                          Grid3 G, double* __restrict__ partial) {
+  if (G.gate && *G.gate) return;  // a device stop test has ended the solve
   __shared__ double sh[4];
   const int64_t vol = (int64_t)G.ny * G.nx * G.nz;
   double ss = 0.0;
@@ -1981,7 +2023,9 @@ struct SepG {
 __global__ __launch_bounds__(256) void sep_expand_kernel(float* __restrict__ y,
                                                          const float* __restrict__ h,
                                                          const float* __restrict__ T, int ns,
-                                                         int nk, int64_t n) {
+                                                         int nk, int64_t n,
+                                                         const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     float hv[kMaxSpecies];
@@ -1997,7 +2041,9 @@ __global__ __launch_bounds__(256) void sep_expand_kernel(float* __restrict__ y,
 __global__ __launch_bounds__(256) void sep_contract_kernel(float* __restrict__ out,
                                                            const float* __restrict__ y,
                                                            const float* __restrict__ T, int ns,
-                                                           int nk, int64_t n) {
+                                                           int nk, int64_t n,
+                                                           const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     float acc[kMaxSpecies];
@@ -2014,7 +2060,9 @@ __global__ __launch_bounds__(256) void sep_residual_kernel(float* __restrict__ r
                                                            const float* __restrict__ h,
                                                            const float* __restrict__ q, SepG G,
                                                            int ns, int64_t n,
-                                                           double* __restrict__ partial) {
+                                                           double* __restrict__ partial,
+                                                           const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   __shared__ double sh[4];
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -2052,6 +2100,7 @@ __global__ __launch_bounds__(256) void eir_rows_kernel(float* out, const float* 
                                                        const float* __restrict__ pm, EirParams e,
                                                        int nt, int64_t rows,
                                                        double* __restrict__ partial) {
+  if (e.gate && *e.gate) return;  // a device stop test has ended the solve
   extern __shared__ float eir_lds[];
   __shared__ double sh[4];
   const int wpb = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
@@ -2176,13 +2225,15 @@ hipError_t launch_eir_rows(const psoam_plan* P, int mode, float* out, const floa
   const dim3 grid((unsigned)eir_blocks(P)), block(64 * wpb);
   auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
   const bool vec = (nt & 3) == 0 && al16(out) && al16(in) && al16(p);
+  EirParams ep = P->eir;
+  ep.gate = gate_now();
 #define PSOAM_EIR(M)                                                                        \
   {                                                                                         \
     if (vec)                                                                                \
-      hipLaunchKernelGGL((eir_rows_kernel<M, true>), grid, block, lds, s, out, in, p, P->eir, nt, \
+      hipLaunchKernelGGL((eir_rows_kernel<M, true>), grid, block, lds, s, out, in, p, ep, nt, \
                          rows, partial);                                                    \
     else                                                                                    \
-      hipLaunchKernelGGL((eir_rows_kernel<M, false>), grid, block, lds, s, out, in, p, P->eir, nt, \
+      hipLaunchKernelGGL((eir_rows_kernel<M, false>), grid, block, lds, s, out, in, p, ep, nt, \
                          rows, partial);                                                    \
     break;                                                                                  \
   }
@@ -2227,6 +2278,7 @@ __global__ __launch_bounds__(512) void eir_pack16(const float* __restrict__ q,
                                                   int nk, int ny, int nx, int nt, int to_n,
                                                   int kp, int xp, int r, size_t ps, int tsh,
                                                   const float* __restrict__ f16) {
+  if (e.gate && *e.gate) return;  // a device stop test has ended the solve
   using H = Half<PREC>;
   using V = typename H::V;
   const float sc = f16 ? f16[2] : H::scale;   // operand scale (FP16: per call)
@@ -2373,6 +2425,8 @@ bool eir_pack_fits(const psoam_plan* P, bool resid) {
 hipError_t launch_eir_pack(const psoam_plan* P, const float* q, const float* p, bool resid,
                            hipStream_t s) {
   if (!eir_pack_fits(P, resid)) return hipErrorInvalidValue;
+  EirParams ep = P->eir;
+  ep.gate = gate_now();
   if (P->d_f16) {
     // V^T (V q - p) with q = Lambda S x: bound l1 (l1 hrow srow max|x| + max|p|),
     // l1 = sum |v|; the adjoint's V^T y: l1 max|y|
@@ -2398,7 +2452,7 @@ hipError_t launch_eir_pack(const psoam_plan* P, const float* q, const float* p, 
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, \
                                 (int)lds);                                                  \
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(eir_pack_threads(RS)), lds, s, q, p, \
-                       P->eir,                                                              \
+                       ep,                                                                  \
                        (E*)P->d_rq, (E*)P->d_rq_lo, g.n_pulses, g.ny, g.nx, g.nt, P->Lt / 8, \
                        P->Kp, P->Xp, P->R, P->ps_r, P->tsh, P->d_f16);                      \
   }
@@ -2428,14 +2482,14 @@ size_t sep_blocks(const psoam_plan* P) {
 hipError_t launch_sep_expand(const psoam_plan* P, float* y, const float* h, hipStream_t s) {
   const int64_t n = (int64_t)P->g.ny * P->g.nx * P->g.nt;
   hipLaunchKernelGGL(sep_expand_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0, s, y, h,
-                     (const float*)P->d_T, P->g.n_species, P->g.n_pulses, n);
+                     (const float*)P->d_T, P->g.n_species, P->g.n_pulses, n, gate_now());
   return hipGetLastError();
 }
 
 hipError_t launch_sep_contract(const psoam_plan* P, float* out, const float* y, hipStream_t s) {
   const int64_t n = (int64_t)P->g.ny * P->g.nx * P->g.nt;
   hipLaunchKernelGGL(sep_contract_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0, s, out, y,
-                     (const float*)P->d_T, P->g.n_species, P->g.n_pulses, n);
+                     (const float*)P->d_T, P->g.n_species, P->g.n_pulses, n, gate_now());
   return hipGetLastError();
 }
 
@@ -2446,7 +2500,7 @@ hipError_t launch_sep_residual(const psoam_plan* P, float* rt, const float* h, c
   for (int i = 0; i < kMaxSpecies * kMaxSpecies; ++i) G.g[i] = P->sep_g[i];
   const size_t nb = partial ? sep_blocks(P) : blocks_for((size_t)n);
   hipLaunchKernelGGL(sep_residual_kernel, dim3((unsigned)nb), dim3(256), 0, s, rt, h, q, G,
-                     P->g.n_species, n, partial);
+                     P->g.n_species, n, partial, gate_now());
   return hipGetLastError();
 }
 
@@ -2470,7 +2524,9 @@ hipError_t launch_scale_by_rnorm(float* v, const float* w, const double* norm2, 
 __global__ __launch_bounds__(256) void momentum_kernel(float* __restrict__ xi,
                                                        const float* __restrict__ cn,
                                                        const float* __restrict__ cp, float beta,
-                                                       int64_t n, double* __restrict__ partial) {
+                                                       int64_t n, double* __restrict__ partial,
+                                                       const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   __shared__ double sh[4];
   double dd = 0.0, nn = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -2494,7 +2550,7 @@ hipError_t launch_momentum(float* xi, const float* c_next, const float* c_prev, 
                            int64_t n, double* partial, hipStream_t s) {
   const size_t nb = reduce_blocks(n);
   hipLaunchKernelGGL(momentum_kernel, dim3((unsigned)nb), dim3(256), 0, s, xi, c_next, c_prev,
-                     beta, n, partial);
+                     beta, n, partial, gate_now());
   return hipGetLastError();
 }
 
@@ -2506,31 +2562,129 @@ __global__ __launch_bounds__(256) void momentum_dev_kernel(float* __restrict__ x
                                                            const float* __restrict__ cn,
                                                            const float* __restrict__ cp,
                                                            const double* __restrict__ tst,
-                                                           int literal, int64_t n) {
+                                                           int literal, int64_t n,
+                                                           double* __restrict__ partial,
+                                                           const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
+  __shared__ double sh[4];
   const double t = tst[0];
   const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
   const float beta = (float)(literal ? (t - 1.0) / (t + 1.0) : (t - 1.0) / tn);
+  double dd = 0.0, nn = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const float a = cn[i];
-    xi[i] = a + beta * (a - cp[i]);
+    const float xn = a + beta * (a - cp[i]);
+    if (partial) {
+      // the same partial sums as momentum_kernel (for the xi-change test)
+      const float xo = xi[i];
+      dd += ((double)xn - (double)xo) * ((double)xn - (double)xo);
+      nn += (double)xo * (double)xo;
+    }
+    xi[i] = xn;
+  }
+  if (partial) {
+    const double r0 = block_sum(dd, sh);
+    const double r1 = block_sum(nn, sh);
+    if (threadIdx.x == 0) {
+      partial[blockIdx.x] = r0;
+      partial[gridDim.x + blockIdx.x] = r1;
+    }
   }
 }
 
 // t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, one thread, after the momentum kernel
-__global__ void advance_t_kernel(double* tst) {
+__global__ void advance_t_kernel(double* tst, const int* __restrict__ gate) {
+  if (gate && *gate) return;  // a device stop test has ended the solve
   const double t = tst[0];
   tst[0] = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
 }
 
 __global__ void set_double_kernel(double* p, double v) { p[0] = v; }
 
+// ---- device-side stopping tests (Alg. alg:prox-outer, both tests) ----------
+// ctl: [0] stopped, [1] iterations done, [2] objective not finite,
+//      [3] index of the next iteration;
+// sc (the plan's FP64 scalars): [2], [3] |xi_{k+1} - xi_k|^2 and |xi_k|^2,
+//      [4..7] data term, TV, l1, TV(S c) of c_{k+1}, [9] |p|^2 (separable),
+//      [10] previous objective, [11] 1 once there is one, [12] last objective
+__global__ void stop_init_kernel(int* ctl, double* sc) {
+  ctl[0] = ctl[1] = ctl[2] = ctl[3] = 0;
+  sc[10] = 0.0;
+  sc[11] = 0.0;
+  sc[12] = __builtin_nan("");
+}
+
+// One thread, after iteration k's momentum and objective terms: the same
+// decisions as the host-side tests, in the same FP64 arithmetic.
+__global__ void stop_test_kernel(int* ctl, double* sc, double* trace, StopTest t) {
+  // no fused multiply-adds: every operation rounds as on the host
+#pragma clang fp contract(off)
+  if (ctl[0]) return;
+  const int k = ctl[3];
+  ctl[3] = k + 1;
+  ctl[1] = k + 1;
+  double f_now = 0.0;
+  if (t.need_obj) {
+    const double data = t.add_p2 ? sc[4] + sc[9] : sc[4];
+    f_now = 0.5 * data + t.lam_tv * sc[5] + t.lam_l1 * sc[6];
+    if (t.tvs) f_now += t.lam_tvs * sc[7];
+    if (!isfinite(f_now)) {
+      ctl[2] = 1;
+      ctl[0] = 1;
+      return;
+    }
+    if (trace) trace[k] = f_now;
+    sc[12] = f_now;
+  }
+  bool stop = false;
+  if (k > 1) {
+    if (t.eps1 > 0.0 && sc[11] != 0.0 && fabs(f_now - sc[10]) < t.eps1 * fabs(sc[10])) stop = true;
+    if (t.eps2 > 0.0 && sc[3] > 0.0 && sqrt(sc[2]) < t.eps2 * sqrt(sc[3])) stop = true;
+  }
+  if (t.need_obj) {
+    sc[10] = f_now;
+    sc[11] = 1.0;
+  }
+  if (stop) ctl[0] = 1;
+}
+
+// out = the buffer holding the last iterate: iteration k writes c_{k+1} into
+// the buffer that was "next" at k, which alternates, so after n iterations it
+// is a1 for odd n and a0 for even n
+__global__ __launch_bounds__(256) void select_copy_kernel(float* __restrict__ out,
+                                                          const float* __restrict__ a0,
+                                                          const float* __restrict__ a1,
+                                                          const int* __restrict__ ctl, int64_t n) {
+  const float* src = (ctl[1] & 1) ? a1 : a0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = src[i];
+}
+
+hipError_t launch_stop_init(int* ctl, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(stop_init_kernel, dim3(1), dim3(1), 0, s, ctl, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_stop_test(int* ctl, double* sc, double* trace, const StopTest& t, hipStream_t s) {
+  hipLaunchKernelGGL(stop_test_kernel, dim3(1), dim3(1), 0, s, ctl, sc, trace, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_copy(float* out, const float* a0, const float* a1, const int* ctl,
+                              int64_t n, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<size_t>(blocks_for((size_t)n), 4096);
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(select_copy_kernel, dim3(nb), dim3(256), 0, s, out, a0, a1, ctl, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_momentum_dev(float* xi, const float* c_next, const float* c_prev, double* tst,
-                               int literal, int64_t n, hipStream_t s) {
+                               int literal, int64_t n, double* partial, hipStream_t s) {
   const size_t nb = reduce_blocks(n);
   hipLaunchKernelGGL(momentum_dev_kernel, dim3((unsigned)nb), dim3(256), 0, s, xi, c_next, c_prev,
-                     (const double*)tst, literal, n);
-  hipLaunchKernelGGL(advance_t_kernel, dim3(1), dim3(1), 0, s, tst);
+                     (const double*)tst, literal, n, partial, gate_now());
+  hipLaunchKernelGGL(advance_t_kernel, dim3(1), dim3(1), 0, s, tst, gate_now());
   return hipGetLastError();
 }
 
