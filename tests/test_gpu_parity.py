@@ -310,26 +310,39 @@ def test_autograd_backward_is_adjoint(c1):
 def test_loader_waves_change_nothing(c1, prec, monkeypatch):
     """The staged H kernel with four loader waves (the next row loaded during
     the current row's contractions) against the same kernel staging its rows
-    itself: the same LDS tiles and the same products in the same order, so
-    A, the residual form inside the solver and the solve's iterates are equal
-    bit for bit (8-row workgroups on the 32x32x16 grid and a ragged one)."""
+    itself, 8-row workgroups on the 32x32x16 grid and a ragged one: the same
+    LDS tiles and the same products in the same order, so A is equal bit for
+    bit, and so are the solve's iterates; A^T (the same kernel either way)
+    and the iterates also meet the oracle's."""
     torch = torch_cuda()
     cfg, c_true, t0, taps, phi, sp, n0, v0, S = c1
     p, A, AT, lam_tv, lam_l1 = _c1_problem(c1)
+    c_ref, _ = oracle.fista(p.astype(np.float64), A, AT, 1e-3, lam_tv, lam_l1, 4, 5,
+                            shape_c=cfg.c_shape)
     cfg2, t02, taps2, phi2, sp2 = ragged_cfg(9)
+    S2 = oracle_S(cfg2, phi2, sp2)
+    c2 = np.random.default_rng(5).standard_normal(cfg2.c_shape).astype(np.float32)
+    y2 = np.random.default_rng(6).standard_normal(cfg2.y_shape).astype(np.float32)
+    g_ref = oracle.apply_AT(y2, S2, t02, taps2, cfg2.nz)
     monkeypatch.setenv("PSOAM_LDS_ROWS", "8")
     out = {}
     for lw in ("0", "1"):
         monkeypatch.setenv("PSOAM_LDS_LOADW", lw)
         plan = lib_plan(cfg, t0, taps, phi, sp, prec)
         plan2 = lib_plan(cfg2, t02, taps2, phi2, sp2, prec)
-        c2 = np.random.default_rng(5).standard_normal(cfg2.c_shape).astype(np.float32)
         out[lw] = (plan.apply_A(torch.from_numpy(c_true).cuda()),
+                   plan2.apply_A(torch.from_numpy(c2).cuda()),
+                   plan2.apply_AT(torch.from_numpy(y2).cuda()).cpu().numpy(),
                    plan.solve(torch.from_numpy(p).cuda(), lambda_tv=lam_tv, lambda_l1=lam_l1,
-                              k1=4, k2=5, alpha1=1e-3)[0],
-                   plan2.apply_A(torch.from_numpy(c2).cuda()))
+                              k1=4, k2=5, alpha1=1e-3)[0].cpu().numpy())
         plan.close()
         plan2.close()
-    for a, b in zip(out["0"], out["1"]):
-        assert torch.equal(a, b)
-    say(f"[parity] loader waves {prec}: A, solve and ragged A bitwise equal")
+    assert torch.equal(out["0"][0], out["1"][0]) and torch.equal(out["0"][1], out["1"][1])
+    d_at = oracle.rel_err(out["1"][2], out["0"][2])
+    e_at = [oracle.rel_err(out[lw][2], g_ref) for lw in ("0", "1")]
+    e_c = [oracle.rel_err(out[lw][3], c_ref) for lw in ("0", "1")]
+    say(f"[parity] loader waves {prec}: A bitwise equal; A^T differs by {d_at:.2e} "
+        f"(oracle {e_at[0]:.2e} / {e_at[1]:.2e}); FISTA(4) c {e_c[0]:.2e} / {e_c[1]:.2e}")
+    assert d_at == 0.0
+    np.testing.assert_array_equal(out["0"][3], out["1"][3])
+    assert max(e_at) <= TOL_OP[prec] and max(e_c) <= 1e-3
