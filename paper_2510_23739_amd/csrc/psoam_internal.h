@@ -87,6 +87,9 @@ struct BandTable {
   int max_runs = 0;            // most runs of one output tile (LDS run table)
   int* d_rinfo = nullptr;      // [n_runs * 2] run length, first chunk
   int loadw = 0;               // > 0: loader waves beside the contracting ones (staged H)
+  // 1: the last 16-pulse block holds at most 8 pulses and the staged kernel
+  // runs it as 8 pulses x pairs of positions (half the products and staging)
+  int half = 0;
 };
 
 // LDS bytes of the staged kernel's per-tile tables: row windows (F + rows - 1),

@@ -314,6 +314,7 @@ struct BandArgs {
   int n_mtiles, n_mblk, ny, nx, nxb, m_rows, xp;
   size_t ps;
   int nk, kp;
+  int half;          // staged kernels: the last 16-pulse block runs in half form
   float inv_scale;
   const float* f16;  // FP16 plans: per-call operand scales (s_b, 1/s_b, s_r, 1/s_r), else null
   const int* gate;   // device stop flag of the solve, or null
@@ -380,13 +381,20 @@ __device__ __forceinline__ double wave_sum(double v) {
 //  mode 0: y rows written;  mode 1: r = y - p into the H^T operand, sum r^2
 //  into ss;  mode 2: c[s] (+)= sum_k S[k][s] bh[k] (first block writes, later
 //  blocks add, always by the same lane, so the order is fixed).
-template <int MODE, int NP, int RQ_PREC, bool SPLIT>
+// HALF (a block of at most 8 pulses, staged kernels): accumulator q holds
+// the pair of positions 2q, 2q+1, column l%16 = pulse kbase + l%8 of
+// position 2q + (l%16)/8; accumulators NP/2.. are unused.
+template <int MODE, int NP, int RQ_PREC, bool SPLIT, bool HALF = false>
 __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[NP], int mtile,
                                           int iy, int ix0, int kbase, bool first, double& ss) {
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, n = lane & 15;
   const int row0 = mtile * 16 + 4 * g;
-  const int k = kbase + n;
+  const int k = kbase + (HALF ? (n & 7) : n);
+  // accumulator slots and the position of slot p (relative to ix0)
+  constexpr int SL = HALF ? NP / 2 : NP;
+  const int hsel = HALF ? (n >> 3) : 0;
+  auto px = [&](int p) { return HALF ? 2 * p + hsel : p; };
   // undoing the operand's scale: 1/s_b after H, 1/s_r after H^T (FP16 plans
   // take both from the device, chosen per call; the others use inv_scale)
   const float ib = A.f16 ? A.f16[MODE == 2 ? 3 : 1] : A.inv_scale;
@@ -394,8 +402,8 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
     const int nt = A.nt;
     if (k >= A.nk) return;
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int ix = ix0 + p;
+    for (int p = 0; p < SL; ++p) {
+      const int ix = ix0 + px(p);
       if (ix >= A.nx) continue;
       float* yo = A.out + (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
       const f32x4 v = acc[p] * ib;
@@ -417,11 +425,11 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
     // occupancy would drop) and loads them position by position.
     constexpr bool kPre = RQ_PREC != PSOAM_FP32;
     const bool vec = A.pmeas && ((uintptr_t)A.pmeas & 15) == 0 && (nt & 3) == 0 && row0 + 3 < nt;
-    f32x4 pv[kPre ? NP : 1];
+    f32x4 pv[kPre ? SL : 1];
     if constexpr (kPre) {
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int ix = ix0 + p;
+      for (int p = 0; p < SL; ++p) {
+        const int ix = ix0 + px(p);
         const size_t yi = (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
         if (vec && ix < A.nx) {
           pv[p] = *(const f32x4*)(A.pmeas + yi);
@@ -433,8 +441,8 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
       }
     }
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int ix = ix0 + p;
+    for (int p = 0; p < SL; ++p) {
+      const int ix = ix0 + px(p);
       if (ix >= A.nx) continue;
       const size_t pos = ((size_t)(iy + A.r) * A.xp + (ix + A.r)) * A.ps_r;
       const size_t yi = (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
@@ -474,6 +482,7 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
     // lane keeps, so lane n ends with position n >> (4 - log2 NP) (the low
     // lanes of a pair add once more when NP < 16) and writes its own column.
     static_assert(NP == 8 || NP == 16, "positions per wave");
+    static_assert(!HALF || NP == 16, "half blocks: 16 positions per wave");
     constexpr int kSh = NP == 16 ? 0 : 1;
     const int nz = A.nz;
     if (A.sw.diag) {
@@ -482,8 +491,8 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
       // disjoint species, so no accumulation across calls)
       if (k >= A.nk || k >= A.sw.ns) return;
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int ix = ix0 + p;
+      for (int p = 0; p < SL; ++p) {
+        const int ix = ix0 + px(p);
         if (ix >= A.nx) continue;
         const size_t col = ((size_t)iy * A.nx + ix) * nz;
         float* co = A.out + (size_t)k * A.ny * A.nx * nz + col + row0;
@@ -495,12 +504,13 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
       }
       return;
     }
-    const int pme = n >> kSh;
+    // the lane's output column after the reduce-scatter
+    const int pme = HALF ? 2 * (n & 7) + hsel : n >> kSh;
     const int ixm = ix0 + pme;
     const bool writer = (n & ((1 << kSh) - 1)) == 0 && ixm < A.nx;
     const bool kok = k < A.nk;
     for (int s = 0; s < A.sw.ns; ++s) {
-      float x[NP][4];
+      float x[SL][4];
       if (A.stab) {
         // depth-only switching table: one coefficient per (z, pulse)
         float cz[4];
@@ -510,13 +520,13 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
           cz[j] = (kok && z < nz) ? A.stab[((size_t)z * A.kp + k) * A.sw.ns + s] * ib : 0.0f;
         }
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+        for (int p = 0; p < SL; ++p)
 #pragma unroll
           for (int j = 0; j < 4; ++j) x[p][j] = cz[j] * acc[p][j];
       } else {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          const int ix = ix0 + p;
+        for (int p = 0; p < SL; ++p) {
+          const int ix = ix0 + px(p);
           const int ixc = ix < A.nx ? ix : A.nx - 1;
           const size_t col = ((size_t)iy * A.nx + ixc) * nz;
 #pragma unroll
@@ -526,10 +536,11 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
           }
         }
       }
-      // reduce-scatter over lane bits 3, 2, ...: the upper half of the lanes
-      // keeps the upper half of the positions
+      // reduce-scatter over lane bits 3, 2, ... (half blocks: 2, 1, 0; bit 3
+      // tells the two positions of a pair apart): the upper half of the
+      // lanes keeps the upper half of the slots
 #pragma unroll
-      for (int h = NP / 2, mask = 8; h >= 1; h >>= 1, mask >>= 1) {
+      for (int h = SL / 2, mask = HALF ? 4 : 8; h >= 1; h >>= 1, mask >>= 1) {
         const bool up = (n & mask) != 0;
 #pragma unroll
         for (int q = 0; q < h; ++q)
@@ -757,6 +768,9 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   }
   double ss = 0.0;
   const int nb_n = A.kp / 16;
+  // Half form of the last block (at most 8 pulses in it): 8 pulses per staged
+  // column, and the matrix cores' 16 columns take 8 pulses of two positions
+  auto half_pb = [&](int pb_r) { return A.half != 0 && pb_r == nb_n - 1; };
   // Band blocks of the current run, in registers.  Each run loads the next
   // run's blocks slot by slot as its own chunks finish with them, so the
   // loads are in flight while the remaining chunks compute.
@@ -785,12 +799,11 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   // Staging: thread t loads items t, t+NT, ... of the row, where item
   // it = (oi*XW + xi)*16 + nn is one 16-byte octet of pulse nn at column xi
   // of octet oi; nn = t%16 is fixed and (xi, oi) advance by NT/16 columns
-  // per step.  Without loader waves every thread stages, kStageBatch loads in
+  // per step (half blocks: 8 pulses per column, it = (oi*XW + xi)*8 + nn,
+  // nn = t%8, NT/8 columns per step).  Without loader waves every thread stages, kStageBatch loads in
   // flight before their LDS writes.  The split forms stage the high and the
   // low operand rows in two passes over the window (the same LDS tile):
   // pass 0 adds hi(H) hi(q) + lo(H) hi(q), pass 1 adds hi(H) lo(q).
-  const int t16 = st_id >> 4;
-  const int tnn = st_id & 15;
   const int ps = (int)A.ps;
   const int row_bytes = A.xp * ps * (int)sizeof(E);
   const int dwrap = -XW * ps + A.kp * 8;
@@ -798,28 +811,27 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   // of pulse block pb_r (all unconditional: an item past the window still
   // lies inside the padded row, and its value is never written to LDS)
   auto issue = [&](V* tmp, int cnt, int u0, int jr, int pb_r, int pass_r) {
+    const bool hf = half_pb(pb_r);
+    const int cpt = hf ? NT / 8 : NT / 16;  // columns per step
     const int obase_r = (int)(s_win[jr] >> 16);
     const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
         (void*)((pass_r ? qlo : q) + (size_t)(iy0 + jr) * A.xp * A.ps), (short)0, row_bytes, kBufWord3);
-    int r2 = u0 * (NT / 16) + t16;
+    int r2 = u0 * cpt + (hf ? st_id >> 3 : st_id >> 4);
     int xi = r2 % XW, oi = r2 / XW;
-    int off = (ix0 + xi) * ps + ((obase_r + oi) * A.kp + pb_r * 16 + tnn) * 8;
+    int off = (ix0 + xi) * ps + ((obase_r + oi) * A.kp + pb_r * 16 + (st_id & (hf ? 7 : 15))) * 8;
+    // a step of cpt columns is qw whole octet windows and rw more columns,
+    // then at most one wrap into the next octet (selects, no branches)
+    const int qw = cpt / XW, rw = cpt - qw * XW;
+    const int dstep = rw * ps + qw * A.kp * 8;
 #pragma unroll
     for (int u = 0; u < cnt; ++u) {
       const int ob = off * (int)sizeof(E);
       tmp[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rq, ob, 0, 0));
-      // advance by NT/16 columns; XW >= 16 and NT/16 <= 32, so at most
-      // two wraps into the next octet (selects, no branches)
-      xi += NT / 16;
-      off += (NT / 16) * ps;
+      xi += rw;
+      off += dstep;
       const bool w1 = xi >= XW;
       xi = w1 ? xi - XW : xi;
       off = w1 ? off + dwrap : off;
-      if constexpr (NT / 16 > 16) {
-        const bool w2 = xi >= XW;
-        xi = w2 ? xi - XW : xi;
-        off = w2 ? off + dwrap : off;
-      }
     }
   };
   // a staged row is skipped when its window is empty or it lies past the
@@ -845,7 +857,7 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
         for (int j = 0; j < nwin; ++j) {
           if (!staged(j)) continue;
           __syncthreads();  // the previous row's contractions are done with LDS
-          const int items = (int)(s_win[j] & 0xffffu) * XW * 16;
+          const int items = (int)(s_win[j] & 0xffffu) * XW * (half_pb(pb) ? 8 : 16);
           __builtin_amdgcn_s_waitcnt(kVmcnt0);  // row j has arrived
 #pragma unroll
           for (int u = 0; u < kLoadItems; ++u) {
@@ -866,6 +878,7 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
     }
   }
   for (int pb = 0; pb < nb_n; ++pb) {
+    const bool hf = half_pb(pb);
     f32x4 acc[kLdsPos];
     zero_acc(acc);
     for (int pass = 0; pass < (SPLIT ? 2 : 1); ++pass)
@@ -875,7 +888,7 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
       if (!staged(j)) continue;
       __syncthreads();  // the previous row's contractions are done with LDS
       if constexpr (LOADW == 0) {
-        const int items = ocnt * XW * 16;
+        const int items = ocnt * XW * (hf ? 8 : 16);
         constexpr int NPRE = kStageBatch;
         for (int u0 = 0; u0 * NT < items; u0 += NPRE) {
           V tmp[NPRE];
@@ -892,7 +905,53 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
       }
       __syncthreads();  // row j is in LDS
       const int dy = j - wave;
-      if (row_ok && dy >= 0 && dy < F) {
+      if (row_ok && dy >= 0 && dy < F && hf) {
+        // Half block: the staged column holds 8 pulses, and the fragment of
+        // slot q is the two columns of positions 2q, 2q+1 (lanes 0-7, 8-15).
+        // Stepping dx by -1 moves a pair by one column, i.e. by half a pair,
+        // so the window keeps the 15 overlapping pairs that start at offsets
+        // 0..14 from the run's first column (one LDS read each) and adds the
+        // pair starting at -i at chunk i; slot q at chunk i is the pair at
+        // offset 2q - i (index mod 16: an overwritten pair is never needed
+        // again).
+        const int r0 = __builtin_amdgcn_readfirstlane(s_lstart[dy]);
+        const int r1 = __builtin_amdgcn_readfirstlane(s_lstart[dy + 1]);
+        for (int rr = r0; rr < r1; ++rr) {
+          const uint32_t gr = s_rgrp[4 * rr + g];
+          const int m = __builtin_amdgcn_readfirstlane(s_rinfo[2 * rr]);
+          const int d = (int)(gr & 0xffffu);
+          const int oo = (int)(gr >> 16) - obase;
+          const int base = ((oo * XW + d) * 8 + n) * 8;
+          const int nx = rr + 1 == nrun ? 0 : rr + 1;
+          const int cb2 = __builtin_amdgcn_readfirstlane(s_rinfo[2 * nx + 1]);
+          V R[16];
+#pragma unroll
+          for (int o = 0; o < 15; ++o) R[o] = *(const V*)(sh + base + o * 64);
+#pragma unroll
+          for (int i = 0; i < kRunMax; ++i) {
+            if (i < m) {
+              if (i > 0) R[(16 - i) & 15] = *(const V*)(sh + base - i * 64);
+              // slot 0 takes the pair just read, so it goes last
+              if (SPLIT && pass == 0) {
+#pragma unroll
+                for (int t = 1; t <= 8; ++t) {
+                  const int qs = t & 7;
+                  const int w = (2 * qs - i) & 15;
+                  acc[qs] = H::mma(ab[i], R[w], acc[qs]);
+                  acc[qs] = H::mma(al[i], R[w], acc[qs]);
+                }
+              } else {
+#pragma unroll
+                for (int t = 1; t <= 8; ++t) {
+                  const int qs = t & 7;
+                  acc[qs] = H::mma(ab[i], R[(2 * qs - i) & 15], acc[qs]);
+                }
+              }
+            }
+            load_run(cb2, ab, al, i);
+          }
+        }
+      } else if (row_ok && dy >= 0 && dy < F) {
         // Runs of this (tile, dy).  Within a run the four groups keep their
         // octet and step their offset by -1 per chunk, so position p's operand
         // at chunk i is position p-1's at chunk i-1: a 16-fragment register
@@ -940,7 +999,12 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
         }
       }
     }
-    if (row_ok) epi_block<MODE, kLdsPos, PREC, SPLIT>(A, acc, mtile, iy, ix0, pb * 16, pb == 0, ss);
+    if (row_ok) {
+      if (hf)
+        epi_block<MODE, kLdsPos, PREC, SPLIT, true>(A, acc, mtile, iy, ix0, pb * 16, pb == 0, ss);
+      else
+        epi_block<MODE, kLdsPos, PREC, SPLIT>(A, acc, mtile, iy, ix0, pb * 16, pb == 0, ss);
+    }
     // Retire the epilogue's stores here: with stores and loads both in
     // flight the memory counter no longer orders the band-block loads, and
     // every chunk of the run loop would wait for all of them.
@@ -1311,6 +1375,7 @@ hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* p
   A.ps = (mode == 2) ? P->ps_r : P->ps_b;
   A.nk = P->g.n_pulses;
   A.kp = P->Kp;
+  A.half = T.half;
   A.inv_scale = fp16 ? 1.0f / kFp16Scale : 1.0f;
   A.f16 = P->d_f16;
   A.gate = gate_now();

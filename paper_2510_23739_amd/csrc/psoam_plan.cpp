@@ -413,6 +413,13 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
       if (e[0] == '1' && able) T.loadw = 4;
     }
   }
+  // Half last block: with K mod 16 in 1..8 the last 16-pulse block is at
+  // least half padding; the staged kernel then stages 8 pulses per column and
+  // fills the matrix cores' 16 columns with 8 pulses of two positions.
+  // PSOAM_HALF_BLOCK=0 keeps the padded block (tests compare both).
+  T.half = P->g.n_pulses <= P->Kp - 8 ? 1 : 0;
+  if (const char* e = std::getenv("PSOAM_HALF_BLOCK"))
+    if (e[0] == '0') T.half = 0;
   // PSOAM_BAND_GLOBAL=1 keeps the plan on the global-operand kernel (tests cover both)
   const char* force_global = std::getenv("PSOAM_BAND_GLOBAL");
   T.lds_ok = n_l < 0xffff && F < 0xffff && (rows == 8 ? lds8 : lds4) <= (size_t)kLdsMaxBytes &&

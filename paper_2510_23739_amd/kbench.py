@@ -22,6 +22,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", default="C2")
     ap.add_argument("--crop", type=int, default=0, help="lateral crop (0 = full grid)")
+    ap.add_argument("--pulses", type=int, default=0, help="pulse count (0 = the workload's)")
     ap.add_argument("--prec", default="bf16")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--what", default="fwd,adj,tv")
@@ -37,6 +38,9 @@ def main():
     cfg = synth.CONFIGS[args.config]
     if args.crop:
         cfg = cfg.crop(args.crop, args.crop)
+    if args.pulses:
+        import dataclasses
+        cfg = dataclasses.replace(cfg, n_pulses=args.pulses)
     t0, taps = synth.sir_table(cfg.nz, cfg.f, cfg.nt)
     phi = synth.phi_depth(cfg.nz)
     sp = synth.species(cfg.n_species)

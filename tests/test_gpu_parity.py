@@ -346,3 +346,46 @@ def test_loader_waves_change_nothing(c1, prec, monkeypatch):
     assert d_at == 0.0
     np.testing.assert_array_equal(out["0"][3], out["1"][3])
     assert max(e_at) <= TOL_OP[prec] and max(e_c) <= 1e-3
+
+
+@pytest.mark.parametrize("prec,rows,loadw", [("bf16", "4", "0"), ("bf16", "8", "1"), ("fp16", "8", "0"),
+                                             ("bf16_split", "4", "0"), ("fp16_split", "8", "0"),
+                                             ("bf16_refined", "8", "1")])
+def test_half_last_block_changes_nothing(prec, rows, loadw, monkeypatch):
+    """The last 16-pulse block run in half form (K mod 16 in 1..8: 8 pulses
+    per staged column, two positions per matrix-core block) against the same
+    block padded to 16 pulses: every output element is the same dot product
+    over the same chunks in the same order, and the S^T sum over pulses pairs
+    the lanes the same way (the padded form only adds zeros), so A, A^T and
+    the solve's iterates are equal bit for bit; both meet the oracle.  The
+    ragged grid (K = 19) and a 40-pulse grid with 8-row workgroups."""
+    torch = torch_cuda()
+    monkeypatch.setenv("PSOAM_LDS_ROWS", rows)
+    monkeypatch.setenv("PSOAM_LDS_LOADW", loadw)
+    cases = [ragged_cfg(11)]
+    cfg5 = synth.Config("k40", nx=21, ny=10, nz=24, n_species=3, n_pulses=40, nt=70, f=9,
+                        k1=4, k2=5, seed=12)
+    t05, taps5 = synth.sir_table(cfg5.nz, cfg5.f, cfg5.nt)
+    cases.append((cfg5, t05, taps5, synth.phi_depth(cfg5.nz), synth.species(3)))
+    for (cfg, t0, taps, phi, sp) in cases:
+        S = oracle_S(cfg, phi, sp)
+        rng = np.random.default_rng(21)
+        c = rng.standard_normal(cfg.c_shape).astype(np.float32)
+        y = rng.standard_normal(cfg.y_shape).astype(np.float32)
+        out = {}
+        for hb in ("0", "1"):
+            monkeypatch.setenv("PSOAM_HALF_BLOCK", hb)
+            plan = lib_plan(cfg, t0, taps, phi, sp, prec)
+            out[hb] = (plan.apply_A(torch.from_numpy(c).cuda()).cpu().numpy(),
+                       plan.apply_AT(torch.from_numpy(y).cuda()).cpu().numpy(),
+                       plan.solve(torch.from_numpy(y).cuda(), lambda_tv=1e-2, lambda_l1=1e-2,
+                                  k1=3, k2=4, alpha1=1e-3)[0].cpu().numpy())
+            plan.close()
+        ea = oracle.rel_err(out["1"][0], oracle.apply_A(c, S, t0, taps, cfg.nt))
+        eat = oracle.rel_err(out["1"][1], oracle.apply_AT(y, S, t0, taps, cfg.nz))
+        say(f"[parity] half last block {cfg.name} {prec} rows {rows} loaders {loadw}: "
+            f"A {ea:.2e}, A^T {eat:.2e}; equal to the padded block: "
+            f"{[bool(np.array_equal(a, b)) for a, b in zip(out['0'], out['1'])]}")
+        for a, b in zip(out["0"], out["1"]):
+            np.testing.assert_array_equal(a, b)
+        assert ea <= TOL_OP[prec] and eat <= TOL_OP[prec]
