@@ -127,6 +127,34 @@ def main():
                                                         k1=5, k2=cfg.k2, alpha1=1e-3)) / 5
     if "tv" in what:
         out["prox_tv_k20_ms"] = timed(lambda: plan.prox_tv(c, 0.01, 20, x=g))
+    if "batch" in what:
+        # the batched uneven family (16 instances, 100 outer iterations, K2 20,
+        # 10-step power iteration): one solve_batch call, then one by one
+        import time
+        plans, ps, opts = [], [], []
+        for i in range(16):
+            ci = synth.c4_instance(i)
+            a0, a1 = synth.sir_table(ci.nz, ci.f, ci.nt)
+            plans.append(pk.Plan.from_config(ci, synth.phi_depth(ci.nz), synth.species(ci.n_species),
+                                             a0, a1, prec=args.prec))
+            rng = np.random.default_rng(ci.seed)
+            ps.append(torch.from_numpy(rng.standard_normal(ci.y_shape, dtype=np.float32)).cuda())
+            opts.append(dict(lambda_tv=1e-3, lambda_l1=1e-3, k1=ci.k1, k2=20, n_power=10))
+        cs = [torch.zeros(pl.c_shape, dtype=torch.float32, device="cuda") for pl in plans]
+        pk.solve_batch(plans, ps, cs, [dict(o, k1=2) for o in opts])
+        torch.cuda.synchronize()
+        t_0 = time.perf_counter()
+        pk.solve_batch(plans, ps, cs, opts)
+        torch.cuda.synchronize()
+        out["batch_s"] = time.perf_counter() - t_0
+        t_0 = time.perf_counter()
+        for pl, p_, c_, o in zip(plans, ps, cs, opts):
+            c_.zero_()
+            pl.solve(p_, c=c_, **o)
+        torch.cuda.synchronize()
+        out["one_by_one_s"] = time.perf_counter() - t_0
+        for pl in plans:
+            pl.close()
     if "r3" in what:
         out["prox_r3_k20_ms"] = timed(lambda: plan.prox_r3(c, 0.01, 0.005, 0.01, 20, x=g))
     print(json.dumps(out), flush=True)
