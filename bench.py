@@ -57,6 +57,8 @@ def parse(argv=None):
     ap.add_argument("--compare", default="fp16,bf16_split,fp32",
                     help="other precisions timed on the headline workload ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="headline plan with the built-in launch-shape rules instead of the autotuner")
     ap.add_argument("--no-c1-oracle", action="store_true",
                     help="skip the FP64 oracle solve at 32x32x16 used for each precision's c error")
     ap.add_argument("--cpu-crop", type=int, default=0,
@@ -140,14 +142,19 @@ def headline_inputs(torch, pk, cfg, synth):
 
 
 def run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1, prec,
-             steps, warmup, reps, separable=False, full_solve=False, v0=None, tvs=False):
+             steps, warmup, reps, separable=False, full_solve=False, v0=None, tvs=False,
+             tune=False):
     """Times one precision on one workload: optionally the full K1-iteration
     solve with its power iteration (first; alpha1 <= 0 takes the step from it),
     isolated applies, the band kernels alone (HIP events), `steps` solver
-    steps after `warmup`, optionally the steps with the TV(S c) term."""
-    plan = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=prec, separable=separable)
+    steps after `warmup`, optionally the steps with the TV(S c) term.  tune:
+    the plan's launch shapes chosen by the autotuner (its report kept)."""
+    t_plan = time.perf_counter()
+    plan = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=prec, separable=separable, tune=tune)
     info = plan.stats()
     out = dict(plan=plan, info=info)
+    if tune:
+        out["autotune"] = dict(plan.tune_report, seconds=time.perf_counter() - t_plan)
     c_full = None
     if full_solve:
         c_full = torch.zeros(cfg.c_shape, dtype=torch.float32, device="cuda")
@@ -626,7 +633,8 @@ def main(argv=None):
     lam_tv, lam_l1 = 5e-3 * aty_inf, 1e-2 * aty_inf
     log(f"[bench] {cfg.name} {args.prec}: full solve, applies, kernels, steps")
     res = run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, 0.0, lam_tv, lam_l1, args.prec,
-                   args.steps, args.warmup, reps, full_solve=True, v0=v0, tvs=not big)
+                   args.steps, args.warmup, reps, full_solve=True, v0=v0, tvs=not big,
+                   tune=not args.no_tune)
     alpha1 = res["alpha1"]
     runs = {args.prec: res}
     others = [] if args.headline_only else [q for q in args.compare.split(",") if q and q != args.prec]
@@ -688,6 +696,7 @@ def main(argv=None):
         "power_iteration": {"steps": 30, "start": "seeded Gaussian",
                             "lambda_max": res["lambda_max"], "alpha1": alpha1},
         "band_fill": info["useful_macs"][0] / max(1, info["executed_macs"][0]),
+        "autotune": res.get("autotune"),
         "precisions": per_prec_rows(runs, flops, cfg),
     }
     headline_precs = list(runs)

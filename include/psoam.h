@@ -387,26 +387,37 @@ typedef struct {
   int32_t h_rows;        /* output rows per workgroup of the staged H kernel (0: not staged) */
   int32_t ht_rows;       /* the same for S^T H^T */
   int32_t ht_shift;      /* sample shift of the 16-bit H^T operand (0 or 4) */
-  int32_t candidates;    /* launch shapes timed (0: nothing to tune, or taken from the cache) */
-  int32_t from_cache;    /* 1 when the choice came from this process's cache */
+  int32_t candidates;    /* launch shapes timed (0: nothing to tune, or taken from a cache) */
+  int32_t from_cache;    /* 1: the choice came from this process's cache, 2: from the disk cache */
   double h_ms, ht_ms;    /* kernel times of the choice (residual form of H; S^T H^T) */
   double h_ms_default, ht_ms_default;  /* the same for the plan's own rules' choice */
+  int32_t h_loaders;     /* loader waves beside H's eight contracting waves (0 or 4) */
+  int32_t tv_tile[4];    /* tile of the TV dual step: y, x, z extent and threads per block */
+  double tv_ms, tv_ms_default;  /* one TV dual step with the chosen / the default tile */
 } psoam_tune_report;
 
-/* psoam_plan_create with the launch shape of the band kernels chosen by
- * measurement: for a 16-bit plan of the general form it builds the plan the
- * built-in rules choose and the alternatives that fit the LDS (4 or 8
- * output rows per workgroup for H and for H^T, operand shift 0 or 4 for
- * H^T), times each kernel's solver form on `stream` (HIP events, one warm-up
- * and three timed launches on the zeroed operands), and returns the plan
- * with the fastest H and the fastest H^T.  Results do not depend on the
- * choice (the same products are summed in the same order).  The choice is
- * cached per process, keyed by the geometry, precision and a hash of the
- * impulse-response table, so a second call with the same inputs only builds
- * the plan.  FP32 and separable plans have nothing to tune and are built
- * directly.  For callers who create a plan once and apply it many times:
- * tuning builds up to six plans (about 0.25 s at 128 x 128 x 64).  `report` may
- * be null.  Errors as psoam_plan_create; synchronises `stream`. */
+/* psoam_plan_create with the launch shapes chosen by measurement: for a
+ * 16-bit plan of the general form it builds the plan the built-in rules
+ * choose and the alternatives that fit (4 or 8 output rows per workgroup for
+ * H, with or without four loader waves at 8 rows; 4 or 8 rows and operand
+ * shift 0 or 4 for H^T), times each band kernel's solver form on `stream`
+ * (HIP events, one warm-up and three timed launches on the zeroed operands),
+ * times the TV dual step on the plan's grid with each tile shape of the
+ * kernel's list (8x8x32 with 512 threads, 4x8x32/256, 4x16x32/512,
+ * 4x8x64/512, 8x8x32/1024; one warm-up and ten steps), and returns the plan
+ * with the fastest H, H^T and TV step.  Results do not depend on the choice
+ * (the same products are summed in the same order; every TV output is the
+ * same expression whatever the tile).  The choice is cached per process and
+ * on disk, keyed by the device (architecture and compute units), the
+ * geometry, the precision and a hash of the impulse-response table; the disk
+ * cache is the file named by the environment variable PSOAM_TUNE_CACHE
+ * (empty: no disk cache), else $HOME/.cache/psoam/tune.txt, one line per
+ * choice, appended after each tuning (a file that cannot be read or written
+ * is skipped silently).  A call served from a cache only builds the plan.
+ * FP32 and separable plans have nothing to tune and are built directly.  For
+ * callers who create a plan once and apply it many times: tuning builds up
+ * to seven plans (about 0.25 s at 128 x 128 x 64).  `report` may be null.
+ * Errors as psoam_plan_create; synchronises `stream`. */
 int psoam_plan_create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
                             const int32_t* sir_t0, const float* sir_taps, int32_t sir_w,
                             int32_t prec, void* stream, psoam_plan** out,

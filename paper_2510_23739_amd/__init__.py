@@ -73,7 +73,9 @@ class Plan:
         if tune:
             rep = _lib.TuneReport()
             check(lib.psoam_plan_create_tuned(*args, C.byref(rep)))
-            self.tune_report = {name: getattr(rep, name) for name, _ in _lib.TuneReport._fields_}
+            self.tune_report = {name: (list(v) if isinstance(v, C.Array) else v)
+                                for name, v in ((n, getattr(rep, n))
+                                                for n, _ in _lib.TuneReport._fields_)}
         else:
             check(lib.psoam_plan_create(*args))
         self._h = handle

@@ -51,7 +51,9 @@ class TuneReport(C.Structure):
     _fields_ = [("h_rows", C.c_int32), ("ht_rows", C.c_int32), ("ht_shift", C.c_int32),
                 ("candidates", C.c_int32), ("from_cache", C.c_int32),
                 ("h_ms", C.c_double), ("ht_ms", C.c_double),
-                ("h_ms_default", C.c_double), ("ht_ms_default", C.c_double)]
+                ("h_ms_default", C.c_double), ("ht_ms_default", C.c_double),
+                ("h_loaders", C.c_int32), ("tv_tile", C.c_int32 * 4),
+                ("tv_ms", C.c_double), ("tv_ms_default", C.c_double)]
 
 
 EXPORTS = {

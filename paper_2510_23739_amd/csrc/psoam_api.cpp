@@ -7,6 +7,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <map>
@@ -14,6 +15,8 @@
 #include <mutex>
 #include <string>
 #include <vector>
+
+#include <sys/stat.h>
 
 #include "psoam_internal.h"
 
@@ -786,13 +789,17 @@ namespace psoam {
 namespace {
 
 // ---- launch-shape autotuner (psoam_plan_create_tuned) ---------------------
-// The choice: rows per staged workgroup of H and of H^T, and the H^T operand
-// shift.  Measured per process and cached by geometry, precision and a hash
-// of the impulse-response table.
+// The choice: rows per staged workgroup of H and of H^T, the H^T operand
+// shift, H's loader waves, and the tile of the TV dual step.  Measured per
+// process and cached in memory and on disk by device, geometry, precision
+// and a hash of the impulse-response table.
+constexpr int kTuneVersion = 2;  // bump when the kernels or the choices change meaning
+
 struct Shape {
-  int h_rows = 0, ht_rows = 0, tsh = 0;
+  int h_rows = 0, ht_rows = 0, tsh = 0, h_loadw = 0, tv = 0;
   bool operator==(const Shape& o) const {
-    return h_rows == o.h_rows && ht_rows == o.ht_rows && tsh == o.tsh;
+    return h_rows == o.h_rows && ht_rows == o.ht_rows && tsh == o.tsh && h_loadw == o.h_loadw &&
+           tv == o.tv;
   }
 };
 
@@ -809,11 +816,67 @@ std::string tune_key(const psoam_geom& g, int32_t sir_w, int32_t prec, const int
   const size_t ntab = (size_t)g.nz * g.f * g.f;
   mix(t0, ntab * sizeof(int32_t));
   mix(taps, ntab * (size_t)sir_w * sizeof(float));
-  char buf[200];
-  std::snprintf(buf, sizeof buf, "%d %d %d %d %d %d %d %d %d %d %016llx", g.nx, g.ny, g.nz,
-                g.n_species, g.n_pulses, g.nt, g.f, g.phi_per_voxel, sir_w, prec,
-                (unsigned long long)h);
+  // the device: architecture and compute units
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  char arch[64] = "unknown";
+  int cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    std::snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    for (char* c = arch; *c; ++c)
+      if (*c == ' ' || *c == '\t') *c = '_';
+    cus = prop.multiProcessorCount;
+  }
+  char buf[320];
+  std::snprintf(buf, sizeof buf, "v%d %s %d %d %d %d %d %d %d %d %d %d %d %016llx", kTuneVersion,
+                arch, cus, g.nx, g.ny, g.nz, g.n_species, g.n_pulses, g.nt, g.f, g.phi_per_voxel,
+                sir_w, prec, (unsigned long long)h);
   return buf;
+}
+
+// the disk cache: PSOAM_TUNE_CACHE (empty: none), else $HOME/.cache/psoam/tune.txt
+std::string tune_file() {
+  if (const char* e = std::getenv("PSOAM_TUNE_CACHE")) return e;
+  const char* home = std::getenv("HOME");
+  if (!home || !home[0]) return "";
+  return std::string(home) + "/.cache/psoam/tune.txt";
+}
+
+// the last line "key<TAB>h_rows ht_rows tsh h_loadw tv" of the file for key
+bool disk_lookup(const std::string& key, Shape& out) {
+  const std::string path = tune_file();
+  if (path.empty()) return false;
+  std::FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  bool found = false;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    char* tab = std::strchr(line, '\t');
+    if (!tab || (size_t)(tab - line) != key.size() || key.compare(0, key.size(), line, key.size()))
+      continue;
+    Shape s;
+    if (std::sscanf(tab + 1, "%d %d %d %d %d", &s.h_rows, &s.ht_rows, &s.tsh, &s.h_loadw,
+                    &s.tv) == 5 &&
+        s.tv >= 0 && s.tv < tv_tile_count()) {
+      out = s;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void disk_store(const std::string& key, const Shape& s) {
+  const std::string path = tune_file();
+  if (path.empty()) return;
+  // make the parent folders (best effort)
+  for (size_t i = 1; i < path.size(); ++i)
+    if (path[i] == '/') (void)::mkdir(path.substr(0, i).c_str(), 0755);
+  std::FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%s\t%d %d %d %d %d\n", key.c_str(), s.h_rows, s.ht_rows, s.tsh, s.h_loadw,
+               s.tv);
+  std::fclose(f);
 }
 
 Shape shape_of(const psoam_plan* P) {
@@ -821,25 +884,20 @@ Shape shape_of(const psoam_plan* P) {
   s.h_rows = P->fwd.lds_ok ? P->fwd.rows : 0;
   s.ht_rows = P->adj.lds_ok ? P->adj.rows : 0;
   s.tsh = P->tsh;
+  s.h_loadw = P->fwd.lds_ok && P->fwd.loadw > 0 ? 1 : 0;
+  s.tv = P->tv_tile;
   return s;
 }
 
-// average ms of the band kernel of direction dir in the solver's form
-// (dir 0: H with the residual epilogue, dir 1: S^T H^T), one warm-up launch
-int time_band(psoam_plan* P, int dir, hipStream_t s, double* ms) {
-  SolveBufs B;
-  if (int rc = ensure_solve_ws(P, B)) return rc;
-  auto launch = [&]() {
-    return dir == 0 ? launch_band(P, 1, nullptr, nullptr, P->d_partial, s)
-                    : launch_band(P, 2, B.g, nullptr, nullptr, s);
-  };
+// average ms of `launch` over kReps launches after one warm-up
+template <class F>
+int time_launches(F&& launch, int reps, hipStream_t s, double* ms) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = launch(0);
   if (e == hipSuccess) e = hipEventRecord(e0, s);
-  constexpr int kReps = 3;
-  for (int i = 0; i < kReps && e == hipSuccess; ++i) e = launch();
+  for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch(i + 1);
   if (e == hipSuccess) e = hipEventRecord(e1, s);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float t = 0.0f;
@@ -847,17 +905,48 @@ int time_band(psoam_plan* P, int dir, hipStream_t s, double* ms) {
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(e, "autotune: timing launch");
-  *ms = (double)t / kReps;
+  *ms = (double)t / reps;
   return PSOAM_OK;
+}
+
+// average ms of the band kernel of direction dir in the solver's form
+// (dir 0: H with the residual epilogue, dir 1: S^T H^T), one warm-up launch
+int time_band(psoam_plan* P, int dir, hipStream_t s, double* ms) {
+  SolveBufs B;
+  if (int rc = ensure_solve_ws(P, B)) return rc;
+  return time_launches(
+      [&](int) {
+        return dir == 0 ? launch_band(P, 1, nullptr, nullptr, P->d_partial, s)
+                        : launch_band(P, 2, B.g, nullptr, nullptr, s);
+      },
+      3, s, ms);
+}
+
+// average ms of one TV dual step with the plan's tile, on zeroed duals
+int time_tv(psoam_plan* P, hipStream_t s, double* ms) {
+  SolveBufs B;
+  if (int rc = ensure_solve_ws(P, B)) return rc;
+  const size_t sv = P->c_elems();
+  for (float* b : {B.u[0], B.u[1], B.u[2]}) PSOAM_HIP(hipMemsetAsync(b, 0, sizeof(float) * 3 * sv, s));
+  PSOAM_HIP(hipMemsetAsync(B.zb, 0, sizeof(float) * sv, s));
+  return time_launches(
+      [&](int i) {
+        float* nxt = B.u[i % 3];
+        const float* cur = B.u[(i + 2) % 3];
+        const float* prev = B.u[(i + 1) % 3];
+        return launch_tv_step(P, nxt, B.zb, cur, prev, 0.5f, 0.08f, 1.0f, s);
+      },
+      10, s, ms);
 }
 
 // a plan built with the given launch shape (0 entries: the plan's own rules)
 int build_shaped(const psoam_geom* g, const psoam_species* sp, const float* phi,
                  const int32_t* t0, const float* taps, int32_t sir_w, int32_t prec,
                  hipStream_t s, const Shape& want, psoam_plan** out) {
-  set_tune_choice(want.h_rows, want.ht_rows, want.tsh);
+  set_tune_choice(want.h_rows, want.ht_rows, want.tsh, want.h_rows ? want.h_loadw : -1);
   const int rc = create_plan(g, sp, phi, t0, taps, sir_w, prec, s, out);
   clear_tune_choice();
+  if (rc == PSOAM_OK) (*out)->tv_tile = want.tv;
   return rc;
 }
 
@@ -870,6 +959,8 @@ int create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
     r.h_rows = got.h_rows;
     r.ht_rows = got.ht_rows;
     r.ht_shift = got.tsh;
+    r.h_loaders = got.h_loadw ? 4 : 0;
+    tv_tile_dims(got.tv, r.tv_tile);
     if (rep) *rep = r;
     *out = P;
     return PSOAM_OK;
@@ -886,22 +977,48 @@ int create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
     return create_plan(g, sp, phi, t0, taps, sir_w, prec, s, out);  // its own errors
   const std::string key = tune_key(*g, sir_w, prec, t0, taps);
   {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-      const Shape want = it->second;
+    Shape want;
+    int from = 0;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      // PSOAM_TUNE_MEMO=0 skips this process's cache (tests read the disk's)
+      const char* memo = std::getenv("PSOAM_TUNE_MEMO");
+      auto it = memo && memo[0] == '0' ? g_tune_cache.end() : g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        want = it->second;
+        from = 1;
+      } else if (disk_lookup(key, want)) {
+        g_tune_cache[key] = want;
+        from = 2;
+      }
+    }
+    if (from) {
       if (int rc = build_shaped(g, sp, phi, t0, taps, sir_w, prec, s, want, &P)) return rc;
-      r.from_cache = 1;
+      r.from_cache = from;
       return done(P);
     }
   }
   // the plan's own choice, timed
   if (int rc = create_plan(g, sp, phi, t0, taps, sir_w, prec, s, &P)) return rc;
   const Shape base = shape_of(P);
-  double h_best = 0.0, ht_best = 0.0;
+  double h_best = 0.0, ht_best = 0.0, tv_best = 0.0;
   int rc = PSOAM_OK;
   if (base.h_rows) rc = time_band(P, 0, s, &h_best);
   if (rc == PSOAM_OK && base.ht_rows) rc = time_band(P, 1, s, &ht_best);
+  if (rc == PSOAM_OK) rc = time_tv(P, s, &tv_best);  // the default tile
+  r.tv_ms_default = tv_best;
+  Shape best = base;
+  // TV tiles: the same plan, another tile
+  for (int t = 1; t < tv_tile_count() && rc == PSOAM_OK; ++t) {
+    P->tv_tile = t;
+    double ms = 0.0;
+    rc = time_tv(P, s, &ms);
+    if (rc == PSOAM_OK && ms < tv_best * 0.995) {
+      tv_best = ms;
+      best.tv = t;
+    }
+  }
+  P->tv_tile = base.tv;
   if (rc != PSOAM_OK) {
     free_plan(P);
     return rc;
@@ -909,15 +1026,19 @@ int create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
   r.candidates = 1;
   r.h_ms_default = h_best;
   r.ht_ms_default = ht_best;
-  Shape best = base;
-  // alternatives: the other row count for H; the other row counts and
-  // shifts for H^T (each timed on the direction it changes)
+  // alternatives: the other row counts and loader-wave settings for H; the
+  // other row counts and shifts for H^T (each timed on the direction it changes)
   std::vector<std::pair<Shape, int>> alts;
-  if (base.h_rows) alts.push_back({Shape{base.h_rows == 4 ? 8 : 4, base.ht_rows, base.tsh}, 0});
+  if (base.h_rows)
+    for (int rows : {4, 8})
+      for (int lw : {0, 1})
+        if ((rows != base.h_rows || lw != base.h_loadw) && !(rows == 4 && lw == 1))
+          alts.push_back({Shape{rows, base.ht_rows, base.tsh, lw, base.tv}, 0});
   if (base.ht_rows)
     for (int rows : {4, 8})
       for (int tsh : {0, 4})
-        if (rows != base.ht_rows || tsh != base.tsh) alts.push_back({Shape{base.h_rows, rows, tsh}, 1});
+        if (rows != base.ht_rows || tsh != base.tsh)
+          alts.push_back({Shape{base.h_rows, rows, tsh, base.h_loadw, base.tv}, 1});
   for (const auto& a : alts) {
     psoam_plan* Q = nullptr;
     if ((rc = build_shaped(g, sp, phi, t0, taps, sir_w, prec, s, a.first, &Q))) break;
@@ -933,6 +1054,7 @@ int create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
     if (a.second == 0 && ms < h_best) {
       h_best = ms;
       best.h_rows = a.first.h_rows;
+      best.h_loadw = a.first.h_loadw;
     }
     if (a.second == 1 && ms < ht_best) {
       ht_best = ms;
@@ -944,13 +1066,20 @@ int create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
     free_plan(P);
     return rc;
   }
+  r.candidates += tv_tile_count() - 1;
   r.h_ms = h_best;
   r.ht_ms = ht_best;
+  r.tv_ms = tv_best;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
+    disk_store(key, best);
   }
-  if (best == base) return done(P);
+  if (best.h_rows == base.h_rows && best.ht_rows == base.ht_rows && best.tsh == base.tsh &&
+      best.h_loadw == base.h_loadw) {
+    P->tv_tile = best.tv;
+    return done(P);
+  }
   free_plan(P);
   P = nullptr;
   if ((rc = build_shaped(g, sp, phi, t0, taps, sir_w, prec, s, best, &P))) return rc;

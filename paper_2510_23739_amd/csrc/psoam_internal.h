@@ -115,6 +115,7 @@ struct psoam_plan {
   int Yp, Xp;
   int Lz, Lt;       // contracted lengths of the H operand (z) and H^T operand (t), in samples
   int tsh = 0;      // 16-bit H^T operand: sample t is stored at t + tsh (0 or 4)
+  int tv_tile = 0;  // tile shape of the TV dual step (index into the kernel's shape list)
   size_t ps_b, ps_r;  // elements per padded position of the H / H^T operands
   int device;
   float* d_phi = nullptr;
@@ -175,10 +176,10 @@ namespace psoam {
 
 // Launch-shape choice for the next plan built on this thread (the
 // autotuner's lever): output rows per staged workgroup for H (rows_fwd) and
-// H^T (rows_adj), 4 or 8, and the H^T operand shift, 0 or 4; any other value
-// leaves that choice to the plan's own rules.  A choice that does not fit
-// the LDS is ignored.
-void set_tune_choice(int rows_fwd, int rows_adj, int tsh);
+// H^T (rows_adj), 4 or 8, the H^T operand shift, 0 or 4, and H's loader
+// waves, 0 (off) or 1 (on where they can run); any other value leaves that
+// choice to the plan's own rules.  A choice that does not fit is ignored.
+void set_tune_choice(int rows_fwd, int rows_adj, int tsh, int loadw_fwd);
 void clear_tune_choice();
 
 // Device stop gate of the calling thread: while a solve with device-side
@@ -214,6 +215,9 @@ hipError_t launch_prox_l1(float* x, const float* z, int64_t n, float thresh, int
 hipError_t launch_tv_step(const psoam_plan* P, float* u_next, const float* z, const float* u_cur,
                           const float* u_prev, float beta, float inv_mu, float theta,
                           hipStream_t s);
+// tile shapes of the TV dual step: count, and (y, x, z, threads) of shape i
+int tv_tile_count();
+void tv_tile_dims(int i, int* d);
 // x = z - grad^T u (u may be null: x = z); then mode 0: as is, 1: max(x,0), 2: max(x - t1, 0)
 hipError_t launch_tv_final(const psoam_plan* P, float* x, const float* z, const float* u,
                            int mode, float thresh1, hipStream_t s);

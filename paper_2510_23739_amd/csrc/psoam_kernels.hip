@@ -1484,13 +1484,22 @@ __device__ __forceinline__ float gradT_at(const float* __restrict__ uc, const fl
 // plane that component's difference needs; w is formed on the tile plus the
 // forward halo; the new duals are written for the tile.  Global traffic is
 // about u_j, u_{j-1} (3 components each), z in and u_{j+1} out per voxel.
-constexpr int kTvY = 8, kTvX = 8, kTvZ = 32;
-constexpr int kTvThreads = 512;  // 8 waves per 2048-voxel tile
+// Every output is the same expression of the same inputs whatever the tile,
+// so the tile shape (chosen per plan by the autotuner) never changes results.
 template <int Y, int X, int Z>
 struct Dims3 {
   static constexpr int y = Y, x = X, z = Z;
 };
+// tile shapes (y, x, z, threads); entry 0 is the default
+constexpr int kTvTiles = 5;
+constexpr int kTvTile[kTvTiles][4] = {
+    {8, 8, 32, 512}, {4, 8, 32, 256}, {4, 16, 32, 512}, {4, 8, 64, 512}, {8, 8, 32, 1024}};
+int tv_tile_count() { return kTvTiles; }
+void tv_tile_dims(int i, int* d) {
+  for (int k = 0; k < 4; ++k) d[k] = kTvTile[i][k];
+}
 
+template <int kTvY, int kTvX, int kTvZ, int kTvThreads>
 __global__ __launch_bounds__(kTvThreads) void tv_step_kernel(float* __restrict__ un,
                                                       const float* __restrict__ zin,
                                                       const float* __restrict__ uc,
@@ -1635,11 +1644,28 @@ hipError_t launch_tv_step(const psoam_plan* P, float* u_next, const float* z, co
                           const float* u_prev, float beta, float inv_mu, float theta,
                           hipStream_t s) {
   const Grid3 G = grid3(P);
-  const size_t nb = (size_t)P->g.n_species * ((G.ny + kTvY - 1) / kTvY) *
-                    ((G.nx + kTvX - 1) / kTvX) * ((G.nz + kTvZ - 1) / kTvZ);
+  const int t = P->tv_tile >= 0 && P->tv_tile < kTvTiles ? P->tv_tile : 0;
+  const int* d = kTvTile[t];
+  const size_t nb = (size_t)P->g.n_species * ((G.ny + d[0] - 1) / d[0]) *
+                    ((G.nx + d[1] - 1) / d[1]) * ((G.nz + d[2] - 1) / d[2]);
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(tv_step_kernel, dim3((unsigned)nb), dim3(kTvThreads), 0, s, u_next, z, u_cur,
-                     u_prev, beta, inv_mu, theta, G);
+#define PSOAM_TV(I)                                                                          \
+  case I:                                                                                    \
+    hipLaunchKernelGGL((tv_step_kernel<kTvTile[I][0], kTvTile[I][1], kTvTile[I][2],          \
+                                       kTvTile[I][3]>),                                      \
+                       dim3((unsigned)nb), dim3(kTvTile[I][3]), 0, s, u_next, z, u_cur, u_prev, \
+                       beta, inv_mu, theta, G);                                              \
+    break;
+  switch (t) {
+    PSOAM_TV(0)
+    PSOAM_TV(1)
+    PSOAM_TV(2)
+    PSOAM_TV(3)
+    PSOAM_TV(4)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef PSOAM_TV
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ thread_local std::string g_last_error;
 struct TuneChoice {
   int rows[2] = {0, 0};
   int tsh = -1;
+  int loadw = -1;  // H's loader waves: 0 off, 1 on where they can run, else the rules
 };
 thread_local TuneChoice g_tune;
 
@@ -67,10 +68,11 @@ struct Group {
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-void set_tune_choice(int rows_fwd, int rows_adj, int tsh) {
+void set_tune_choice(int rows_fwd, int rows_adj, int tsh, int loadw_fwd) {
   g_tune.rows[0] = rows_fwd;
   g_tune.rows[1] = rows_adj;
   g_tune.tsh = tsh;
+  g_tune.loadw = loadw_fwd;
 }
 
 void clear_tune_choice() { g_tune = TuneChoice(); }
@@ -412,6 +414,9 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
       if (e[0] == '0') T.loadw = 0;
       if (e[0] == '1' && able) T.loadw = 4;
     }
+    // the autotuner's choice
+    if (dir == 0 && g_tune.loadw == 0) T.loadw = 0;
+    if (dir == 0 && g_tune.loadw == 1 && able) T.loadw = 4;
   }
   // Half last block: with K mod 16 in 1..8 the last 16-pulse block is at
   // least half padding; the staged kernel then stages 8 pulses per column and
@@ -681,6 +686,11 @@ static int create_plan_impl(const psoam_geom* gp, const psoam_species* sp, const
     // PSOAM_ADJ_SHIFT=0 or 4 overrides the choice (tests cover both)
     if (const char* e = std::getenv("PSOAM_ADJ_SHIFT")) P->tsh = e[0] == '4' ? 4 : 0;
     if (g_tune.tsh == 0 || g_tune.tsh == 4) P->tsh = g_tune.tsh;  // the autotuner's choice
+  }
+  // PSOAM_TV_TILE=i takes tile shape i of the TV dual step (tests run each)
+  if (const char* e = std::getenv("PSOAM_TV_TILE")) {
+    const int t = std::atoi(e);
+    if (t >= 0 && t < tv_tile_count()) P->tv_tile = t;
   }
   P->Lt = (g.nt + 15) / 16 * 16 + (P->tsh ? 16 : 0);
   P->ps_b = (size_t)P->Lz * P->Kp;

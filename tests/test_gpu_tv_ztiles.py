@@ -106,3 +106,28 @@ def test_prox_tv_largest_volume():
     z += np.sin(np.arange(base.nz) / 11.0).astype(np.float32)
     _check(torch, plan, z, 0.05, 10, True, "320x320x128")
     plan.close()
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+def test_every_tile_shape_gives_the_default_result(tile, monkeypatch):
+    """Each tile shape of the fused dual step (chosen per plan by the
+    autotuner) against the default 8 x 8 x 32 tile: every output is the same
+    expression of the same inputs, so the prox is equal bit for bit; on the
+    ragged 9 x 13 x 70 grid (partial tiles in every direction, and one or
+    three depth tiles of 64 or 32) and against the oracle."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(70 + tile)
+    z = rng.standard_normal((2, 9, 13, 70)).astype(np.float32)
+    out = {}
+    for t in (0, tile):
+        monkeypatch.setenv("PSOAM_TV_TILE", str(t))
+        plan, cfg = _plan(9, 13, 70)
+        zt = torch.from_numpy(z).cuda()
+        out[t] = plan.prox_tv(zt, 0.1, 20, nonneg=True, x=nan_buf(z.shape)).cpu().numpy()
+        plan.close()
+    ref = oracle.prox_tv(z, 0.1, 20, nonneg=True)
+    e = oracle.rel_err(out[tile], ref)
+    say(f"[tv-z] tile {tile}: rel err {e:.3e}, equal to the default tile "
+        f"{bool(np.array_equal(out[0], out[tile]))}")
+    np.testing.assert_array_equal(out[0], out[tile])
+    assert e <= TOL
