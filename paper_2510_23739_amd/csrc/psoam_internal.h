@@ -90,6 +90,8 @@ struct BandTable {
   // 1: the last 16-pulse block holds at most 8 pulses and the staged kernel
   // runs it as 8 pulses x pairs of positions (half the products and staging)
   int half = 0;
+  // FP32 plans: the run tables (no windows) feed the global-operand run kernel
+  bool runs32 = false;
 };
 
 // LDS bytes of the staged kernel's per-tile tables: row windows (F + rows - 1),

@@ -1016,6 +1016,105 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   }
 }
 
+// --------------------------------------------------------------------------
+// FP32 band contraction over the run-packed table (single-sample groups).
+//
+// The staged kernel's runs without the staging: a wave owns one output row x
+// kLdsPos positions x one output tile, walks every dy of the footprint and
+// every run of (tile, dy), and keeps a 16-fragment register window of the
+// operand (one float per lane: sample l of its group, pulse n) that slides
+// one column per chunk, so a chunk reads one new column from global memory
+// (the neighbouring waves and positions read the same rows: L1/L2 hits) and
+// issues kLdsPos products.  The band values (one float per lane per chunk)
+// are loaded a run ahead into a ring of kRunMax slots, as in the staged
+// kernel.  A block holds kWavesPerBlock consecutive output rows; blocks are
+// ordered by XCD and tile work like the staged kernel's.
+// --------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(MODE == 2 ? 2 : 3))) void band32_run(
+    BandArgs A, LdsArgs L) {
+  if (A.gate && *A.gate) return;  // a device stop test has ended the solve
+  const int b = blockIdx.x;
+  const int npos = L.nxb * L.nyb;
+  int mtile, pos;
+  if ((npos & 7) == 0) {
+    const int xcd = b & 7, k = b >> 3;
+    const int per_x = npos >> 3;
+    mtile = L.order[k / per_x];
+    pos = xcd * per_x + k % per_x;
+  } else {
+    mtile = L.order[b / npos];
+    pos = b % npos;
+  }
+  const int xb = pos % L.nxb, yb = pos / L.nxb;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, n = lane & 15;
+  const int iy = yb * kWavesPerBlock + wave, ix0 = xb * kLdsPos;
+  const int F = L.f;
+  double ss = 0.0;
+  if (iy < A.ny) {
+    const int rt0 = L.lstart[mtile * F];
+    const int rt1 = L.lstart[(mtile + 1) * F];
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)L.la, (short)0, L.la_bytes, kBufWord3);
+    const int vo = lane * (int)sizeof(float);
+    float ab[kRunMax];
+    auto load_run = [&](int cb, int i) {
+      ab[i] = __builtin_bit_cast(
+          float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, (cb + i) * kWaveLanes * (int)sizeof(float), 0));
+    };
+    const float* q = (const float*)A.q;
+    const int nb_n = A.kp / 16;
+    for (int pb = 0; pb < nb_n; ++pb) {
+      f32x4 acc[kLdsPos];
+      zero_acc(acc);
+      if (pb == 0 && rt1 > rt0) {
+        const int cb0 = __builtin_amdgcn_readfirstlane(L.rinfo[2 * rt0 + 1]);
+#pragma unroll
+        for (int i = 0; i < kRunMax; ++i) load_run(cb0, i);
+      }
+      for (int dy = 0; dy < F; ++dy) {
+        const int r0 = __builtin_amdgcn_readfirstlane(L.lstart[mtile * F + dy]);
+        const int r1 = __builtin_amdgcn_readfirstlane(L.lstart[mtile * F + dy + 1]);
+        // padded input row iy + dy; column ix0 + x of the padded grid
+        const float* qrow = q + (size_t)(iy + dy) * A.xp * A.ps + (size_t)ix0 * A.ps + pb * 16 + n;
+        for (int rr = r0; rr < r1; ++rr) {
+          const uint32_t gr = L.lgrp[4 * rr + g];
+          const int m = __builtin_amdgcn_readfirstlane(L.rinfo[2 * rr]);
+          const int d = (int)(gr & 0xffffu);
+          const int l = (int)(gr >> 16);
+          const float* base = qrow + (size_t)d * A.ps + (size_t)l * A.kp;
+          // the run after this one (the first of the tile after the last)
+          const int nx = rr + 1 == rt1 ? rt0 : rr + 1;
+          const int cb2 = __builtin_amdgcn_readfirstlane(L.rinfo[2 * nx + 1]);
+          float R[kLdsPos];
+#pragma unroll
+          for (int p = 0; p < kLdsPos; ++p) R[p] = base[(size_t)p * A.ps];
+#pragma unroll
+          for (int i = 0; i < kRunMax; ++i) {
+            if (i < m) {
+              if (i > 0) R[(kLdsPos - i) & (kLdsPos - 1)] = base[-(ptrdiff_t)i * A.ps];
+#pragma unroll
+              for (int t = 1; t <= kLdsPos; ++t) {
+                const int p = t & (kLdsPos - 1);
+                acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[i], R[(p - i) & (kLdsPos - 1)],
+                                                                acc[p], 0, 0, 0);
+              }
+            }
+            load_run(cb2, i);
+          }
+        }
+      }
+      epi_block<MODE, kLdsPos, PSOAM_FP32, false>(A, acc, mtile, iy, ix0, pb * 16, pb == 0, ss);
+    }
+  }
+  if constexpr (MODE == 1) {
+    ss = wave_sum(ss);
+    if (lane == 0) A.partial[(size_t)b * kWavesPerBlock + wave] = ss;
+  }
+}
+
 // H and the residual form are held to three waves per SIMD with one-part
 // operands (three 4-row workgroups of ~47 KB share a CU at 31 x 31
 // footprints) and to two with split operands (their second band-block
@@ -1219,8 +1318,18 @@ static bool use_lds(const psoam_plan* P, int mode) {
   return P->prec != PSOAM_FP32 && T.lds_ok;
 }
 
+static bool use_runs32(const psoam_plan* P, int mode) {
+  const BandTable& T = (mode == 2) ? P->adj : P->fwd;
+  return P->prec == PSOAM_FP32 && T.runs32;
+}
+
 static size_t band_blocks(const psoam_plan* P, int mode) {
   const BandTable& T = (mode == 2) ? P->adj : P->fwd;
+  if (use_runs32(P, mode)) {
+    const size_t nyb = (P->g.ny + kWavesPerBlock - 1) / kWavesPerBlock;
+    const size_t nxb = (P->g.nx + kLdsPos - 1) / kLdsPos;
+    return (size_t)T.n_mtiles * nyb * nxb;
+  }
   if (use_lds(P, mode)) {
     const size_t nyb = (P->g.ny + T.rows - 1) / T.rows;
     const size_t nxb = (P->g.nx + kLdsPos - 1) / kLdsPos;
@@ -1400,6 +1509,26 @@ hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* p
   A.nt = P->g.nt;
   const dim3 grid((unsigned)band_blocks(P, mode));
   (void)split;
+  if (use_runs32(P, mode)) {
+    LdsArgs L{};
+    L.lstart = T.d_lstart;
+    L.lgrp = T.d_lgrp;
+    L.la = T.d_la;
+    L.order = T.d_order;
+    L.rinfo = T.d_rinfo;
+    L.f = P->F;
+    L.nyb = (P->g.ny + kWavesPerBlock - 1) / kWavesPerBlock;
+    L.nxb = (P->g.nx + kLdsPos - 1) / kLdsPos;
+    L.la_bytes = (int)((size_t)(T.l_chunks + kRunMax) * kWaveLanes * sizeof(float));
+    const dim3 blk(64 * kWavesPerBlock);
+    switch (mode) {
+      case 0: hipLaunchKernelGGL(band32_run<0>, grid, blk, 0, s, A, L); break;
+      case 1: hipLaunchKernelGGL(band32_run<1>, grid, blk, 0, s, A, L); break;
+      case 2: hipLaunchKernelGGL(band32_run<2>, grid, blk, 0, s, A, L); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   if (use_lds(P, mode)) {
     switch (mode) {
       case 0: return launch_band_lds<0>(P, T, A, grid, s);

@@ -191,6 +191,7 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
     const size_t nc = (n_chunks > 0 ? (size_t)n_chunks : 1) + (size_t)pad;
     if (!half) {
       PSOAM_HIP(hipMalloc(hi_out, sizeof(float) * 64 * nc));
+      PSOAM_HIP(hipMemset(*hi_out, 0, sizeof(float) * 64 * nc));
       if (n_chunks)
         PSOAM_HIP(hipMemcpy(*hi_out, vals.data(), sizeof(float) * 64 * n_chunks, hipMemcpyHostToDevice));
       return PSOAM_OK;
@@ -256,7 +257,13 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
     if (n_chunks) PSOAM_HIP(hipMemcpy(T.d_off, off.data(), sizeof(int) * 4 * n_chunks, hipMemcpyHostToDevice));
     if (int rc = upload_vals(vals, n_chunks, &T.d_a, &T.d_a_lo, 0)) return rc;
   }
-  if (!half) return PSOAM_OK;
+  // FP32 plans use the runs below with the global-operand run kernel
+  // (PSOAM_FP32_RUNS=0 or PSOAM_BAND_GLOBAL=1 keeps them on the per-tile kernel)
+  if (!half) {
+    const char* e = std::getenv("PSOAM_FP32_RUNS");
+    const char* gl = std::getenv("PSOAM_BAND_GLOBAL");
+    if ((e && e[0] == '0') || (gl && gl[0] == '1')) return PSOAM_OK;
+  }
 
   // ---- packing 2: runs per (tile, dy) for the LDS-staged kernel.
   // A run holds m consecutive chunks whose 4 groups keep their octet while
@@ -341,6 +348,57 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   T.max_runs = 0;
   for (int tile = 0; tile < n_mt; ++tile)
     T.max_runs = std::max(T.max_runs, rstart[(size_t)(tile + 1) * F] - rstart[(size_t)tile * F]);
+  // the run tables on the device: per (tile, dy) first run, per run its four
+  // group words and (length, first chunk), the tile order, the band values
+  auto upload_runs = [&]() -> int {
+    std::vector<float> lvals((size_t)l_chunks * 64 * gw, 0.0f);
+    {
+      // chunk -> tile for the band fill
+      std::vector<int> chunk_tile(l_chunks, 0);
+      for (int tile = 0; tile < n_mt; ++tile)
+        for (int jy = 0; jy < F; ++jy) {
+          const size_t key = (size_t)tile * F + jy;
+          for (int r = rstart[key]; r < rstart[key + 1]; ++r)
+            for (int c = rcb[r]; c < rcb[r] + rlen[r]; ++c) chunk_tile[c] = tile;
+        }
+      for (int c = 0; c < l_chunks; ++c)
+        for (int gi = 0; gi < 4; ++gi) {
+          const Group& G = lgroups[(size_t)c * 4 + gi];
+          if (G.jy >= 0) fill(lvals, c, gi, G, chunk_tile[c]);
+        }
+    }
+    const size_t nr = std::max<size_t>(rlen.size(), 1);
+    PSOAM_HIP(hipMalloc(&T.d_lstart, sizeof(int) * rstart.size()));
+    PSOAM_HIP(hipMemcpy(T.d_lstart, rstart.data(), sizeof(int) * rstart.size(), hipMemcpyHostToDevice));
+    PSOAM_HIP(hipMalloc(&T.d_lgrp, sizeof(uint32_t) * 4 * nr));
+    if (!rgrp.empty())
+      PSOAM_HIP(hipMemcpy(T.d_lgrp, rgrp.data(), sizeof(uint32_t) * rgrp.size(), hipMemcpyHostToDevice));
+    {
+      std::vector<int> rinfo(2 * nr, 0);  // (length, first chunk) per run
+      for (size_t r = 0; r < rlen.size(); ++r) {
+        rinfo[2 * r] = rlen[r];
+        rinfo[2 * r + 1] = rcb[r];
+      }
+      PSOAM_HIP(hipMalloc(&T.d_rinfo, sizeof(int) * rinfo.size()));
+      PSOAM_HIP(hipMemcpy(T.d_rinfo, rinfo.data(), sizeof(int) * rinfo.size(), hipMemcpyHostToDevice));
+    }
+    {
+      std::vector<int> order(n_mt);
+      for (int i = 0; i < n_mt; ++i) order[i] = i;
+      std::vector<long> work(n_mt, 0);
+      for (int t = 0; t < n_mt; ++t)
+        for (int r = rstart[(size_t)t * F]; r < rstart[(size_t)(t + 1) * F]; ++r) work[t] += rlen[r];
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+      PSOAM_HIP(hipMalloc(&T.d_order, sizeof(int) * n_mt));
+      PSOAM_HIP(hipMemcpy(T.d_order, order.data(), sizeof(int) * n_mt, hipMemcpyHostToDevice));
+    }
+    return upload_vals(lvals, l_chunks, &T.d_la, &T.d_la_lo, kRunMax);
+  };
+  if (!half) {
+    if (n_l >= 0xffff || F >= 0xffff) return PSOAM_OK;
+    T.runs32 = true;
+    return upload_runs();
+  }
   // staged row windows for a workgroup of `rows` output rows (waves): the
   // union of the octet ranges of the dy values j - r, r < rows
   auto windows = [&](int rows, std::vector<uint32_t>& win, int& max_oct) {
@@ -430,51 +488,9 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   T.lds_ok = n_l < 0xffff && F < 0xffff && (rows == 8 ? lds8 : lds4) <= (size_t)kLdsMaxBytes &&
              !(force_global && force_global[0] == '1');
   if (!T.lds_ok) return PSOAM_OK;
-  std::vector<float> lvals((size_t)l_chunks * 64 * gw, 0.0f);
-  {
-    // chunk -> tile for the band fill
-    std::vector<int> chunk_tile(l_chunks, 0);
-    for (int tile = 0; tile < n_mt; ++tile)
-      for (int jy = 0; jy < F; ++jy) {
-        const size_t key = (size_t)tile * F + jy;
-        for (int r = rstart[key]; r < rstart[key + 1]; ++r)
-          for (int c = rcb[r]; c < rcb[r] + rlen[r]; ++c) chunk_tile[c] = tile;
-      }
-    for (int c = 0; c < l_chunks; ++c)
-      for (int gi = 0; gi < 4; ++gi) {
-        const Group& G = lgroups[(size_t)c * 4 + gi];
-        if (G.jy >= 0) fill(lvals, c, gi, G, chunk_tile[c]);
-      }
-  }
-  const size_t nr = std::max<size_t>(rlen.size(), 1);
-  PSOAM_HIP(hipMalloc(&T.d_lstart, sizeof(int) * rstart.size()));
-  PSOAM_HIP(hipMemcpy(T.d_lstart, rstart.data(), sizeof(int) * rstart.size(), hipMemcpyHostToDevice));
-  PSOAM_HIP(hipMalloc(&T.d_lgrp, sizeof(uint32_t) * 4 * nr));
-  if (!rgrp.empty())
-    PSOAM_HIP(hipMemcpy(T.d_lgrp, rgrp.data(), sizeof(uint32_t) * rgrp.size(), hipMemcpyHostToDevice));
-  {
-    std::vector<int> rinfo(2 * nr, 0);  // (length, first chunk) per run
-    for (size_t r = 0; r < rlen.size(); ++r) {
-      rinfo[2 * r] = rlen[r];
-      rinfo[2 * r + 1] = rcb[r];
-    }
-    PSOAM_HIP(hipMalloc(&T.d_rinfo, sizeof(int) * rinfo.size()));
-    PSOAM_HIP(hipMemcpy(T.d_rinfo, rinfo.data(), sizeof(int) * rinfo.size(), hipMemcpyHostToDevice));
-  }
-  {
-    std::vector<int> order(n_mt);
-    for (int i = 0; i < n_mt; ++i) order[i] = i;
-    std::vector<long> work(n_mt, 0);
-    for (int t = 0; t < n_mt; ++t)
-      for (int r = rstart[(size_t)t * F]; r < rstart[(size_t)(t + 1) * F]; ++r) work[t] += rlen[r];
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
-    PSOAM_HIP(hipMalloc(&T.d_order, sizeof(int) * n_mt));
-    PSOAM_HIP(hipMemcpy(T.d_order, order.data(), sizeof(int) * n_mt, hipMemcpyHostToDevice));
-  }
   PSOAM_HIP(hipMalloc(&T.d_win, sizeof(uint32_t) * win.size()));
   PSOAM_HIP(hipMemcpy(T.d_win, win.data(), sizeof(uint32_t) * win.size(), hipMemcpyHostToDevice));
-  if (int rc = upload_vals(lvals, l_chunks, &T.d_la, &T.d_la_lo, kRunMax)) return rc;
-  return PSOAM_OK;
+  return upload_runs();
 }
 
 static void free_table(BandTable& T) {
