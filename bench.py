@@ -143,12 +143,15 @@ def headline_inputs(torch, pk, cfg, synth):
 
 def run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam_l1, prec,
              steps, warmup, reps, separable=False, full_solve=False, v0=None, tvs=False,
-             tune=False):
+             tune=False, paper_stop=False):
     """Times one precision on one workload: optionally the full K1-iteration
     solve with its power iteration (first; alpha1 <= 0 takes the step from it),
     isolated applies, the band kernels alone (HIP events), `steps` solver
     steps after `warmup`, optionally the steps with the TV(S c) term.  tune:
-    the plan's launch shapes chosen by the autotuner (its report kept)."""
+    the plan's launch shapes chosen by the autotuner (its report kept).
+    paper_stop: the full solve again with the stopping thresholds of the
+    paper's experiments (eps1 1e-8, eps2 1e-4, K1 as the cap), tested on the
+    device."""
     t_plan = time.perf_counter()
     plan = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=prec, separable=separable, tune=tune)
     info = plan.stats()
@@ -170,6 +173,19 @@ def run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, alpha1, lam_tv, lam
         torch.cuda.synchronize()
         out["solve_s"] = time.perf_counter() - t1
         out["lambda_max"] = st_full["lambda_max"]
+        if paper_stop:
+            c_tol = torch.zeros(cfg.c_shape, dtype=torch.float32, device="cuda")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, st_tol = plan.solve(p_t, c=c_tol, lambda_tv=lam_tv, lambda_l1=lam_l1, k1=cfg.k1,
+                                   k2=cfg.k2, alpha1=0.0, n_power=30, v0=v0_t, eps1=1e-8,
+                                   eps2=1e-4, device_stop=True)
+            torch.cuda.synchronize()
+            out["solve_tol"] = {"eps1": 1e-8, "eps2": 1e-4, "k1_cap": cfg.k1,
+                                "iterations": st_tol["iterations"],
+                                "seconds": time.perf_counter() - t1,
+                                "stopping_tests": "on the device (device_stop)"}
+            del c_tol
         if alpha1 <= 0.0:
             alpha1 = st_full["alpha1"]
     out["alpha1"] = alpha1
@@ -634,7 +650,7 @@ def main(argv=None):
     log(f"[bench] {cfg.name} {args.prec}: full solve, applies, kernels, steps")
     res = run_prec(torch, pk, cfg, t0, taps, phi, sp, c_true, p_t, 0.0, lam_tv, lam_l1, args.prec,
                    args.steps, args.warmup, reps, full_solve=True, v0=v0, tvs=not big,
-                   tune=not args.no_tune)
+                   tune=not args.no_tune, paper_stop=True)
     alpha1 = res["alpha1"]
     runs = {args.prec: res}
     others = [] if args.headline_only else [q for q in args.compare.split(",") if q and q != args.prec]
@@ -693,6 +709,7 @@ def main(argv=None):
                      "traffic_source": traffic_src},
         "cpu_baseline": None,
         "fista_s_to_tol": res["solve_s"], "fista_iterations": cfg.k1,
+        "fista_paper_stopping": res.get("solve_tol"),
         "power_iteration": {"steps": 30, "start": "seeded Gaussian",
                             "lambda_max": res["lambda_max"], "alpha1": alpha1},
         "band_fill": info["useful_macs"][0] / max(1, info["executed_macs"][0]),

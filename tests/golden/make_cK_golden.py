@@ -32,11 +32,15 @@ if ROOT not in sys.path:
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
-# name: (base workload, crop side, K1, K2)
+# name: (base workload, crop side, K1, K2); "C4_<i>" is instance i of the
+# batched uneven family
 CASES = {
     "C2_crop24_k2_20": ("C2", 24, 20, 20),
     "C2_crop24_k2_50": ("C2", 24, 20, 50),
     "C5_crop16_k2_50": ("C5", 16, 20, 50),
+    "C4_3_crop12": ("C4_3", 12, 20, 20),
+    "C4_4_crop12": ("C4_4", 12, 20, 20),
+    "C4_13_crop12": ("C4_13", 12, 20, 20),
 }
 N_POWER = 30
 JSON = os.path.join(HERE, "cK_golden.json")
@@ -44,7 +48,8 @@ JSON = os.path.join(HERE, "cK_golden.json")
 
 def case_config(name: str):
     base, side, k1, k2 = CASES[name]
-    cfg = synth.CONFIGS[base].crop(side, side, name=name)
+    full = synth.c4_instance(int(base[3:])) if base.startswith("C4_") else synth.CONFIGS[base]
+    cfg = full.crop(side, side, name=name)
     return cfg, k1, k2
 
 

@@ -1,9 +1,10 @@
 """Reconstructed concentrations against the FP64 oracle's c_K on lateral crops
 of the larger workloads' geometry (full depth, pulses, samples, footprint):
 128 x 128 x 64-geometry crops of 24 x 24 scans with K2 = 20 and 50 dual steps,
-and a 320 x 320 x 128-geometry crop (40 pulses, Nt 512, footprint 51 x 51) of
-16 x 16 scans with K2 = 50, each after K1 = 20 solver iterations
-(Alg. alg:prox-outer, TV + l1 + nonnegativity).
+a 320 x 320 x 128-geometry crop (40 pulses, Nt 512, footprint 51 x 51) of
+16 x 16 scans with K2 = 50, and 12 x 12-scan crops of three instances of the
+batched uneven family (solved together by psoam_solve_batch), each after
+K1 = 20 solver iterations (Alg. alg:prox-outer, TV + l1 + nonnegativity).
 
 The reference c_K, the step alpha1 (the oracle's power iteration) and the
 weights were written by tests/golden/make_cK_golden.py from the oracle alone;
@@ -71,5 +72,38 @@ def test_concentrations_match_oracle(name, prec):
     plan.close()
 
 
+BATCH = ["C4_3_crop12", "C4_4_crop12", "C4_13_crop12"]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_batched_family_crops_match_oracle(prec):
+    """Crops of three uneven instances (depths 77, 59, 89; 21, 48, 29 pulses;
+    2, 2, 3 species; Nt 384, 352, 320) solved in one psoam_solve_batch call
+    (per-problem streams, captured iteration pairs), twice, each c_K against
+    its stored oracle c_K."""
+    torch = torch_cuda()
+    import paper_2510_23739_amd as pk
+    plans, ps, opts, refs = [], [], [], []
+    for name in BATCH:
+        meta = TABLE[name]
+        cfg, p, t0, taps, phi, sp, ref = _case(name)
+        plans.append(lib_plan(cfg, t0, taps, phi, sp, prec))
+        ps.append(torch.from_numpy(p).cuda())
+        opts.append(dict(lambda_tv=meta["lambda_tv"], lambda_l1=meta["lambda_l1"], k1=meta["k1"],
+                         k2=meta["k2"], alpha1=meta["alpha1"]))
+        refs.append(ref)
+    for call in range(2):
+        cs = [torch.zeros(pl.c_shape, dtype=torch.float32, device="cuda") for pl in plans]
+        stats = pk.solve_batch(plans, ps, cs, opts)
+        torch.cuda.synchronize()
+        for name, c, st, ref, o in zip(BATCH, cs, stats, refs, opts):
+            e = oracle.rel_err(c.cpu().numpy(), ref)
+            say(f"[golden] batch call {call} {name} {prec}: c_K rel err {e:.3e}")
+            assert st["iterations"] == o["k1"]
+            assert e <= TOL_C[prec]
+    for pl in plans:
+        pl.close()
+
+
 def test_golden_cases_present():
-    assert {"C2_crop24_k2_20", "C2_crop24_k2_50", "C5_crop16_k2_50"} <= set(CASES)
+    assert {"C2_crop24_k2_20", "C2_crop24_k2_50", "C5_crop16_k2_50"} | set(BATCH) <= set(CASES)
