@@ -394,30 +394,34 @@ typedef struct {
   int32_t h_loaders;     /* loader waves beside H's eight contracting waves (0 or 4) */
   int32_t tv_tile[4];    /* tile of the TV dual step: y, x, z extent and threads per block */
   double tv_ms, tv_ms_default;  /* one TV dual step with the chosen / the default tile */
+  int32_t fp32_runs[2];  /* FP32 plans: 1 when H (H^T) runs the run-packed kernel, 0 per-tile */
 } psoam_tune_report;
 
 /* psoam_plan_create with the launch shapes chosen by measurement: for a
  * 16-bit plan of the general form it builds the plan the built-in rules
  * choose and the alternatives that fit (4 or 8 output rows per workgroup for
  * H, with or without four loader waves at 8 rows; 4 or 8 rows and operand
- * shift 0 or 4 for H^T), times each band kernel's solver form on `stream`
+ * shift 0 or 4 for H^T), for an FP32 plan the one with the per-tile instead
+ * of the run-packed kernel, times each band kernel's solver form on `stream`
  * (HIP events, one warm-up and three timed launches on the zeroed operands),
  * times the TV dual step on the plan's grid with each tile shape of the
  * kernel's list (8x8x32 with 512 threads, 4x8x32/256, 4x16x32/512,
  * 4x8x64/512, 8x8x32/1024; one warm-up and ten steps), and returns the plan
- * with the fastest H, H^T and TV step.  Results do not depend on the choice
- * (the same products are summed in the same order; every TV output is the
- * same expression whatever the tile).  The choice is cached per process and
- * on disk, keyed by the device (architecture and compute units), the
- * geometry, the precision and a hash of the impulse-response table; the disk
- * cache is the file named by the environment variable PSOAM_TUNE_CACHE
- * (empty: no disk cache), else $HOME/.cache/psoam/tune.txt, one line per
- * choice, appended after each tuning (a file that cannot be read or written
- * is skipped silently).  A call served from a cache only builds the plan.
- * FP32 and separable plans have nothing to tune and are built directly.  For
- * callers who create a plan once and apply it many times: tuning builds up
- * to seven plans (about 0.25 s at 128 x 128 x 64).  `report` may be null.
- * Errors as psoam_plan_create; synchronises `stream`. */
+ * with the fastest H, H^T and TV step.  Rows, loader waves and TV tiles do
+ * not change results (the same products and sums in the same order);
+ * another H^T operand shift or the other FP32 kernel can regroup the band's
+ * entries and so the summation order (rounding-level differences).  The
+ * choice is cached per process and on disk, keyed by the device
+ * (architecture and compute units), the geometry, the precision and a hash
+ * of the impulse-response table; the disk cache is the file named by the
+ * environment variable PSOAM_TUNE_CACHE (empty: no disk cache), else
+ * $HOME/.cache/psoam/tune.txt, one line per choice, appended after each
+ * tuning (a file that cannot be read or written is skipped silently).  A
+ * call served from a cache only builds the plan.  Separable plans have
+ * nothing to tune and are built directly.  For callers who create a plan
+ * once and apply it many times: tuning builds up to seven plans (about
+ * 0.25 s at 128 x 128 x 64).  `report` may be null.  Errors as
+ * psoam_plan_create; synchronises `stream`. */
 int psoam_plan_create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
                             const int32_t* sir_t0, const float* sir_taps, int32_t sir_w,
                             int32_t prec, void* stream, psoam_plan** out,

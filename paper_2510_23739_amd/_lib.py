@@ -53,7 +53,8 @@ class TuneReport(C.Structure):
                 ("h_ms", C.c_double), ("ht_ms", C.c_double),
                 ("h_ms_default", C.c_double), ("ht_ms_default", C.c_double),
                 ("h_loaders", C.c_int32), ("tv_tile", C.c_int32 * 4),
-                ("tv_ms", C.c_double), ("tv_ms_default", C.c_double)]
+                ("tv_ms", C.c_double), ("tv_ms_default", C.c_double),
+                ("fp32_runs", C.c_int32 * 2)]
 
 
 EXPORTS = {

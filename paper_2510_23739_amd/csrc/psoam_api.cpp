@@ -793,13 +793,14 @@ namespace {
 // shift, H's loader waves, and the tile of the TV dual step.  Measured per
 // process and cached in memory and on disk by device, geometry, precision
 // and a hash of the impulse-response table.
-constexpr int kTuneVersion = 2;  // bump when the kernels or the choices change meaning
+constexpr int kTuneVersion = 3;  // bump when the kernels or the choices change meaning
 
 struct Shape {
   int h_rows = 0, ht_rows = 0, tsh = 0, h_loadw = 0, tv = 0;
+  int runs_h = 0, runs_ht = 0;  // FP32: run-packed (1) or per-tile (0) kernel
   bool operator==(const Shape& o) const {
     return h_rows == o.h_rows && ht_rows == o.ht_rows && tsh == o.tsh && h_loadw == o.h_loadw &&
-           tv == o.tv;
+           tv == o.tv && runs_h == o.runs_h && runs_ht == o.runs_ht;
   }
 };
 
@@ -842,7 +843,7 @@ std::string tune_file() {
   return std::string(home) + "/.cache/psoam/tune.txt";
 }
 
-// the last line "key<TAB>h_rows ht_rows tsh h_loadw tv" of the file for key
+// the last line "key<TAB>h_rows ht_rows tsh h_loadw tv runs_h runs_ht" of the file for key
 bool disk_lookup(const std::string& key, Shape& out) {
   const std::string path = tune_file();
   if (path.empty()) return false;
@@ -855,8 +856,8 @@ bool disk_lookup(const std::string& key, Shape& out) {
     if (!tab || (size_t)(tab - line) != key.size() || key.compare(0, key.size(), line, key.size()))
       continue;
     Shape s;
-    if (std::sscanf(tab + 1, "%d %d %d %d %d", &s.h_rows, &s.ht_rows, &s.tsh, &s.h_loadw,
-                    &s.tv) == 5 &&
+    if (std::sscanf(tab + 1, "%d %d %d %d %d %d %d", &s.h_rows, &s.ht_rows, &s.tsh, &s.h_loadw,
+                    &s.tv, &s.runs_h, &s.runs_ht) == 7 &&
         s.tv >= 0 && s.tv < tv_tile_count()) {
       out = s;
       found = true;
@@ -874,8 +875,8 @@ void disk_store(const std::string& key, const Shape& s) {
     if (path[i] == '/') (void)::mkdir(path.substr(0, i).c_str(), 0755);
   std::FILE* f = std::fopen(path.c_str(), "a");
   if (!f) return;
-  std::fprintf(f, "%s\t%d %d %d %d %d\n", key.c_str(), s.h_rows, s.ht_rows, s.tsh, s.h_loadw,
-               s.tv);
+  std::fprintf(f, "%s\t%d %d %d %d %d %d %d\n", key.c_str(), s.h_rows, s.ht_rows, s.tsh,
+               s.h_loadw, s.tv, s.runs_h, s.runs_ht);
   std::fclose(f);
 }
 
@@ -886,6 +887,8 @@ Shape shape_of(const psoam_plan* P) {
   s.tsh = P->tsh;
   s.h_loadw = P->fwd.lds_ok && P->fwd.loadw > 0 ? 1 : 0;
   s.tv = P->tv_tile;
+  s.runs_h = P->fwd.runs32 ? 1 : 0;
+  s.runs_ht = P->adj.runs32 ? 1 : 0;
   return s;
 }
 
@@ -943,7 +946,9 @@ int time_tv(psoam_plan* P, hipStream_t s, double* ms) {
 int build_shaped(const psoam_geom* g, const psoam_species* sp, const float* phi,
                  const int32_t* t0, const float* taps, int32_t sir_w, int32_t prec,
                  hipStream_t s, const Shape& want, psoam_plan** out) {
-  set_tune_choice(want.h_rows, want.ht_rows, want.tsh, want.h_rows ? want.h_loadw : -1);
+  const bool fp32 = prec == PSOAM_FP32;
+  set_tune_choice(want.h_rows, want.ht_rows, want.tsh, want.h_rows ? want.h_loadw : -1,
+                  fp32 ? want.runs_h : -1, fp32 ? want.runs_ht : -1);
   const int rc = create_plan(g, sp, phi, t0, taps, sir_w, prec, s, out);
   clear_tune_choice();
   if (rc == PSOAM_OK) (*out)->tv_tile = want.tv;
@@ -961,6 +966,8 @@ int create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
     r.ht_shift = got.tsh;
     r.h_loaders = got.h_loadw ? 4 : 0;
     tv_tile_dims(got.tv, r.tv_tile);
+    r.fp32_runs[0] = got.runs_h;
+    r.fp32_runs[1] = got.runs_ht;
     if (rep) *rep = r;
     *out = P;
     return PSOAM_OK;
@@ -969,7 +976,7 @@ int create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
   *out = nullptr;
   if (!g || !sp || !phi || !t0 || !taps) return fail(PSOAM_EINVAL, "plan_create_tuned: NULL argument");
   psoam_plan* P = nullptr;
-  if (g->separable != 0 || prec == PSOAM_FP32) {
+  if (g->separable != 0) {
     if (int rc = create_plan(g, sp, phi, t0, taps, sir_w, prec, s, &P)) return rc;
     return done(P);
   }
@@ -1003,8 +1010,9 @@ int create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
   const Shape base = shape_of(P);
   double h_best = 0.0, ht_best = 0.0, tv_best = 0.0;
   int rc = PSOAM_OK;
-  if (base.h_rows) rc = time_band(P, 0, s, &h_best);
-  if (rc == PSOAM_OK && base.ht_rows) rc = time_band(P, 1, s, &ht_best);
+  const bool fp32 = prec == PSOAM_FP32;
+  if (base.h_rows || fp32) rc = time_band(P, 0, s, &h_best);
+  if (rc == PSOAM_OK && (base.ht_rows || fp32)) rc = time_band(P, 1, s, &ht_best);
   if (rc == PSOAM_OK) rc = time_tv(P, s, &tv_best);  // the default tile
   r.tv_ms_default = tv_best;
   Shape best = base;
@@ -1039,18 +1047,37 @@ int create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
       for (int tsh : {0, 4})
         if (rows != base.ht_rows || tsh != base.tsh)
           alts.push_back({Shape{base.h_rows, rows, tsh, base.h_loadw, base.tv}, 1});
+  if (fp32 && (base.runs_h || base.runs_ht)) {
+    // the other FP32 kernel, for both directions at once (timed on each)
+    Shape o = base;
+    o.runs_h = base.runs_h ? 0 : 1;
+    o.runs_ht = base.runs_ht ? 0 : 1;
+    alts.push_back({o, 2});
+  }
   for (const auto& a : alts) {
     psoam_plan* Q = nullptr;
     if ((rc = build_shaped(g, sp, phi, t0, taps, sir_w, prec, s, a.first, &Q))) break;
     const Shape got = shape_of(Q);
-    double ms = 0.0;
+    double ms = 0.0, ms2 = 0.0;
     if (got == a.first) {  // it fitted
-      rc = time_band(Q, a.second, s, &ms);
+      rc = time_band(Q, a.second == 2 ? 0 : a.second, s, &ms);
+      if (rc == PSOAM_OK && a.second == 2) rc = time_band(Q, 1, s, &ms2);
       ++r.candidates;
     }
     free_plan(Q);
     if (rc != PSOAM_OK) break;
     if (!(got == a.first)) continue;
+    if (a.second == 2) {
+      if (ms < h_best) {
+        h_best = ms;
+        best.runs_h = a.first.runs_h;
+      }
+      if (ms2 < ht_best) {
+        ht_best = ms2;
+        best.runs_ht = a.first.runs_ht;
+      }
+      continue;
+    }
     if (a.second == 0 && ms < h_best) {
       h_best = ms;
       best.h_rows = a.first.h_rows;
@@ -1076,7 +1103,7 @@ int create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
     disk_store(key, best);
   }
   if (best.h_rows == base.h_rows && best.ht_rows == base.ht_rows && best.tsh == base.tsh &&
-      best.h_loadw == base.h_loadw) {
+      best.h_loadw == base.h_loadw && best.runs_h == base.runs_h && best.runs_ht == base.runs_ht) {
     P->tv_tile = best.tv;
     return done(P);
   }

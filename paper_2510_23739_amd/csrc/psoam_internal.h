@@ -178,10 +178,12 @@ namespace psoam {
 
 // Launch-shape choice for the next plan built on this thread (the
 // autotuner's lever): output rows per staged workgroup for H (rows_fwd) and
-// H^T (rows_adj), 4 or 8, the H^T operand shift, 0 or 4, and H's loader
-// waves, 0 (off) or 1 (on where they can run); any other value leaves that
-// choice to the plan's own rules.  A choice that does not fit is ignored.
-void set_tune_choice(int rows_fwd, int rows_adj, int tsh, int loadw_fwd);
+// H^T (rows_adj), 4 or 8, the H^T operand shift, 0 or 4, H's loader
+// waves, 0 (off) or 1 (on where they can run), and for FP32 plans the kernel
+// of H and of H^T, 0 (per-tile) or 1 (run-packed); any other value leaves
+// that choice to the plan's own rules.  A choice that does not fit is ignored.
+void set_tune_choice(int rows_fwd, int rows_adj, int tsh, int loadw_fwd, int runs_fwd = -1,
+                     int runs_adj = -1);
 void clear_tune_choice();
 
 // Device stop gate of the calling thread: while a solve with device-side

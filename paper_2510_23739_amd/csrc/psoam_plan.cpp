@@ -26,6 +26,7 @@ struct TuneChoice {
   int rows[2] = {0, 0};
   int tsh = -1;
   int loadw = -1;  // H's loader waves: 0 off, 1 on where they can run, else the rules
+  int runs[2] = {-1, -1};  // FP32: 0 per-tile kernel, 1 run kernel, else the rules
 };
 thread_local TuneChoice g_tune;
 
@@ -68,11 +69,14 @@ struct Group {
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-void set_tune_choice(int rows_fwd, int rows_adj, int tsh, int loadw_fwd) {
+void set_tune_choice(int rows_fwd, int rows_adj, int tsh, int loadw_fwd, int runs_fwd,
+                     int runs_adj) {
   g_tune.rows[0] = rows_fwd;
   g_tune.rows[1] = rows_adj;
   g_tune.tsh = tsh;
   g_tune.loadw = loadw_fwd;
+  g_tune.runs[0] = runs_fwd;
+  g_tune.runs[1] = runs_adj;
 }
 
 void clear_tune_choice() { g_tune = TuneChoice(); }
@@ -263,6 +267,7 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
     const char* e = std::getenv("PSOAM_FP32_RUNS");
     const char* gl = std::getenv("PSOAM_BAND_GLOBAL");
     if ((e && e[0] == '0') || (gl && gl[0] == '1')) return PSOAM_OK;
+    if (g_tune.runs[dir] == 0) return PSOAM_OK;  // the autotuner's choice
   }
 
   // ---- packing 2: runs per (tile, dy) for the LDS-staged kernel.

@@ -69,7 +69,7 @@ def test_tuned_plan_matches_default(which, prec):
     again = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=prec, tune=True)
     r2 = again.tune_report
     assert r2["from_cache"] == 1 and r2["candidates"] == 0
-    keys = ("h_rows", "ht_rows", "ht_shift", "h_loaders", "tv_tile")
+    keys = ("h_rows", "ht_rows", "ht_shift", "h_loaders", "tv_tile", "fp32_runs")
     assert [r2[k] for k in keys] == [rep[k] for k in keys]
     for p in (base, tuned, again):
         p.close()
@@ -95,7 +95,7 @@ def test_disk_cache_serves_a_later_creation(_tune_file, monkeypatch):
     again.close()
     say(f"   from the file: {r2}")
     assert r2["from_cache"] == 2 and r2["candidates"] == 0
-    keys = ("h_rows", "ht_rows", "ht_shift", "h_loaders", "tv_tile")
+    keys = ("h_rows", "ht_rows", "ht_shift", "h_loaders", "tv_tile", "fp32_runs")
     assert [r2[k] for k in keys] == [rep[k] for k in keys]
     # other inputs (another table): not in the file, so tuned afresh
     cfg2, t02, taps2, phi2, sp2 = ragged_cfg(13)
@@ -104,10 +104,30 @@ def test_disk_cache_serves_a_later_creation(_tune_file, monkeypatch):
     other.close()
 
 
-def test_fp32_plan_is_built_untuned():
-    torch_cuda()
+@pytest.mark.parametrize("which", ["c1", "ragged"])
+def test_fp32_plan_tunes_its_kernel(which):
+    """FP32 plans: the tuner times the run-packed and the per-tile kernel for
+    H and H^T and the TV tiles; the tuned plan applies the same operator as
+    the default one up to the summation order of the other kernel."""
+    torch = torch_cuda()
     import paper_2510_23739_amd as pk
-    cfg, t0, taps, phi, sp = _inputs("ragged")
+    cfg, t0, taps, phi, sp = _inputs(which)
+    base = lib_plan(cfg, t0, taps, phi, sp, "fp32")
     p = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec="fp32", tune=True)
-    assert p.tune_report["candidates"] == 0 and p.tune_report["from_cache"] == 0
+    rep = p.tune_report
+    say(f"[tune] fp32 {which}: {rep}")
+    assert rep["h_rows"] == 0 and rep["ht_rows"] == 0
+    assert all(x in (0, 1) for x in rep["fp32_runs"]) and rep["tv_tile"] in TV_TILES
+    if not rep["from_cache"]:
+        assert rep["candidates"] >= 2 + len(TV_TILES) - 1
+        assert 0.0 < rep["h_ms"] <= rep["h_ms_default"]
+        assert 0.0 < rep["ht_ms"] <= rep["ht_ms_default"]
+    rng = np.random.default_rng(10)
+    c = torch.from_numpy(rng.standard_normal(cfg.c_shape).astype(np.float32)).cuda()
+    y = torch.from_numpy(rng.standard_normal(cfg.y_shape).astype(np.float32)).cuda()
+    e = [oracle.rel_err(p.apply_A(c).cpu().numpy(), base.apply_A(c).cpu().numpy()),
+         oracle.rel_err(p.apply_AT(y).cpu().numpy(), base.apply_AT(y).cpu().numpy())]
+    say(f"   tuned vs default: A {e[0]:.2e}  A^T {e[1]:.2e}")
+    assert max(e) <= 1e-6
+    base.close()
     p.close()
