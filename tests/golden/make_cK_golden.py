@@ -38,6 +38,7 @@ CASES = {
     "C2_crop24_k2_20": ("C2", 24, 20, 20),
     "C2_crop24_k2_50": ("C2", 24, 20, 50),
     "C5_crop16_k2_50": ("C5", 16, 20, 50),
+    "C3_crop16_k2_20": ("C3", 16, 20, 20),
     "C4_3_crop12": ("C4_3", 12, 20, 20),
     "C4_4_crop12": ("C4_4", 12, 20, 20),
     "C4_13_crop12": ("C4_13", 12, 20, 20),

@@ -2,7 +2,8 @@
 of the larger workloads' geometry (full depth, pulses, samples, footprint):
 128 x 128 x 64-geometry crops of 24 x 24 scans with K2 = 20 and 50 dual steps,
 a 320 x 320 x 128-geometry crop (40 pulses, Nt 512, footprint 51 x 51) of
-16 x 16 scans with K2 = 50, and 12 x 12-scan crops of three instances of the
+16 x 16 scans with K2 = 50, a 256 x 256 x 96-geometry crop (footprint 41 x 41,
+Nt 384) of 16 x 16 scans with K2 = 20, and 12 x 12-scan crops of three instances of the
 batched uneven family (solved together by psoam_solve_batch), each after
 K1 = 20 solver iterations (Alg. alg:prox-outer, TV + l1 + nonnegativity).
 
@@ -38,7 +39,8 @@ TOL_C = {"bf16": 1e-3, "fp16": 1e-3, "bf16_refined": 1e-3, "fp32": 1e-4, "bf16_s
          "fp16_split": 1e-4}
 PRECS = {"C2_crop24_k2_20": ["bf16", "fp16", "bf16_refined", "fp32", "bf16_split", "fp16_split"],
          "C2_crop24_k2_50": ["bf16", "fp32"],
-         "C5_crop16_k2_50": ["bf16", "fp16", "fp32", "bf16_split"]}
+         "C5_crop16_k2_50": ["bf16", "fp16", "fp32", "bf16_split"],
+         "C3_crop16_k2_20": ["bf16", "fp16", "fp32", "bf16_split", "fp16_split"]}
 
 _MEAS = {}
 
@@ -106,4 +108,5 @@ def test_batched_family_crops_match_oracle(prec):
 
 
 def test_golden_cases_present():
-    assert {"C2_crop24_k2_20", "C2_crop24_k2_50", "C5_crop16_k2_50"} | set(BATCH) <= set(CASES)
+    assert {"C2_crop24_k2_20", "C2_crop24_k2_50", "C5_crop16_k2_50",
+            "C3_crop16_k2_20"} | set(BATCH) <= set(CASES)
