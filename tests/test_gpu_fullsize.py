@@ -117,7 +117,7 @@ def test_c2_apply_AT_sampled(c2, prec):
     assert _check_AT(torch, c2, prec, cols) <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16_split", "fp32"])
 def test_c3_apply_A_and_AT_sampled(c3, prec):
     torch = torch_cuda()
     pts = _corners(256) + [(128, 128), (20, 230), (200, 61)]
