@@ -340,18 +340,24 @@ def scale_runs(torch, pk):
     del c, y, g
     torch.cuda.empty_cache()
     # batched family: 16 instances, BF16, 100 outer iterations each (K2 20),
-    # step from a 10-step power iteration, batch vs one-by-one
+    # step from a 10-step power iteration, batch vs one-by-one; every plan's
+    # launch shapes chosen by the autotuner (before the timed region)
     log("[bench] batched family")
-    plans, ps, opts = [], [], []
+    plans, ps, opts, choices = [], [], [], []
+    t_tune = time.perf_counter()
     for i in range(16):
         cfg = synth.c4_instance(i)
         t0, taps = synth.sir_table(cfg.nz, cfg.f, cfg.nt)
         plan = pk.Plan.from_config(cfg, synth.phi_depth(cfg.nz), synth.species(cfg.n_species), t0,
-                                   taps, prec="bf16")
+                                   taps, prec="bf16", tune=True)
+        r = plan.tune_report
+        choices.append([r["h_rows"], r["ht_rows"], r["ht_shift"], r["h_loaders"],
+                        "x".join(str(v) for v in r["tv_tile"])])
         rng = np.random.default_rng(cfg.seed)
         ps.append(torch.from_numpy(rng.standard_normal(cfg.y_shape, dtype=np.float32)).cuda())
         plans.append(plan)
         opts.append(dict(lambda_tv=1e-3, lambda_l1=1e-3, k1=cfg.k1, k2=20, n_power=10))
+    t_tune = time.perf_counter() - t_tune
     cs = [torch.zeros(pl.c_shape, dtype=torch.float32, device="cuda") for pl in plans]
     pk.solve_batch(plans, ps, cs, [dict(o, k1=2) for o in opts])   # warm-up
     torch.cuda.synchronize()
@@ -366,8 +372,11 @@ def scale_runs(torch, pk):
                  n_power=o["n_power"])
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t
-    out[f"batched_16_uneven_bf16_k1_{opts[0]['k1']}"] = {"batch_s": t_batch, "one_by_one_s": t_seq,
-                                                        "speedup": t_seq / t_batch}
+    out[f"batched_16_uneven_bf16_k1_{opts[0]['k1']}"] = {
+        "batch_s": t_batch, "one_by_one_s": t_seq, "speedup": t_seq / t_batch,
+        "autotuned_plans": {"seconds": t_tune,
+                            "choice_per_instance": "H rows, H^T rows, H^T shift, H loaders, TV tile",
+                            "choices": choices}}
     for pl in plans:
         pl.close()
     return out

@@ -26,6 +26,8 @@ def main():
     ap.add_argument("--prec", default="bf16")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--what", default="fwd,adj,tv")
+    ap.add_argument("--tune", action="store_true",
+                    help="launch shapes chosen by the autotuner (plain and batched plans)")
     ap.add_argument("--fact", action="store_true",
                     help="factorised acoustic operator (shell sums + impulse-response pass)")
     args = ap.parse_args()
@@ -53,7 +55,7 @@ def main():
                                   synth.spr_table(cfg.nz, cfg.f), eir, origin, dr, z_focus,
                                   t_focus, prec=args.prec)
     else:
-        plan = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=args.prec)
+        plan = pk.Plan.from_config(cfg, phi, sp, t0, taps, prec=args.prec, tune=args.tune)
     y = torch.empty(cfg.y_shape, dtype=torch.float32, device="cuda")
     g = torch.empty(cfg.c_shape, dtype=torch.float32, device="cuda")
     st = torch.cuda.current_stream()
@@ -69,7 +71,8 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / args.reps
 
-    out = {"config": cfg.name, "prec": args.prec, "factorised": args.fact, "stats": plan.stats()}
+    out = {"config": cfg.name, "prec": args.prec, "factorised": args.fact, "tuned": args.tune,
+           "stats": plan.stats()}
     what = args.what.split(",")
     if "mfma" in what:
         # dense BF16 matrix-core rate of this device: a loop of
@@ -136,7 +139,7 @@ def main():
             ci = synth.c4_instance(i)
             a0, a1 = synth.sir_table(ci.nz, ci.f, ci.nt)
             plans.append(pk.Plan.from_config(ci, synth.phi_depth(ci.nz), synth.species(ci.n_species),
-                                             a0, a1, prec=args.prec))
+                                             a0, a1, prec=args.prec, tune=args.tune))
             rng = np.random.default_rng(ci.seed)
             ps.append(torch.from_numpy(rng.standard_normal(ci.y_shape, dtype=np.float32)).cuda())
             opts.append(dict(lambda_tv=1e-3, lambda_l1=1e-3, k1=ci.k1, k2=20, n_power=10))
