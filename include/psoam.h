@@ -214,7 +214,13 @@ typedef struct {
   double eps1;             /* relative objective change stop; 0 disables */
   double eps2;             /* relative momentum-iterate change stop; 0 disables */
   double alpha1;           /* step; <= 0: 1/(1.01 * power-iteration estimate) */
-  int32_t n_power;         /* power iterations when alpha1 <= 0 (e.g. 30) */
+  int32_t n_power;         /* power iterations when alpha1 <= 0 (e.g. 30).  The
+                              estimate rises towards eig_max(A^T A) from below,
+                              so with few steps the step can exceed
+                              1/eig_max by a few percent where the top
+                              eigenvalues lie close together (the iteration
+                              stays stable; FISTA's O(1/k^2) bound assumes it
+                              does not); more steps close the gap */
   int32_t literal_momentum;/* 0: (t_k - 1)/t_{k+1}; 1: printed (t_k - 1)/(t_k + 1) */
   int32_t warm_inner;      /* 0: cold dual start every outer step; 1: warm */
   const float* v0;         /* device [S][Ny][Nx][Nz] power start, or NULL (constant) */
