@@ -793,7 +793,7 @@ namespace {
 // shift, H's loader waves, and the tile of the TV dual step.  Measured per
 // process and cached in memory and on disk by device, geometry, precision
 // and a hash of the impulse-response table.
-constexpr int kTuneVersion = 3;  // bump when the kernels or the choices change meaning
+constexpr int kTuneVersion = 4;  // bump when the kernels or the choices change meaning
 
 struct Shape {
   int h_rows = 0, ht_rows = 0, tsh = 0, h_loadw = 0, tv = 0;

@@ -680,7 +680,6 @@ __global__ __launch_bounds__(256) void band32(BandArgs A) {
 // (tile, dy); each group names (octet, dx), so the operand of position p is
 // the staged column p + dx.
 // --------------------------------------------------------------------------
-constexpr int kStageBatch = 16;
 
 struct LdsArgs {
   const int* lstart;       // [n_mtiles * F + 1]
@@ -800,38 +799,54 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   // it = (oi*XW + xi)*16 + nn is one 16-byte octet of pulse nn at column xi
   // of octet oi; nn = t%16 is fixed and (xi, oi) advance by NT/16 columns
   // per step (half blocks: 8 pulses per column, it = (oi*XW + xi)*8 + nn,
-  // nn = t%8, NT/8 columns per step).  Without loader waves every thread stages, kStageBatch loads in
-  // flight before their LDS writes.  The split forms stage the high and the
-  // low operand rows in two passes over the window (the same LDS tile):
-  // pass 0 adds hi(H) hi(q) + lo(H) hi(q), pass 1 adds hi(H) lo(q).
+  // nn = t%8, NT/8 columns per step).  Without loader waves every thread
+  // stages, with buffer loads that write LDS directly.  The split forms stage
+  // the high and the low operand rows in two passes over the window (the
+  // same LDS tile): pass 0 adds hi(H) hi(q) + lo(H) hi(q), pass 1 adds
+  // hi(H) lo(q).
   const int ps = (int)A.ps;
   const int row_bytes = A.xp * ps * (int)sizeof(E);
   const int dwrap = -XW * ps + A.kp * 8;
-  // issue the loads of items u0*NT + t, (u0+1)*NT + t, ... of staged row jr
-  // of pulse block pb_r (all unconditional: an item past the window still
-  // lies inside the padded row, and its value is never written to LDS)
-  auto issue = [&](V* tmp, int cnt, int u0, int jr, int pb_r, int pass_r) {
+  // A thread's walk over items u0*NT + t, (u0+1)*NT + t, ... of staged row
+  // jr of pulse block pb_r: the row's buffer, and per item its column xi and
+  // element offset off.  A step of cpt columns is qw whole octet windows and
+  // rw more columns, then at most one wrap into the next octet (selects, no
+  // branches).
+  struct Walk {
+    int xi, off, rw, dstep;
+  };
+  auto walk_start = [&](int u0, int jr, int pb_r, int pass_r, __amdgpu_buffer_rsrc_t& rq) {
     const bool hf = half_pb(pb_r);
     const int cpt = hf ? NT / 8 : NT / 16;  // columns per step
     const int obase_r = (int)(s_win[jr] >> 16);
-    const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
+    rq = __builtin_amdgcn_make_buffer_rsrc(
         (void*)((pass_r ? qlo : q) + (size_t)(iy0 + jr) * A.xp * A.ps), (short)0, row_bytes, kBufWord3);
-    int r2 = u0 * cpt + (hf ? st_id >> 3 : st_id >> 4);
-    int xi = r2 % XW, oi = r2 / XW;
-    int off = (ix0 + xi) * ps + ((obase_r + oi) * A.kp + pb_r * 16 + (st_id & (hf ? 7 : 15))) * 8;
-    // a step of cpt columns is qw whole octet windows and rw more columns,
-    // then at most one wrap into the next octet (selects, no branches)
-    const int qw = cpt / XW, rw = cpt - qw * XW;
-    const int dstep = rw * ps + qw * A.kp * 8;
+    const int r2 = u0 * cpt + (hf ? st_id >> 3 : st_id >> 4);
+    const int qw = cpt / XW;
+    Walk w;
+    w.xi = r2 % XW;
+    w.off = (ix0 + w.xi) * ps + ((obase_r + r2 / XW) * A.kp + pb_r * 16 + (st_id & (hf ? 7 : 15))) * 8;
+    w.rw = cpt - qw * XW;
+    w.dstep = w.rw * ps + qw * A.kp * 8;
+    return w;
+  };
+  auto walk_next = [&](Walk& w) {
+    w.xi += w.rw;
+    w.off += w.dstep;
+    const bool w1 = w.xi >= XW;
+    w.xi = w1 ? w.xi - XW : w.xi;
+    w.off = w1 ? w.off + dwrap : w.off;
+  };
+  // loader waves: cnt items into registers (all loads unconditional: an item
+  // past the window still lies inside the padded row, and its value is never
+  // written to LDS)
+  auto issue = [&](V* tmp, int cnt, int u0, int jr, int pb_r, int pass_r) {
+    __amdgpu_buffer_rsrc_t rq;
+    Walk w = walk_start(u0, jr, pb_r, pass_r, rq);
 #pragma unroll
     for (int u = 0; u < cnt; ++u) {
-      const int ob = off * (int)sizeof(E);
-      tmp[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rq, ob, 0, 0));
-      xi += rw;
-      off += dstep;
-      const bool w1 = xi >= XW;
-      xi = w1 ? xi - XW : xi;
-      off = w1 ? off + dwrap : off;
+      tmp[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rq, w.off * (int)sizeof(E), 0, 0));
+      walk_next(w);
     }
   };
   // a staged row is skipped when its window is empty or it lies past the
@@ -888,20 +903,24 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
       if (!staged(j)) continue;
       __syncthreads();  // the previous row's contractions are done with LDS
       if constexpr (LOADW == 0) {
+        // Every item of the row goes straight from global memory to LDS
+        // (buffer loads with the LDS destination: no registers, no LDS write
+        // instructions), all of a thread's items in flight at once.  A wave's
+        // 64 lanes fill 64 consecutive 16-byte slots, so item u*NT + t lands
+        // at slot u*NT + t as the LDS layout wants; lanes past the window
+        // are masked off and write nothing.
         const int items = ocnt * XW * (hf ? 8 : 16);
-        constexpr int NPRE = kStageBatch;
-        for (int u0 = 0; u0 * NT < items; u0 += NPRE) {
-          V tmp[NPRE];
-          issue(tmp, NPRE, u0, j, pb, pass);
-          // all of the batch has landed (the writes below are conditional, and
-          // a load left pending on a skipped path would stall the run loop)
-          __builtin_amdgcn_s_waitcnt(kVmcnt0);
-#pragma unroll
-          for (int u = 0; u < NPRE; ++u) {
-            const int it = (u0 + u) * NT + (int)threadIdx.x;
-            if (it < items) *(V*)(sh + it * 8) = tmp[u];
-          }
+        __amdgpu_buffer_rsrc_t rq;
+        Walk w = walk_start(0, j, pb, pass, rq);
+        const int wbase = __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63);
+        for (int u = 0; u * NT < items; ++u) {
+          if (u * NT + st_id < items)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rq, (__attribute__((address_space(3))) void*)(sh + (u * NT + wbase) * 8), 16,
+                w.off * (int)sizeof(E), 0, 0, 0);
+          walk_next(w);
         }
+        __builtin_amdgcn_s_waitcnt(kVmcnt0);  // this thread's items are in LDS
       }
       __syncthreads();  // row j is in LDS
       const int dy = j - wave;

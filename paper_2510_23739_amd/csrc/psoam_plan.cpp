@@ -460,17 +460,17 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   T.rows = rows;
   T.max_oct = rows == 8 ? mo8 : mo4;
   T.lds_bytes = (size_t)T.max_oct * XW * 16 * 8 * sizeof(uint16_t);
-  // Loader waves: with one 8-row workgroup per CU (LDS above half a CU's)
-  // nothing else hides the staging latency, so four more waves load the next
-  // row into registers during the current row's contractions (H and its
-  // residual form, one-part operands; 25 items per loader thread must cover
-  // the widest window).
+  // Loader waves: four more waves that load the next staged row into
+  // registers during the current row's contractions (H and its residual
+  // form, one 8-row workgroup per CU, one-part operands; 25 items per loader
+  // thread must cover the widest window).  Off by default: staging straight
+  // into LDS (buffer loads with the LDS destination, every item in flight at
+  // once) is faster on every workload measured; the autotuner still times
+  // them.
   T.loadw = 0;
   {
     const size_t items = (size_t)T.max_oct * XW * 16;
     const bool able = rows == 8 && !split && dir == 0 && items <= (size_t)25 * 256;
-    const bool alone = lds8 > (size_t)kLdsMaxBytes / 2;
-    T.loadw = (able && alone) ? 4 : 0;
     // PSOAM_LDS_LOADW=0 keeps the plain staging, =1 takes the loader waves
     // wherever they can run (tests and A/B timing run both)
     if (const char* e = std::getenv("PSOAM_LDS_LOADW")) {
