@@ -1134,13 +1134,14 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_pe
   }
 }
 
-// H and the residual form are held to three waves per SIMD with one-part
-// operands (three 4-row workgroups of ~47 KB share a CU at 31 x 31
-// footprints) and to two with split operands (their second band-block
-// buffer needs the registers) or with the row prefetch (one 8-row
-// workgroup per CU: its 256 registers hold the prefetched row).
+// H and the residual form are held to three waves per SIMD where three can
+// share it: 4-row workgroups with one-part operands (three of ~47 KB share a
+// CU at 31 x 31 footprints) and 8-row ones with loader waves (twelve waves).
+// An 8-row workgroup without loader waves runs two waves per SIMD whatever
+// its registers (a second one would need four), and split operands need the
+// registers for their second band-block buffer: these get 256.
 template <int PREC, bool SPLIT, int MODE, int ROWS, int LOADW>
-__global__ __launch_bounds__(64 * (ROWS + LOADW)) __attribute__((amdgpu_waves_per_eu(!SPLIT ? 3 : 2))) void band16_lds(
+__global__ __launch_bounds__(64 * (ROWS + LOADW)) __attribute__((amdgpu_waves_per_eu((SPLIT || (ROWS == 8 && LOADW == 0)) ? 2 : 3))) void band16_lds(
     BandArgs A, LdsArgs L) {
   band16_lds_body<PREC, SPLIT, MODE, ROWS, LOADW>(A, L);
 }
