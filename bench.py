@@ -92,6 +92,38 @@ def time_events(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def tv_bandwidth(torch, pk, plan, cfg, z_host):
+    """The TV prox's dual step (HBM-bound): per-step time from two prox_tv
+    calls of K2 and K2/5 dual steps on the same input (the difference holds
+    only dual steps, not the prox's set-up and final kernels), its
+    algorithmic bytes (40 per species-voxel: u_j, u_{j-1}, z in, u_{j+1} out)
+    per second, against a plain 1 GiB device copy timed in the same process
+    and against the 8 TB/s HBM figure."""
+    z = torch.from_numpy(z_host).cuda()
+    x = torch.empty_like(z)
+    nws = int(pk.load().psoam_prox_tv_ws_bytes(plan.handle)) // 4 + 64
+    ws = torch.empty(nws, dtype=torch.float32, device="cuda")
+    k_hi, k_lo = cfg.k2, max(1, cfg.k2 // 5)
+    t_hi = time_events(torch, lambda: plan.prox_tv(z, 0.01, k_hi, x=x, ws=ws), 3)
+    t_lo = time_events(torch, lambda: plan.prox_tv(z, 0.01, k_lo, x=x, ws=ws), 3)
+    step_ms = (t_hi - t_lo) / (k_hi - k_lo)
+    del z, x, ws
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    copy_ms = time_events(torch, lambda: b.copy_(a), 5)
+    del a, b
+    torch.cuda.empty_cache()
+    alg = 40.0 * cfg.n_species * cfg.nx * cfg.ny * cfg.nz
+    gbps = alg / (step_ms * 1e-3) / 1e9
+    copy_gbps = 2.0 * 4 * n / (copy_ms * 1e-3) / 1e9
+    return {"dual_step_ms": step_ms, "alg_bytes_per_step": alg, "achieved_GBps": gbps,
+            "copy_GBps_measured": copy_gbps, "frac_of_copy": gbps / copy_gbps,
+            "frac_of_8TBps": gbps / 8000.0,
+            "method": f"(t(prox_tv, K2={k_hi}) - t(prox_tv, K2={k_lo})) / {k_hi - k_lo}, "
+                      "HIP events; copy: 1 GiB torch copy_, read + write bytes"}
+
+
 def alg_flops(cfg, t0, taps):
     """Algorithmic flops of one H (or H^T) apply: 2 K times the number of
     (scan, voxel, sample) triples with a nonzero band entry whose voxel lies in
@@ -661,6 +693,7 @@ def main(argv=None):
                    args.steps, args.warmup, reps, full_solve=True, v0=v0, tvs=not big,
                    tune=not args.no_tune, paper_stop=True)
     alpha1 = res["alpha1"]
+    tvb = tv_bandwidth(torch, pk, res["plan"], cfg, c_true)
     runs = {args.prec: res}
     others = [] if args.headline_only else [q for q in args.compare.split(",") if q and q != args.prec]
     for q in others:
@@ -722,6 +755,7 @@ def main(argv=None):
         "power_iteration": {"steps": 30, "start": "seeded Gaussian",
                             "lambda_max": res["lambda_max"], "alpha1": alpha1},
         "band_fill": info["useful_macs"][0] / max(1, info["executed_macs"][0]),
+        "tv_prox_dual_step": tvb,
         "autotune": res.get("autotune"),
         "precisions": per_prec_rows(runs, flops, cfg),
     }
