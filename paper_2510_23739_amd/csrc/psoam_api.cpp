@@ -189,6 +189,7 @@ struct R3Bufs {
   float* u2[3];
   float* u3[3];
   float* w;
+  float* pq;  // projections of eta2 through the switching coefficients, [6][S][V]
 };
 
 // three dual sets and w carved from a 256-byte aligned block
@@ -206,11 +207,15 @@ R3Bufs r3_carve(const psoam_plan* P, void* base) {
     p += al(sv);
   }
   B.w = p;
+  p += al(sv);
+  B.pq = p;
   return B;
 }
 
 size_t r3_ws_bytes(const psoam_plan* P) {
-  return sizeof(float) * (3 * r3_set_floats(P) + (P->c_elems() + 63) / 64 * 64) + 256;
+  const size_t sv = P->c_elems();
+  return sizeof(float) * (3 * r3_set_floats(P) + (sv + 63) / 64 * 64 + (6 * sv + 63) / 64 * 64) +
+         256;
 }
 
 // x = prox of the full regulariser (TV of c, TV of S c, l1, then the final
@@ -225,7 +230,7 @@ int r3_prox_core(const psoam_plan* P, float* x, const float* z, const float th[3
   double bsum = 0.0;
   for (int b = 0; b < 3; ++b) bsum += (double)th[b] * th[b] * m[b];
   if (n_inner <= 0 || bsum == 0.0) {
-    PSOAM_HIP(launch_r3_w(P, x, z, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0f, 1, s));
+    PSOAM_HIP(launch_r3_w(P, x, z, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0f, 1, s));
     return PSOAM_OK;
   }
   float step[3];
@@ -238,18 +243,22 @@ int r3_prox_core(const psoam_plan* P, float* x, const float* z, const float th[3
     auto U1 = [&](int i) -> const float* { return i < 0 ? nullptr : B.u1[i]; };
     auto U2 = [&](int i) -> const float* { return i < 0 ? nullptr : B.u2[i]; };
     auto U3 = [&](int i) -> const float* { return i < 0 ? nullptr : B.u3[i]; };
-    PSOAM_HIP(launch_r3_w(P, B.w, z, U1(cur), U1(prev), U2(cur), U2(prev), U3(cur), U3(prev),
-                          (float)beta_prev, 0, s));
-    PSOAM_HIP(launch_r3_u(P, B.u1[nxt], B.u2[nxt], B.u3[nxt], B.w, U1(cur), U1(prev), U2(cur),
-                          U2(prev), U3(cur), U3(prev), (float)beta_prev, step, th, s));
-    double beta;
-    momentum_step(t, beta, literal);
+    // the momentum of the next step: its eta2 is projected by this step's update
+    double t_next = t, beta;
+    momentum_step(t_next, beta, literal);
+    const bool last = j == n_inner - 1;
+    PSOAM_HIP(launch_r3_w(P, B.w, z, U1(cur), U1(prev), cur < 0 ? nullptr : B.pq, U3(cur),
+                          U3(prev), (float)beta_prev, 0, s));
+    PSOAM_HIP(launch_r3_u(P, B.u1[nxt], B.u2[nxt], B.u3[nxt], B.pq, B.w, U1(cur), U1(prev),
+                          U2(cur), U2(prev), U3(cur), U3(prev), (float)beta_prev,
+                          last ? 0.0f : (float)beta, step, th, s));
+    t = t_next;
     beta_prev = beta;
     prev = cur;
     cur = nxt;
   }
-  PSOAM_HIP(launch_r3_w(P, x, z, B.u1[cur], nullptr, B.u2[cur], nullptr, B.u3[cur], nullptr, 0.0f,
-                        1, s));
+  // the last update projected u2 itself (no momentum)
+  PSOAM_HIP(launch_r3_w(P, x, z, B.u1[cur], nullptr, B.pq, B.u3[cur], nullptr, 0.0f, 1, s));
   return PSOAM_OK;
 }
 

@@ -273,14 +273,17 @@ hipError_t launch_f16_pmax(const psoam_plan* P, const float* p, hipStream_t s);
 //   u1' = clip(eta1 + step0 grad w), u2' = clip(eta2 + step1 grad S w),
 //   u3' = clip(eta3 + step2 w)  at radii theta[0..2]
 // duals u1 [3][S][V], u2 [3][ceil(K/4)][V][4] (four pulses per 16-byte
-// word), u3 [S][V]; eta from (current, previous)
+// word), u3 [S][V]; eta from (current, previous).  eta2 reaches w through
+// its projections pq [6][S][V] (null: eta2 = 0), which launch_r3_u writes
+// for the next step's eta2 (beta_next; 0 gives those of u2' itself).
 hipError_t launch_r3_w(const psoam_plan* P, float* out, const float* z, const float* u1c,
-                       const float* u1p, const float* u2c, const float* u2p, const float* u3c,
-                       const float* u3p, float beta, int clamp_out, hipStream_t s);
-hipError_t launch_r3_u(const psoam_plan* P, float* n1, float* n2, float* n3, const float* w,
-                       const float* u1c, const float* u1p, const float* u2c, const float* u2p,
-                       const float* u3c, const float* u3p, float beta, const float step[3],
-                       const float theta[3], hipStream_t s);
+                       const float* u1p, const float* pq, const float* u3c, const float* u3p,
+                       float beta, int clamp_out, hipStream_t s);
+hipError_t launch_r3_u(const psoam_plan* P, float* n1, float* n2, float* n3, float* pq,
+                       const float* w, const float* u1c, const float* u1p, const float* u2c,
+                       const float* u2p, const float* u3c, const float* u3p, float beta,
+                       float beta_next, const float step[3], const float theta[3],
+                       hipStream_t s);
 // separable form (n = Ny*Nx*Nt elements per volume; T [K][S] on the device):
 //   y[k] = sum_s T[k][s] h[s]           (expand)
 //   out[s] = sum_k T[k][s] y[k]         (contract)

@@ -1981,14 +1981,29 @@ __device__ __forceinline__ f32x4 eta4(const f32x4* __restrict__ uc, const f32x4*
 // ((d * ceil(K/4) + k / 4) * V + v) * 4 + k % 4, so a thread reads the duals
 // of four pulses with one 16-byte load (consecutive voxels stay consecutive
 // 16-byte words); the padding pulses of the last group are kept at zero.
+//
+// S^T grad^T eta2 needs eta2 at v and at its backward neighbours, summed over
+// the pulses with the coefficients of v.  Both S^T and grad^T are linear, so
+// the update kernel that produces eta2 also reduces it over the pulses
+// (projections, [6][S][V]):
+//   slot d     (d = y, x, z): A_d[s][v] = sum_k S_v[k][s] eta2_d[k][v]
+//   slot 3 + d:               B_d[s][v] = sum_k S_{v + e_d}[k][s] eta2_d[k][v]
+// so that (S^T grad^T eta2)[s][v] = sum_d ([i_d > 0] B_d[s][v - e_d]
+// - [i_d < n_d - 1] A_d[s][v]).  With a per-depth table the y and x
+// neighbours share v's coefficients (B_y = A_y, B_x = A_x; slots 3 and 4 are
+// not written).  u2 is then read once per dual step (current and previous)
+// and written once, instead of being read again for w.
+__device__ __forceinline__ int r3_bslot(bool depth_table, int d) {
+  return (depth_table && d < 2) ? d : 3 + d;
+}
+
 // w = z - (grad^T eta1 + S^T grad^T eta2 + eta3); with clamp_out the
-// algorithm's output max(., 0) instead.  One thread per voxel position, all
-// species.
+// algorithm's output max(., 0) instead.  eta2 enters through its projections
+// pq (null: eta2 = 0).  One thread per voxel position, all species.
 __global__ __launch_bounds__(256) void r3_w_kernel(
     float* __restrict__ out, const float* __restrict__ z, const float* __restrict__ u1c,
-    const float* __restrict__ u1p, const float* __restrict__ u2c, const float* __restrict__ u2p,
-    const float* __restrict__ u3c, const float* __restrict__ u3p, float beta, SwitchParams sw,
-    const float* __restrict__ phi, const float* __restrict__ stab, int kp, Grid3 G, int clamp_out) {
+    const float* __restrict__ u1p, const float* __restrict__ pq, const float* __restrict__ u3c,
+    const float* __restrict__ u3p, float beta, int ns, int depth_table, Grid3 G, int clamp_out) {
   if (G.gate && *G.gate) return;  // a device stop test has ended the solve
   const int64_t vol = (int64_t)G.ny * G.nx * G.nz;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1999,38 +2014,6 @@ __global__ __launch_bounds__(256) void r3_w_kernel(
   const int idx[3] = {iy, ix, iz};
   const int nd[3] = {G.ny, G.nx, G.nz};
   const int64_t st[3] = {(int64_t)G.nx * G.nz, G.nz, 1};
-  const size_t col = (size_t)v - iz;
-  const int ns = sw.ns, nk = sw.nk;
-  float acc[kMaxSpecies];
-#pragma unroll
-  for (int s = 0; s < kMaxSpecies; ++s) acc[s] = 0.0f;
-  // S^T grad^T eta2, four pulses at a time (summed into acc pulse by pulse)
-  const int nk4 = (nk + 3) >> 2;
-  const f32x4* c4 = (const f32x4*)u2c;
-  const f32x4* p4 = (const f32x4*)u2p;
-  for (int kg = 0; kg < nk4; ++kg) {
-    f32x4 gt = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int64_t base = ((int64_t)d * nk4 + kg) * vol;
-      if (idx[d] > 0) {
-        const f32x4 e = eta4(c4, p4, beta, base + v - st[d]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) gt[q] += e[q];
-      }
-      if (idx[d] < nd[d] - 1) {
-        const f32x4 e = eta4(c4, p4, beta, base + v);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) gt[q] -= e[q];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = kg * 4 + q;
-      if (k < nk)
-        for (int s = 0; s < ns; ++s) acc[s] += coef_zt(sw, phi, stab, G.nz, col, iz, k, s) * gt[q];
-    }
-  }
   for (int s = 0; s < ns; ++s) {
     float gt = 0.0f;
 #pragma unroll
@@ -2038,23 +2021,32 @@ __global__ __launch_bounds__(256) void r3_w_kernel(
       const int64_t base = ((int64_t)d * ns + s) * vol;
       if (idx[d] > 0) gt += eta3(u1c, u1p, beta, base + v - st[d]);
       if (idx[d] < nd[d] - 1) gt -= eta3(u1c, u1p, beta, base + v);
+      if (pq) {
+        const int64_t bb = ((int64_t)r3_bslot(depth_table, d) * ns + s) * vol;
+        if (idx[d] > 0) gt += pq[bb + v - st[d]];
+        if (idx[d] < nd[d] - 1) gt -= pq[base + v];
+      }
     }
     const int64_t i = (int64_t)s * vol + v;
-    const float r = z[i] - (gt + acc[s] + eta3(u3c, u3p, beta, i));
+    const float r = z[i] - (gt + eta3(u3c, u3p, beta, i));
     out[i] = clamp_out ? fmaxf(r, 0.0f) : r;
   }
 }
 
 // u1' = clip(eta1 + s1 grad w), u2' = clip(eta2 + s2 grad (S w)),
 // u3' = clip(eta3 + s3 w), each at its own radius; one thread per voxel
-// position (forward differences, zero at the last index of each axis).
+// position (forward differences, zero at the last index of each axis).  Also
+// writes the projections pq of the next step's eta2 = u2' + beta_next (u2' -
+// u2) (beta_next = 0 on the last step: the projections of u2' itself).  NSM
+// bounds the species count for the register arrays.
+template <int NSM>
 __global__ __launch_bounds__(256) void r3_u_kernel(
     float* __restrict__ n1, float* __restrict__ n2, float* __restrict__ n3,
-    const float* __restrict__ w, const float* __restrict__ u1c, const float* __restrict__ u1p,
-    const float* __restrict__ u2c, const float* __restrict__ u2p, const float* __restrict__ u3c,
-    const float* __restrict__ u3p, float beta, float s1, float s2, float s3, float th1, float th2,
-    float th3, SwitchParams sw, const float* __restrict__ phi, const float* __restrict__ stab,
-    int kp, Grid3 G) {
+    float* __restrict__ pq, const float* __restrict__ w, const float* __restrict__ u1c,
+    const float* __restrict__ u1p, const float* __restrict__ u2c, const float* __restrict__ u2p,
+    const float* __restrict__ u3c, const float* __restrict__ u3p, float beta, float beta_next,
+    float s1, float s2, float s3, float th1, float th2, float th3, SwitchParams sw,
+    const float* __restrict__ phi, const float* __restrict__ stab, Grid3 G) {
   if (G.gate && *G.gate) return;  // a device stop test has ended the solve
   const int64_t vol = (int64_t)G.ny * G.nx * G.nz;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2066,14 +2058,19 @@ __global__ __launch_bounds__(256) void r3_u_kernel(
   const int64_t st[3] = {(int64_t)G.nx * G.nz, G.nz, 1};
   const int ns = sw.ns, nk = sw.nk;
   // w at v and at its three forward neighbours
-  float wv[4][kMaxSpecies];
-  for (int s = 0; s < ns; ++s) {
+  float wv[4][NSM];
+#pragma unroll
+  for (int s = 0; s < NSM; ++s) {
+    wv[0][s] = wv[1][s] = wv[2][s] = wv[3][s] = 0.0f;
+    if (s >= ns) continue;
     const int64_t i = (int64_t)s * vol + v;
     wv[0][s] = w[i];
 #pragma unroll
     for (int d = 0; d < 3; ++d) wv[d + 1][s] = fwd[d] ? w[i + st[d]] : 0.0f;
   }
-  for (int s = 0; s < ns; ++s) {
+#pragma unroll
+  for (int s = 0; s < NSM; ++s) {
+    if (s >= ns) continue;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int64_t i = ((int64_t)d * ns + s) * vol + v;
@@ -2083,53 +2080,109 @@ __global__ __launch_bounds__(256) void r3_u_kernel(
     const int64_t i = (int64_t)s * vol + v;
     n3[i] = fminf(fmaxf(eta3(u3c, u3p, beta, i) + s3 * wv[0][s], -th3), th3);
   }
-  // (S w)^k at v and its forward neighbours; with a per-depth table the y and
-  // x neighbours share v's coefficients and the z neighbour uses depth z + 1
+  // coefficients at v and at its forward neighbours, generated in registers:
+  // S_v[k][s] = phi_v (a_s + b_s e_s^k) with e_s = exp(-phi_v^gamma / tau_s);
+  // e_s^k is taken from exp at the first pulse of each group of four and
+  // multiplied by e_s within the group.  With a per-depth fluence the y and x
+  // neighbours share v's coefficients.
+  const bool depth_table = stab != nullptr;
   const size_t col0 = (size_t)v - iz;
-  const size_t colq[3] = {col0 + (size_t)st[0], col0 + (size_t)st[1], col0};
-  const int zq[3] = {iz, iz, iz + 1};
-  const int zn = fwd[2] ? iz + 1 : iz;
+  float ph[4];
+  if (depth_table) {
+    ph[0] = ph[1] = ph[2] = phi[iz];
+    ph[3] = phi[fwd[2] ? iz + 1 : iz];
+  } else {
+    ph[0] = phi[col0 + iz];
+    ph[1] = fwd[0] ? phi[col0 + st[0] + iz] : ph[0];
+    ph[2] = fwd[1] ? phi[col0 + st[1] + iz] : ph[0];
+    ph[3] = fwd[2] ? phi[col0 + iz + 1] : ph[0];
+  }
+  float rate[4][NSM];  // phi^gamma / tau_s per position
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float pg = (sw.gamma == 0.0f) ? 1.0f : powf(ph[j], sw.gamma);
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) rate[j][s] = s < ns ? pg * sw.inv_tau[s] : 0.0f;
+  }
+  float pa[3][NSM], pb[3][NSM];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) pa[d][s] = pb[d][s] = 0.0f;
   // u2 in groups of four pulses (layout above r3_w_kernel)
   const int nk4 = (nk + 3) >> 2;
   const f32x4* c4 = (const f32x4*)u2c;
   const f32x4* p4 = (const f32x4*)u2p;
   f32x4* o4 = (f32x4*)n2;
   for (int kg = 0; kg < nk4; ++kg) {
-    float sq[4][4];
+    f32x4 a[3], e[3], r[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t i = ((int64_t)d * nk4 + kg) * vol + v;
+      a[d] = c4 ? c4[i] : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      e[d] = eta4(c4, p4, beta, i);
+    }
+    float ek[4][NSM], ef[4][NSM];  // e_s^k at the group's first pulse, e_s
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int s = 0; s < NSM; ++s) {
+        ek[j][s] = expf(-(float)(kg * 4) * rate[j][s]);
+        ef[j][s] = expf(-rate[j][s]);
+      }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int k = kg * 4 + q;
-      sq[q][0] = sq[q][1] = sq[q][2] = sq[q][3] = 0.0f;
-      if (k >= nk) continue;
-      if (stab) {
-        for (int s = 0; s < ns; ++s) {
-          const float c0 = stab[((size_t)k * ns + s) * G.nz + iz];
-          const float c1 = stab[((size_t)k * ns + s) * G.nz + zn];
-          sq[q][0] += c0 * wv[0][s];
-          sq[q][1] += c0 * wv[1][s];
-          sq[q][2] += c0 * wv[2][s];
-          sq[q][3] += c1 * wv[3][s];
-        }
-      } else {
-        for (int s = 0; s < ns; ++s) {
-          sq[q][0] += scoef(sw, phi[col0 + iz], k, s) * wv[0][s];
+      if (k >= nk) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) r[d][q] = 0.0f;
+        continue;
+      }
+      float cs[NSM], cf[3][NSM];
+      float sq0 = 0.0f, sqd[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < NSM; ++s) {
+        cs[s] = cf[0][s] = cf[1][s] = cf[2][s] = 0.0f;
+        if (s >= ns) continue;
+        if (sw.diag) {
+          cs[s] = k == s ? ph[0] : 0.0f;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) cf[d][s] = (fwd[d] && k == s) ? ph[d + 1] : 0.0f;
+        } else {
+          cs[s] = ph[0] * (sw.a[s] + sw.b[s] * ek[0][s]);
 #pragma unroll
           for (int d = 0; d < 3; ++d)
-            if (fwd[d]) sq[q][d + 1] += scoef(sw, phi[colq[d] + zq[d]], k, s) * wv[d + 1][s];
+            cf[d][s] = fwd[d] ? ph[d + 1] * (sw.a[s] + sw.b[s] * ek[d + 1][s]) : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ek[j][s] *= ef[j][s];
+        sq0 += cs[s] * wv[0][s];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sqd[d] += cf[d][s] * wv[d + 1][s];
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float g = fwd[d] ? sqd[d] - sq0 : 0.0f;
+        const float un = fminf(fmaxf(e[d][q] + s2 * g, -th2), th2);
+        r[d][q] = un;
+        const float en = un + beta_next * (un - a[d][q]);
+#pragma unroll
+        for (int s = 0; s < NSM; ++s) {
+          pa[d][s] += cs[s] * en;
+          pb[d][s] += cf[d][s] * en;
         }
       }
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int64_t i = ((int64_t)d * nk4 + kg) * vol + v;
-      const f32x4 e = eta4(c4, p4, beta, i);
-      f32x4 r;
+    for (int d = 0; d < 3; ++d) o4[((int64_t)d * nk4 + kg) * vol + v] = r[d];
+  }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float g = fwd[d] ? sq[q][d + 1] - sq[q][0] : 0.0f;
-        r[q] = kg * 4 + q < nk ? fminf(fmaxf(e[q] + s2 * g, -th2), th2) : 0.0f;
-      }
-      o4[i] = r;
+  for (int s = 0; s < NSM; ++s) {
+    if (s >= ns) continue;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      pq[((int64_t)d * ns + s) * vol + v] = pa[d][s];
+      if (!depth_table || d == 2) pq[((int64_t)(3 + d) * ns + s) * vol + v] = pb[d][s];
     }
   }
 }
@@ -2173,26 +2226,34 @@ __global__ __launch_bounds__(256) void tvs_kernel(const float* __restrict__ c, S
 }
 
 hipError_t launch_r3_w(const psoam_plan* P, float* out, const float* z, const float* u1c,
-                       const float* u1p, const float* u2c, const float* u2p, const float* u3c,
-                       const float* u3p, float beta, int clamp_out, hipStream_t s) {
+                       const float* u1p, const float* pq, const float* u3c, const float* u3p,
+                       float beta, int clamp_out, hipStream_t s) {
   const Grid3 G = grid3(P);
   const size_t vol = P->v_elems();
   if (vol == 0) return hipSuccess;
-  hipLaunchKernelGGL(r3_w_kernel, dim3(blocks_for(vol)), dim3(256), 0, s, out, z, u1c, u1p, u2c,
-                     u2p, u3c, u3p, beta, P->sw, P->d_phi, P->d_stab_t, P->Kp, G, clamp_out);
+  hipLaunchKernelGGL(r3_w_kernel, dim3(blocks_for(vol)), dim3(256), 0, s, out, z, u1c, u1p, pq,
+                     u3c, u3p, beta, P->sw.ns, P->d_stab_t ? 1 : 0, G, clamp_out);
   return hipGetLastError();
 }
 
-hipError_t launch_r3_u(const psoam_plan* P, float* n1, float* n2, float* n3, const float* w,
-                       const float* u1c, const float* u1p, const float* u2c, const float* u2p,
-                       const float* u3c, const float* u3p, float beta, const float step[3],
-                       const float theta[3], hipStream_t s) {
+hipError_t launch_r3_u(const psoam_plan* P, float* n1, float* n2, float* n3, float* pq,
+                       const float* w, const float* u1c, const float* u1p, const float* u2c,
+                       const float* u2p, const float* u3c, const float* u3p, float beta,
+                       float beta_next, const float step[3], const float theta[3],
+                       hipStream_t s) {
   const Grid3 G = grid3(P);
   const size_t vol = P->v_elems();
   if (vol == 0) return hipSuccess;
-  hipLaunchKernelGGL(r3_u_kernel, dim3(blocks_for(vol)), dim3(256), 0, s, n1, n2, n3, w, u1c, u1p,
-                     u2c, u2p, u3c, u3p, beta, step[0], step[1], step[2], theta[0], theta[1],
-                     theta[2], P->sw, P->d_phi, P->d_stab_t, P->Kp, G);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(blocks_for(vol)), dim3(256), 0, s, n1, n2, n3, pq, w, u1c, u1p,
+                       u2c, u2p, u3c, u3p, beta, beta_next, step[0], step[1], step[2], theta[0],
+                       theta[1], theta[2], P->sw, P->d_phi, P->d_stab_t, G);
+  };
+  const int ns = P->sw.ns;
+  if (ns <= 2) go(r3_u_kernel<2>);
+  else if (ns == 3) go(r3_u_kernel<3>);
+  else if (ns == 4) go(r3_u_kernel<4>);
+  else go(r3_u_kernel<kMaxSpecies>);
   return hipGetLastError();
 }
 
