@@ -405,9 +405,10 @@ typedef struct {
 
 /* psoam_plan_create with the launch shapes chosen by measurement: for a
  * 16-bit plan of the general form it builds the plan the built-in rules
- * choose and the alternatives that fit (4 or 8 output rows per workgroup for
- * H, with or without four loader waves at 8 rows; 4 or 8 rows and operand
- * shift 0 or 4 for H^T), for an FP32 plan the one with the per-tile instead
+ * choose and the alternatives that fit (4, 8 or 12 output rows per workgroup
+ * for H, with or without four loader waves at 8 rows; 4, 8 or 12 rows and
+ * operand shift 0 or 4 for H^T; 12 rows for one-part operands only), for an
+ * FP32 plan the one with the per-tile instead
  * of the run-packed kernel, times each band kernel's solver form on `stream`
  * (HIP events, one warm-up and three timed launches on the zeroed operands),
  * times the TV dual step on the plan's grid with each tile shape of the

@@ -1047,12 +1047,12 @@ int create_tuned(const psoam_geom* g, const psoam_species* sp, const float* phi,
   // other row counts and shifts for H^T (each timed on the direction it changes)
   std::vector<std::pair<Shape, int>> alts;
   if (base.h_rows)
-    for (int rows : {4, 8})
+    for (int rows : {4, 8, 12})
       for (int lw : {0, 1})
-        if ((rows != base.h_rows || lw != base.h_loadw) && !(rows == 4 && lw == 1))
+        if ((rows != base.h_rows || lw != base.h_loadw) && !(rows != 8 && lw == 1))
           alts.push_back({Shape{rows, base.ht_rows, base.tsh, lw, base.tv}, 0});
   if (base.ht_rows)
-    for (int rows : {4, 8})
+    for (int rows : {4, 8, 12})
       for (int tsh : {0, 4})
         if (rows != base.ht_rows || tsh != base.tsh)
           alts.push_back({Shape{base.h_rows, rows, tsh, base.h_loadw, base.tv}, 1});

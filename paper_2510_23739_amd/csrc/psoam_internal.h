@@ -73,7 +73,7 @@ struct BandTable {
   size_t useful_macs = 0;    // nonzero band entries covered (per position and pulse)
   // staged (LDS) variant, 16-bit operands: chunks listed per (tile, dy)
   bool lds_ok = false;
-  int rows = 4;                // output rows (waves) per workgroup: 4 or 8
+  int rows = 4;                // output rows (waves) per workgroup: 4, 8 or 12
   int l_chunks = 0;
   int max_oct = 0;             // widest staged octet window
   size_t lds_bytes = 0;        // dynamic LDS per workgroup
@@ -178,7 +178,7 @@ namespace psoam {
 
 // Launch-shape choice for the next plan built on this thread (the
 // autotuner's lever): output rows per staged workgroup for H (rows_fwd) and
-// H^T (rows_adj), 4 or 8, the H^T operand shift, 0 or 4, H's loader
+// H^T (rows_adj), 4, 8 or 12, the H^T operand shift, 0 or 4, H's loader
 // waves, 0 (off) or 1 (on where they can run), and for FP32 plans the kernel
 // of H and of H^T, 0 (per-tile) or 1 (run-packed); any other value leaves
 // that choice to the plan's own rules.  A choice that does not fit is ignored.

@@ -723,24 +723,27 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   // round-robin) receives all tiles for its own share of position blocks,
   // and (2) within an XCD the heaviest tiles are dispatched first so the
   // light ones fill the tail (longest-processing-time order, L.order).
+  // When the position blocks do not divide by 8, each XCD's share is rounded
+  // up and the blocks past the last position have no work (the grid holds
+  // 8 ceil(npos / 8) blocks per tile).
   const int b = blockIdx.x;
   const int npos = L.nxb * L.nyb;
-  int mtile, pos;
-  if ((npos & 7) == 0) {
-    const int xcd = b & 7, k = b >> 3;
-    const int per_x = npos >> 3;
-    mtile = L.order[k / per_x];
-    pos = xcd * per_x + k % per_x;
-  } else {
-    mtile = L.order[b / npos];
-    pos = b % npos;
-  }
-  const int xb = pos % L.nxb;
-  const int yb = pos / L.nxb;
+  const int per_x = (npos + 7) >> 3;
+  const int xcd = b & 7, kx = b >> 3;
+  const int mtile = L.order[kx / per_x];
+  const int pos = xcd * per_x + kx % per_x;
   constexpr int NTALL = 64 * (ROWS + LOADW);             // threads of the workgroup
   constexpr int NT = 64 * (LOADW > 0 ? LOADW : ROWS);    // threads that stage rows
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  if (pos >= npos) {
+    // no positions: the residual form still owns its partial sums
+    if constexpr (MODE == 1)
+      if (lane == 0 && wave < ROWS) A.partial[(size_t)b * ROWS + wave] = 0.0;
+    return;
+  }
+  const int xb = pos % L.nxb;
+  const int yb = pos / L.nxb;
   const int g = lane >> 4, n = lane & 15;
   const int iy0 = yb * ROWS, ix0 = xb * kLdsPos;
   const int iy = iy0 + wave;
@@ -1139,7 +1142,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_pe
 // CU at 31 x 31 footprints) and 8-row ones with loader waves (twelve waves).
 // An 8-row workgroup without loader waves runs two waves per SIMD whatever
 // its registers (a second one would need four), and split operands need the
-// registers for their second band-block buffer: these get 256.
+// registers for their second band-block buffer: these get 256.  A 12-row
+// workgroup (one-part operands) needs three waves per SIMD resident.
 template <int PREC, bool SPLIT, int MODE, int ROWS, int LOADW>
 __global__ __launch_bounds__(64 * (ROWS + LOADW)) __attribute__((amdgpu_waves_per_eu((SPLIT || (ROWS == 8 && LOADW == 0)) ? 2 : 3))) void band16_lds(
     BandArgs A, LdsArgs L) {
@@ -1147,9 +1151,10 @@ __global__ __launch_bounds__(64 * (ROWS + LOADW)) __attribute__((amdgpu_waves_pe
 }
 
 // H^T with one-part operands is held to two waves per SIMD (256 registers)
-// so that two 4-row workgroups can share a CU when their staged window fits
+// so that two 4-row workgroups can share a CU when their staged window fits;
+// a 12-row workgroup needs three
 template <int PREC, bool SPLIT, int ROWS, int LOADW>
-__global__ __launch_bounds__(64 * (ROWS + LOADW)) __attribute__((amdgpu_waves_per_eu(SPLIT ? 1 : 2))) void band16_lds_adj(
+__global__ __launch_bounds__(64 * (ROWS + LOADW)) __attribute__((amdgpu_waves_per_eu(SPLIT ? 1 : (ROWS == 12 ? 3 : 2)))) void band16_lds_adj(
     BandArgs A, LdsArgs L) {
   band16_lds_body<PREC, SPLIT, 2, ROWS, LOADW>(A, L);
 }
@@ -1351,9 +1356,10 @@ static size_t band_blocks(const psoam_plan* P, int mode) {
     return (size_t)T.n_mtiles * nyb * nxb;
   }
   if (use_lds(P, mode)) {
+    // 8 ceil(npos / 8) blocks per tile (every XCD takes an equal share)
     const size_t nyb = (P->g.ny + T.rows - 1) / T.rows;
     const size_t nxb = (P->g.nx + kLdsPos - 1) / kLdsPos;
-    return (size_t)T.n_mtiles * nyb * nxb;
+    return (size_t)T.n_mtiles * ((nyb * nxb + 7) / 8 * 8);
   }
   const int n_mblk = (T.n_mtiles + kWavesPerBlock - 1) / kWavesPerBlock;
   const int nxb = (P->g.nx + kPosPerWave - 1) / kPosPerWave;
@@ -1407,6 +1413,14 @@ static hipError_t launch_band_lds(const psoam_plan* P, const BandTable& T, BandA
     if (T.rows == 8) PSOAM_LDS_R(PR, SP, 8) else PSOAM_LDS_R(PR, SP, 4)                     \
     break;                                                                                  \
   }
+  // 12-row workgroups: one-part operands only (the plan never picks them
+  // for split ones)
+#define PSOAM_LDS12(PR)                                                                     \
+  {                                                                                         \
+    if (T.rows == 12) PSOAM_LDS_R(PR, false, 12) else if (T.rows == 8) PSOAM_LDS_R(PR, false, 8) \
+    else PSOAM_LDS_R(PR, false, 4)                                                          \
+    break;                                                                                  \
+  }
   // one-part operands, one 8-row workgroup per CU: four loader waves beside
   // the eight contracting ones (H and its residual form)
 #define PSOAM_LDS_PF(PR)                                                                    \
@@ -1427,15 +1441,18 @@ static hipError_t launch_band_lds(const psoam_plan* P, const BandTable& T, BandA
   }
   }
 #undef PSOAM_LDS_PF
+  if (T.rows == 12 && (P->prec == PSOAM_BF16_SPLIT || P->prec == PSOAM_FP16_SPLIT))
+    return hipErrorInvalidValue;
   switch (P->prec) {
     case PSOAM_BF16:
-    case PSOAM_BF16_REFINED: PSOAM_LDS(PSOAM_BF16, false)
-    case PSOAM_FP16: PSOAM_LDS(PSOAM_FP16, false)
+    case PSOAM_BF16_REFINED: PSOAM_LDS12(PSOAM_BF16)
+    case PSOAM_FP16: PSOAM_LDS12(PSOAM_FP16)
     case PSOAM_BF16_SPLIT: PSOAM_LDS(PSOAM_BF16, true)
     case PSOAM_FP16_SPLIT: PSOAM_LDS(PSOAM_FP16, true)
     default:
       return hipErrorInvalidValue;
   }
+#undef PSOAM_LDS12
 #undef PSOAM_LDS
 #undef PSOAM_LDS_R
 #undef PSOAM_LDS_K

@@ -433,11 +433,14 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
     return (size_t)max_oct * XW * 16 * 8 * sizeof(uint16_t) +
            lds_meta_bytes(F, rows, T.max_runs) + 16;
   };
-  std::vector<uint32_t> win4, win8;
-  int mo4 = 0, mo8 = 0;
+  std::vector<uint32_t> win4, win8, win12;
+  int mo4 = 0, mo8 = 0, mo12 = 0;
   windows(4, win4, mo4);
   windows(8, win8, mo8);
-  const size_t lds4 = lds_of(4, mo4), lds8 = lds_of(8, mo8);
+  windows(12, win12, mo12);
+  const size_t lds4 = lds_of(4, mo4), lds8 = lds_of(8, mo8), lds12 = lds_of(12, mo12);
+  // 12 rows (three waves per SIMD, one-part operands): a staged row serves
+  // twelve output rows instead of eight
   // Rows per workgroup: four while at least two such workgroups fit in one
   // CU's LDS (eight waves per CU); when only one fits, eight rows keep two
   // waves per SIMD resident (measured: H^T at 31 x 31 footprint 2.48 ms with
@@ -448,17 +451,27 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
   // split-operand H^T needs more registers than two waves per SIMD allow, so
   // a second 4-row workgroup could not share the CU: eight rows instead
   if (dir == 1 && split && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
-  // PSOAM_LDS_ROWS=4 or 8 overrides the choice when it fits (tests cover both)
+  const bool fit12 = !split && lds12 <= (size_t)kLdsMaxBytes;
+  // where one workgroup holds the CU anyway, twelve rows stage a row for
+  // twelve output rows instead of eight, at three waves per SIMD: H at 320 x
+  // 320 x 128 (footprint 51) 66.6 -> 63.1 ms, at 256 x 256 x 96 16.6 -> 16.0
+  // ms.  H^T, whose S^T epilogue spills more at three waves per SIMD, keeps
+  // eight rows (63.8 -> 62.3 ms at the first, 15.8 -> 17.0 ms at the second);
+  // the autotuner times both
+  if (dir == 0 && rows == 8 && fit12) rows = 12;
+  // PSOAM_LDS_ROWS=4, 8 or 12 overrides the choice when it fits (tests cover all)
   if (const char* fr = std::getenv("PSOAM_LDS_ROWS")) {
     if (fr[0] == '8' && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
     if (fr[0] == '4' && lds4 <= (size_t)kLdsMaxBytes) rows = 4;
+    if (fr[0] == '1' && fr[1] == '2' && fit12) rows = 12;
   }
   // the autotuner's choice, when it fits
   if (g_tune.rows[dir] == 8 && lds8 <= (size_t)kLdsMaxBytes) rows = 8;
   if (g_tune.rows[dir] == 4 && lds4 <= (size_t)kLdsMaxBytes) rows = 4;
-  std::vector<uint32_t>& win = rows == 8 ? win8 : win4;
+  if (g_tune.rows[dir] == 12 && fit12) rows = 12;
+  std::vector<uint32_t>& win = rows == 12 ? win12 : rows == 8 ? win8 : win4;
   T.rows = rows;
-  T.max_oct = rows == 8 ? mo8 : mo4;
+  T.max_oct = rows == 12 ? mo12 : rows == 8 ? mo8 : mo4;
   T.lds_bytes = (size_t)T.max_oct * XW * 16 * 8 * sizeof(uint16_t);
   // Loader waves: four more waves that load the next staged row into
   // registers during the current row's contractions (H and its residual
@@ -490,7 +503,8 @@ static int build_table(psoam_plan* P, int dir, const int32_t* t0, const float* t
     if (e[0] == '0') T.half = 0;
   // PSOAM_BAND_GLOBAL=1 keeps the plan on the global-operand kernel (tests cover both)
   const char* force_global = std::getenv("PSOAM_BAND_GLOBAL");
-  T.lds_ok = n_l < 0xffff && F < 0xffff && (rows == 8 ? lds8 : lds4) <= (size_t)kLdsMaxBytes &&
+  T.lds_ok = n_l < 0xffff && F < 0xffff &&
+             (rows == 12 ? lds12 : rows == 8 ? lds8 : lds4) <= (size_t)kLdsMaxBytes &&
              !(force_global && force_global[0] == '1');
   if (!T.lds_ok) return PSOAM_OK;
   PSOAM_HIP(hipMalloc(&T.d_win, sizeof(uint32_t) * win.size()));

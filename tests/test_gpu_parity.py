@@ -51,19 +51,23 @@ def test_apply_A_and_AT_C1(c1, prec):
                                          ("fp16_split", "lds8"), ("bf16_refined", "lds"),
                                          ("bf16_refined", "global"), ("bf16_refined", "lds8"),
                                          ("bf16", "lds8load"), ("fp16", "lds8load"),
-                                         ("bf16_refined", "lds8load")])
+                                         ("bf16_refined", "lds8load"), ("bf16", "lds12"),
+                                         ("fp16", "lds12"), ("bf16_refined", "lds12")])
 def test_ragged_random_table(prec, kernel, monkeypatch):
     """Sizes off every tile boundary, per-voxel fluence with the fluence-
     dependent rate, asymmetric random band running off both ends; both the
     LDS-staged and the global-operand band kernels."""
     torch = torch_cuda()
     monkeypatch.setenv("PSOAM_BAND_GLOBAL", "1" if kernel == "global" else "0")
-    monkeypatch.setenv("PSOAM_LDS_ROWS", "8" if kernel.startswith("lds8") else "4")
+    monkeypatch.setenv("PSOAM_LDS_ROWS", "8" if kernel.startswith("lds8") else
+                       "12" if kernel == "lds12" else "4")
     monkeypatch.setenv("PSOAM_LDS_LOADW", "1" if kernel == "lds8load" else "0")
     cfg, t0, taps, phi, sp = ragged_cfg(3)
     say(f"[parity] ragged prec={prec}")
     S = oracle_S(cfg, phi, sp)
     plan = lib_plan(cfg, t0, taps, phi, sp, prec)
+    if kernel == "lds12":
+        assert plan.stats()["lds_rows"] == [12, 12]
     rng = np.random.default_rng(4)
     c = rng.standard_normal(cfg.c_shape).astype(np.float32)
     y = plan.apply_A(torch.from_numpy(c).cuda(), nan_buf(cfg.y_shape)).cpu().numpy()
@@ -348,9 +352,50 @@ def test_loader_waves_change_nothing(c1, prec, monkeypatch):
     assert max(e_at) <= TOL_OP[prec] and max(e_c) <= 1e-3
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_row_counts_change_nothing(prec, monkeypatch):
+    """Workgroups of 4, 8 and 12 output rows: every output row still takes
+    the staged rows, runs and pulse blocks in the same order, so A, A^T and
+    the solve's iterates are equal bit for bit; the C1 grid and a ragged one.
+    The objective trace sums the residual form's FP64 partials (one per
+    workgroup row, zero for the blocks past the last position when the
+    position blocks do not divide among the 8 XCDs) in an order that follows
+    the row count, so it agrees to FP64 rounding."""
+    torch = torch_cuda()
+    cases = [ragged_cfg(13)]
+    cfg1 = synth.C1
+    t01, taps1 = synth.sir_table(cfg1.nz, cfg1.f, cfg1.nt)
+    cases.append((cfg1, t01, taps1, synth.phi_depth(cfg1.nz), synth.species(cfg1.n_species)))
+    monkeypatch.setenv("PSOAM_LDS_LOADW", "0")
+    for (cfg, t0, taps, phi, sp) in cases:
+        S = oracle_S(cfg, phi, sp)
+        rng = np.random.default_rng(23)
+        c = rng.standard_normal(cfg.c_shape).astype(np.float32)
+        y = rng.standard_normal(cfg.y_shape).astype(np.float32)
+        out = {}
+        for rows in ("4", "8", "12"):
+            monkeypatch.setenv("PSOAM_LDS_ROWS", rows)
+            plan = lib_plan(cfg, t0, taps, phi, sp, prec)
+            assert plan.stats()["lds_rows"] == [int(rows)] * 2
+            c_s, _, tr = plan.solve(torch.from_numpy(y).cuda(), lambda_tv=0.05, lambda_l1=0.02,
+                                    k1=4, k2=5, alpha1=1e-3, trace=True)
+            out[rows] = (plan.apply_A(torch.from_numpy(c).cuda()).cpu().numpy(),
+                         plan.apply_AT(torch.from_numpy(y).cuda()).cpu().numpy(),
+                         c_s.cpu().numpy(), np.asarray(tr))
+            plan.close()
+        for rows in ("8", "12"):
+            for a, b in zip(out["4"][:3], out[rows][:3]):
+                np.testing.assert_array_equal(a, b)
+            np.testing.assert_allclose(out[rows][3], out["4"][3], rtol=1e-13, atol=0.0)
+        e = oracle.rel_err(out["12"][0], oracle.apply_A(c, S, t0, taps, cfg.nt))
+        say(f"[parity] rows 4/8/12 {prec} {cfg.name}: bitwise equal; A vs oracle {e:.2e}")
+        assert e <= TOL_OP[prec]
+
+
 @pytest.mark.parametrize("prec,rows,loadw", [("bf16", "4", "0"), ("bf16", "8", "1"), ("fp16", "8", "0"),
                                              ("bf16_split", "4", "0"), ("fp16_split", "8", "0"),
-                                             ("bf16_refined", "8", "1")])
+                                             ("bf16_refined", "8", "1"), ("bf16", "12", "0"),
+                                             ("fp16", "12", "0")])
 def test_half_last_block_changes_nothing(prec, rows, loadw, monkeypatch):
     """The last 16-pulse block run in half form (K mod 16 in 1..8: 8 pulses
     per staged column, two positions per matrix-core block) against the same
