@@ -43,6 +43,50 @@ def test_prox_r3_matches_oracle(which, th):
     plan.close()
 
 
+@pytest.mark.parametrize("which", ["c2_crop_depth_table", "k40_per_voxel"])
+def test_prox_r3_many_pulses_matches_oracle(which):
+    """The dual step's switching coefficients come from exp at the first
+    pulse of each group of four and a per-pulse ratio inside it: checked
+    against the oracle's table at 32 pulses (a 24 x 24 crop of the
+    128 x 128 x 64 geometry: full depth, 3 species, depth-only fluence, the
+    default rate) and at 40 pulses with a per-voxel fluence and the
+    fluence-dependent rate (a ragged grid; the last group of four is full,
+    the depth not a multiple of the tile), 20 dual steps, with max-abs
+    figures beside the normwise error."""
+    torch = torch_cuda()
+    if which == "c2_crop_depth_table":
+        cfg = synth.C2.crop(24, 24)
+        phi, sp = synth.phi_depth(cfg.nz), synth.species(cfg.n_species)
+        t0, taps = synth.sir_table(cfg.nz, cfg.f, cfg.nt)
+    else:
+        cfg = synth.Config("k40", nx=10, ny=9, nz=21, n_species=3, n_pulses=40, nt=48, f=5,
+                           k1=4, k2=20, seed=31)
+        rng = np.random.default_rng(31)
+        t0, taps = synth.random_table(cfg.nz, cfg.f, cfg.nt, 7, rng, t0_lo=-3, t0_hi=cfg.nt)
+        phi = rng.uniform(0.2, 1.0, size=(cfg.ny, cfg.nx, cfg.nz)).astype(np.float32)
+        sp = synth.species(3, gamma=1.0)
+    S = oracle_S(cfg, phi, sp)
+    plan = lib_plan(cfg, t0, taps, phi, sp, "fp32")
+    z = (np.random.default_rng(22).standard_normal(cfg.c_shape) * 0.5 + 0.2).astype(np.float32)
+    zt = torch.from_numpy(z).cuda()
+    th, th0 = (0.05, 0.1, 0.02), (0.05, 0.0, 0.02)
+    out = []
+    for t in (th, th0):
+        x = nan_buf(cfg.c_shape)
+        plan.prox_r3(zt, *t, 20, x=x)
+        out.append(x.cpu().numpy().astype(np.float64))
+    ref, ref0 = oracle.prox_r3(z, S, *th, 20), oracle.prox_r3(z, S, *th0, 20)
+    e = oracle.rel_err(out[0], ref)
+    em = float(np.max(np.abs(out[0] - ref)))
+    # the TV(S c) term's own contribution (about 1% of x here), against the oracle's
+    ed = oracle.rel_err(out[0] - out[1], ref - ref0)
+    say(f"[r3] prox {which} K={cfg.n_pulses}: rel err {e:.3e}, max-abs {em:.3e}; "
+        f"TV(S c) contribution {oracle.rel_err(ref, ref0):.2e} of x, its rel err {ed:.3e}")
+    assert e <= 1e-5 and em <= 1e-5 * max(1.0, float(np.max(np.abs(ref))))
+    assert ed <= 1e-3
+    plan.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16", 1e-2)])
 def test_fista_with_tvs_matches_oracle(prec, tol):
     torch = torch_cuda()
