@@ -262,6 +262,11 @@ typedef struct {
  * entry (zeros for the paper's start), result on exit.  st: host, may be
  * NULL.  Synchronises the stream when it needs host scalars (power
  * iteration result, stopping tests and trace unless device_stop) and at exit.
+ * With eps1 > 0 or a trace, the data term of F(c_{k+1}) comes from A c_{k+1}
+ * = (A xi_{k+1} + beta_k A c_k) / (1 + beta_k), formed in the epilogue of
+ * the next iteration's H (A is linear), not from a second H apply; this
+ * needs a y-sized FP32 array the plan allocates once (4 K Ny Nx Nt bytes).
+ * The separable and factorised plans evaluate F directly.
  * EINVAL: bad options; EDIVERGED: non-finite reduction (c holds the last
  * finite iterate). */
 int psoam_solve(const psoam_plan* plan, const float* p, float* c, const psoam_solve_opts* o,

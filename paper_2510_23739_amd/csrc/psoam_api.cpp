@@ -365,6 +365,36 @@ int objective_terms(psoam_plan* P, int op, const float* c, const float* p, bool 
   return PSOAM_OK;
 }
 
+// A c of the solve's iterate, y-sized (the objective by the momentum recurrence)
+int ensure_yc_ws(psoam_plan* P, float*& yc) {
+  const size_t need = sizeof(float) * P->y_elems() + 256;
+  if (P->yc_ws.bytes < need) {
+    if (P->yc_ws.base) PSOAM_HIP(hipFree(P->yc_ws.base));
+    P->yc_ws.base = nullptr;
+    P->yc_ws.bytes = 0;
+    PSOAM_HIP(hipMalloc(&P->yc_ws.base, need));
+    P->yc_ws.bytes = need;
+  }
+  yc = (float*)(((uintptr_t)P->yc_ws.base + 255) & ~(uintptr_t)255);
+  return PSOAM_OK;
+}
+
+// The objective terms of c_{k+1} for the general operator without a second
+// H: A is linear and xi_{k+1} = c_{k+1} + beta_k (c_{k+1} - c_k), so A c_{k+1}
+// = (A xi_{k+1} + beta_k A c_k) / (1 + beta_k).  H's residual form at
+// xi_{k+1} (the next iteration's, enqueued here) forms it from the stored
+// A c_k and sums (A c_{k+1} - p)^2 into d_scalars[4]; TV, l1 (and TV(S c))
+// of c_{k+1} as in objective_terms.
+int objective_terms_rec(psoam_plan* P, const float* xi_next, const float* c_next,
+                        const float* p, float* yc, double beta, bool with_tvs, hipStream_t s) {
+  PSOAM_HIP(launch_switch_fwd(P, xi_next, s));
+  PSOAM_HIP(launch_band(P, 1, nullptr, p, P->d_partial, s, yc, beta, 0));
+  PSOAM_HIP(launch_sum_partials(P->d_partial, band_partials(P, 1), P->d_scalars + 4, s));
+  PSOAM_HIP(launch_tv_l1_sums(P, c_next, P->d_partial, P->d_scalars + 5, s));
+  if (with_tvs) PSOAM_HIP(launch_tvs_sum(P, c_next, P->d_partial, P->d_scalars + 7, s));
+  return PSOAM_OK;
+}
+
 int check_opts(const float* p, const float* c, const psoam_solve_opts* o) {
   if (!p || !c || !o) return fail(PSOAM_EINVAL, "solve: NULL argument");
   if (o->k1 < 0 || o->k2 < 0 || !(o->lambda_tv >= 0.0) || !(o->lambda_l1 >= 0.0) ||
@@ -453,6 +483,15 @@ int solve_one(psoam_plan* P, int op, const float* p, float* c, const psoam_solve
   const bool r3 = o->lambda_tvs > 0.0;
   R3Bufs RB{};
   if (r3 && (rc = ensure_r3_ws(P, RB))) return rc;
+  // general operator with objective evaluations: F(c_{k+1})'s data term by
+  // the momentum recurrence inside the next iteration's H (enqueued at the
+  // end of iteration k), not by a second H apply; PSOAM_OBJ_DIRECT=1 keeps
+  // the direct evaluation (tests and timing compare both)
+  const char* obj_direct = std::getenv("PSOAM_OBJ_DIRECT");
+  const bool rec = need_obj && op == kOpA && !P->inner && !P->fact && o->k1 > 0 &&
+                   !(obj_direct && obj_direct[0] == '1');
+  float* yc = nullptr;
+  if (rec && (rc = ensure_yc_ws(P, yc))) return rc;
   const float th3[3] = {th_tv, (float)(alpha1 * o->lambda_tvs), th_l1};
   double t = 1.0, f_prev = 0.0;
   bool have_f = false;
@@ -471,9 +510,19 @@ int solve_one(psoam_plan* P, int op, const float* p, float* c, const psoam_solve
     PSOAM_HIP(launch_stop_init(P->d_ctl, P->d_scalars, s));
   }
   std::unique_ptr<GateGuard> gate(dev ? new GateGuard(P->d_ctl) : nullptr);
+  if (rec) {
+    // H's residual form at xi_0 = c_0, which also stores A c_0
+    PSOAM_HIP(launch_switch_fwd(P, B.xi, s));
+    PSOAM_HIP(launch_band(P, 1, nullptr, p, P->d_partial, s, yc, 0.0, 1));
+  }
   for (int k = 0; k < o->k1; ++k) {
-    // gradient A^T (A xi - p)
-    if ((rc = enqueue_grad(P, op, B.xi, p, B.g, s))) return rc;
+    // gradient A^T (A xi - p); with the recurrence H at xi_k ran at the end
+    // of the previous iteration (its residual is H^T's operand)
+    if (rec) {
+      PSOAM_HIP(launch_band(P, 2, B.g, nullptr, nullptr, s));
+    } else if ((rc = enqueue_grad(P, op, B.xi, p, B.g, s))) {
+      return rc;
+    }
     PSOAM_HIP(launch_axpby(B.zb, B.xi, B.g, 1.0f, (float)(-alpha1), sv, s));
     // prox: TV dual iteration, then max(. - alpha1 lambda_l1, 0); with the
     // TV(S c) term the stacked dual iteration of the full regulariser
@@ -504,15 +553,22 @@ int solve_one(psoam_plan* P, int op, const float* p, float* c, const psoam_solve
     }
     std::swap(B.cprev, B.cnext);  // cprev = c_{k+1}
     stats.iterations = k + 1;
+    // the momentum kernel's beta, as the recurrence must use it
+    const double beta_f = (double)(float)beta;
     if (dev) {
-      if (need_obj && (rc = objective_terms(P, op, B.cprev, p, r3, B.w, s))) return rc;
+      if (need_obj) {
+        rc = rec ? objective_terms_rec(P, B.xi, B.cprev, p, yc, beta_f, r3, s)
+                 : objective_terms(P, op, B.cprev, p, r3, B.w, s);
+        if (rc) return rc;
+      }
       PSOAM_HIP(launch_stop_test(P->d_ctl, P->d_scalars, o->trace ? P->d_trace : nullptr, tst, s));
       continue;
     }
     bool stop = false;
     if (need_obj || o->eps2 > 0.0) {
       if (need_obj) {
-        rc = objective_terms(P, op, B.cprev, p, r3, B.w, s);
+        rc = rec ? objective_terms_rec(P, B.xi, B.cprev, p, yc, beta_f, r3, s)
+                 : objective_terms(P, op, B.cprev, p, r3, B.w, s);
         if (rc) return rc;
       }
       rc = copy_scalars(P, hs, 10, s);

@@ -140,6 +140,7 @@ struct psoam_plan {
   size_t n_trace = 0;
   // duals of the full regulariser's prox (TV(S c) term), allocated on first use
   psoam::Workspace r3_ws;
+  psoam::Workspace yc_ws;  // A c of the solve's iterate (objective by the momentum recurrence)
   // max over voxels of the largest eigenvalue of S_v^T S_v (FP64, at creation)
   double smax2 = 0.0;
   // separable switching (fluence-independent rate): S_v[k][s] = phi_v T[k][s].
@@ -206,9 +207,12 @@ int hip_fail(hipError_t e, const char* what);
 hipError_t launch_switch_fwd(const psoam_plan* P, const float* c, hipStream_t s);
 hipError_t launch_pack_r(const psoam_plan* P, const float* y, hipStream_t s);
 // mode 0: y = H b (writes y);  mode 1: r = H b - p (p may be null), written into the
-// H^T operand, sum r^2 into partial[]; mode 2: c = S^T H^T r (writes c)
+// H^T operand, sum r^2 into partial[]; mode 2: c = S^T H^T r (writes c).
+// Mode 1 with yc: also A c = (H b + yc_beta yc) / (1 + yc_beta) (H b alone
+// when yc_first) written back to yc, and the partials sum (A c - p)^2
 hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* pmeas,
-                       double* partial, hipStream_t s);
+                       double* partial, hipStream_t s, float* yc = nullptr, double yc_beta = 0.0,
+                       int yc_first = 0);
 size_t band_partials(const psoam_plan* P, int mode);
 
 hipError_t launch_prox_l1(float* x, const float* z, int64_t n, float thresh, int nonneg,

@@ -328,6 +328,14 @@ struct BandArgs {
   int tsh;          // 16-bit H^T operand: sample t stored at t + tsh (0 or 4)
   float rq_scale;
   double* partial;
+  // residual form only: A c of the current iterate by the momentum recurrence
+  // (null: off).  yc [K][Ny][Nx][Nt] holds A c_{k-1} on entry and A c_k on
+  // exit, A c_k = (H b + yc_beta A c_{k-1}) yc_inv with yc_inv = 1 / (1 +
+  // yc_beta), or H b itself when yc_first; the partial sums are then those of
+  // (A c_k - p)^2 instead of r^2
+  float* yc;
+  float yc_beta, yc_inv;
+  int yc_first;
   SwitchParams sw;
   const float* phi;
   const float* stab;
@@ -446,14 +454,47 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
       if (ix >= A.nx) continue;
       const size_t pos = ((size_t)(iy + A.r) * A.xp + (ix + A.r)) * A.ps_r;
       const size_t yi = (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
-      float rv[4];
+      float rv[4], pm[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const bool ok = row0 + j < nt;
-        float v = acc[p][j] * ib;
-        if (A.pmeas && ok) v -= kPre ? pv[kPre ? p : 0][j] : A.pmeas[yi + j];
-        rv[j] = ok ? v : 0.0f;
-        ss += (double)rv[j] * (double)rv[j];
+        pm[j] = (A.pmeas && ok) ? (kPre ? pv[kPre ? p : 0][j] : A.pmeas[yi + j]) : 0.0f;
+        rv[j] = ok ? acc[p][j] * ib - pm[j] : 0.0f;
+        if (!A.yc) ss += (double)rv[j] * (double)rv[j];
+      }
+      if (A.yc) {
+        // A c of the iterate: a convex combination of H b and the stored A c
+        // of the previous iterate (same element, same lane: in place)
+        float* yp = A.yc + yi;
+        const bool v4 = (nt & 3) == 0 && row0 + 3 < nt;
+        f32x4 yo = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (!A.yc_first) {
+          if (v4) {
+            yo = *(const f32x4*)yp;
+          } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (row0 + j < nt) yo[j] = yp[j];
+          }
+        }
+        f32x4 yn;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float ya = acc[p][j] * ib;
+          yn[j] = A.yc_first ? ya : (ya + A.yc_beta * yo[j]) * A.yc_inv;
+        }
+        if (v4) {
+          *(f32x4*)yp = yn;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (row0 + j < nt) yp[j] = yn[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double d = row0 + j < nt ? (double)yn[j] - (double)pm[j] : 0.0;
+          ss += d * d;
+        }
       }
       if constexpr (RQ_PREC == PSOAM_FP32) {
         float* d = (float*)A.rq + pos + (size_t)row0 * A.kp + k;
@@ -1500,7 +1541,7 @@ static hipError_t launch_band_mode(const psoam_plan* P, BandArgs& A, dim3 grid, 
 }
 
 hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* pmeas,
-                       double* partial, hipStream_t s) {
+                       double* partial, hipStream_t s, float* yc, double yc_beta, int yc_first) {
   const BandTable& T = (mode == 2) ? P->adj : P->fwd;
   const bool split = P->prec == PSOAM_BF16_SPLIT || P->prec == PSOAM_FP16_SPLIT;
   const bool fp16 = P->prec == PSOAM_FP16 || P->prec == PSOAM_FP16_SPLIT;
@@ -1539,6 +1580,10 @@ hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* p
   A.tsh = P->tsh;
   A.rq_scale = fp16 ? kFp16Scale : 1.0f;
   A.partial = partial;
+  A.yc = mode == 1 ? yc : nullptr;
+  A.yc_beta = (float)yc_beta;
+  A.yc_inv = (float)(1.0 / (1.0 + yc_beta));
+  A.yc_first = yc_first;
   A.sw = P->sw;
   A.phi = P->d_phi;
   A.stab = P->d_stab;

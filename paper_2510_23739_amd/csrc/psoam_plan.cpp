@@ -601,7 +601,7 @@ void free_plan(psoam_plan* P) {
   free_table(P->fwd);
   free_table(P->adj);
   void* bufs[] = {P->d_phi, P->d_stab, P->d_stab_t, P->d_stab_o, P->d_bq, P->d_bq_lo, P->d_rq, P->d_rq_lo,
-                  P->solve_ws.base, P->r3_ws.base, P->d_partial, P->d_scalars, P->d_f16,
+                  P->solve_ws.base, P->r3_ws.base, P->yc_ws.base, P->d_partial, P->d_scalars, P->d_f16,
                   P->d_f16acc, P->d_ctl, P->d_trace};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
