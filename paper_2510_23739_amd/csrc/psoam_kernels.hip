@@ -423,7 +423,8 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
           if (row0 + j < nt) yo[j] = v[j];
       }
     }
-  } else if constexpr (MODE == 1) {
+  } else if constexpr (MODE == 1 || MODE == 3) {
+    constexpr bool REC = MODE == 3;
     const int nt = A.nt;
     if (k >= A.nk) return;
     // 16-bit operand (the staged kernels): the measurements of all NP
@@ -433,6 +434,12 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
     // occupancy would drop) and loads them position by position.
     constexpr bool kPre = RQ_PREC != PSOAM_FP32;
     const bool vec = A.pmeas && ((uintptr_t)A.pmeas & 15) == 0 && (nt & 3) == 0 && row0 + 3 < nt;
+    // The operand's row and position strides pass through an empty asm here,
+    // so the positions' 64-bit operand addresses are formed per call instead
+    // of being hoisted out of the pulse-block loop and held (spilled) across
+    // the matrix-core loop
+    int xps = A.xp, psr = (int)A.ps_r;
+    asm volatile("" : "+s"(xps), "+s"(psr));
     f32x4 pv[kPre ? SL : 1];
     if constexpr (kPre) {
 #pragma unroll
@@ -452,7 +459,7 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
     for (int p = 0; p < SL; ++p) {
       const int ix = ix0 + px(p);
       if (ix >= A.nx) continue;
-      const size_t pos = ((size_t)(iy + A.r) * A.xp + (ix + A.r)) * A.ps_r;
+      const size_t pos = ((size_t)(iy + A.r) * xps + (ix + A.r)) * (size_t)psr;
       const size_t yi = (((size_t)k * A.ny + iy) * A.nx + ix) * nt + row0;
       float rv[4], pm[4];
 #pragma unroll
@@ -460,9 +467,9 @@ __device__ __forceinline__ void epi_block(const BandArgs& A, const f32x4 (&acc)[
         const bool ok = row0 + j < nt;
         pm[j] = (A.pmeas && ok) ? (kPre ? pv[kPre ? p : 0][j] : A.pmeas[yi + j]) : 0.0f;
         rv[j] = ok ? acc[p][j] * ib - pm[j] : 0.0f;
-        if (!A.yc) ss += (double)rv[j] * (double)rv[j];
+        if constexpr (!REC) ss += (double)rv[j] * (double)rv[j];
       }
-      if (A.yc) {
+      if constexpr (REC) {
         // A c of the iterate: a convex combination of H b and the stored A c
         // of the previous iterate (same element, same lane: in place)
         float* yp = A.yc + yi;
@@ -625,7 +632,7 @@ __global__ __launch_bounds__(256) void band16(BandArgs A) {
   block_coords(A, mtile, iy, ix0, wid);
   const int lane = threadIdx.x & 63;
   if (mtile >= A.n_mtiles) {
-    if (MODE == 1 && lane == 0) A.partial[wid] = 0.0;
+    if ((MODE == 1 || MODE == 3) && lane == 0) A.partial[wid] = 0.0;
     return;
   }
   const int g = lane >> 4, n = lane & 15;
@@ -662,7 +669,7 @@ __global__ __launch_bounds__(256) void band16(BandArgs A) {
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
     epi_block<MODE, kPosPerWave, PREC, SPLIT>(A, acc[nb], mtile, iy, ix0, nb * 16, nb == 0, ss);
-  if constexpr (MODE == 1) {
+  if constexpr (MODE == 1 || MODE == 3) {
     ss = wave_sum(ss);
     if (lane == 0) A.partial[wid] = ss;
   }
@@ -675,7 +682,7 @@ __global__ __launch_bounds__(256) void band32(BandArgs A) {
   block_coords(A, mtile, iy, ix0, wid);
   const int lane = threadIdx.x & 63;
   if (mtile >= A.n_mtiles) {
-    if (MODE == 1 && lane == 0) A.partial[wid] = 0.0;
+    if ((MODE == 1 || MODE == 3) && lane == 0) A.partial[wid] = 0.0;
     return;
   }
   const int g = lane >> 4, n = lane & 15;
@@ -703,7 +710,7 @@ __global__ __launch_bounds__(256) void band32(BandArgs A) {
   for (int nb = 0; nb < NB; ++nb)
     epi_block<MODE, kPosPerWave, PSOAM_FP32, false>(A, acc[nb], mtile, iy, ix0, nb * 16, nb == 0,
                                                     ss);
-  if constexpr (MODE == 1) {
+  if constexpr (MODE == 1 || MODE == 3) {
     ss = wave_sum(ss);
     if (lane == 0) A.partial[wid] = ss;
   }
@@ -779,7 +786,7 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
   const int lane = threadIdx.x & 63;
   if (pos >= npos) {
     // no positions: the residual form still owns its partial sums
-    if constexpr (MODE == 1)
+    if constexpr (MODE == 1 || MODE == 3)
       if (lane == 0 && wave < ROWS) A.partial[(size_t)b * ROWS + wave] = 0.0;
     return;
   }
@@ -1073,7 +1080,7 @@ __device__ __forceinline__ void band16_lds_body(const BandArgs& A, const LdsArgs
     // every chunk of the run loop would wait for all of them.
     __builtin_amdgcn_s_waitcnt(kVmcnt0);
   }
-  if constexpr (MODE == 1) {
+  if constexpr (MODE == 1 || MODE == 3) {
     ss = wave_sum(ss);
     if (lane == 0 && !loader) A.partial[(size_t)b * ROWS + wave] = ss;
   }
@@ -1172,7 +1179,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_pe
       epi_block<MODE, kLdsPos, PSOAM_FP32, false>(A, acc, mtile, iy, ix0, pb * 16, pb == 0, ss);
     }
   }
-  if constexpr (MODE == 1) {
+  if constexpr (MODE == 1 || MODE == 3) {
     ss = wave_sum(ss);
     if (lane == 0) A.partial[(size_t)b * kWavesPerBlock + wave] = ss;
   }
@@ -1542,6 +1549,9 @@ static hipError_t launch_band_mode(const psoam_plan* P, BandArgs& A, dim3 grid, 
 
 hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* pmeas,
                        double* partial, hipStream_t s, float* yc, double yc_beta, int yc_first) {
+  // the residual form with the A c recurrence is a kernel form of its own
+  // (mode 3), so the plain residual form carries none of its registers
+  if (mode == 1 && yc) mode = 3;
   const BandTable& T = (mode == 2) ? P->adj : P->fwd;
   const bool split = P->prec == PSOAM_BF16_SPLIT || P->prec == PSOAM_FP16_SPLIT;
   const bool fp16 = P->prec == PSOAM_FP16 || P->prec == PSOAM_FP16_SPLIT;
@@ -1566,7 +1576,7 @@ hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* p
   A.inv_scale = fp16 ? 1.0f / kFp16Scale : 1.0f;
   A.f16 = P->d_f16;
   A.gate = gate_now();
-  if (mode == 1 && P->d_f16) {
+  if ((mode == 1 || mode == 3) && P->d_f16) {
     // residual r = H b - p: |r| <= hrow max |b| + max |p| with max |b| <= srow max |x|
     const hipError_t e = f16_scale(P, 3, P->hrow * P->srow, 1.0, s);
     if (e != hipSuccess) return e;
@@ -1580,7 +1590,7 @@ hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* p
   A.tsh = P->tsh;
   A.rq_scale = fp16 ? kFp16Scale : 1.0f;
   A.partial = partial;
-  A.yc = mode == 1 ? yc : nullptr;
+  A.yc = mode == 3 ? yc : nullptr;
   A.yc_beta = (float)yc_beta;
   A.yc_inv = (float)(1.0 / (1.0 + yc_beta));
   A.yc_first = yc_first;
@@ -1607,6 +1617,7 @@ hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* p
       case 0: hipLaunchKernelGGL(band32_run<0>, grid, blk, 0, s, A, L); break;
       case 1: hipLaunchKernelGGL(band32_run<1>, grid, blk, 0, s, A, L); break;
       case 2: hipLaunchKernelGGL(band32_run<2>, grid, blk, 0, s, A, L); break;
+      case 3: hipLaunchKernelGGL(band32_run<3>, grid, blk, 0, s, A, L); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1616,6 +1627,7 @@ hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* p
       case 0: return launch_band_lds<0>(P, T, A, grid, s);
       case 1: return launch_band_lds<1>(P, T, A, grid, s);
       case 2: return launch_band_lds<2>(P, T, A, grid, s);
+      case 3: return launch_band_lds<3>(P, T, A, grid, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -1623,6 +1635,7 @@ hipError_t launch_band(const psoam_plan* P, int mode, float* out, const float* p
     case 0: return launch_band_mode<0>(P, A, grid, s);
     case 1: return launch_band_mode<1>(P, A, grid, s);
     case 2: return launch_band_mode<2>(P, A, grid, s);
+    case 3: return launch_band_mode<3>(P, A, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
