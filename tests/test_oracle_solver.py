@@ -1,7 +1,8 @@
 """Pins of the oracle's solver: FISTA without regularisation converges to the
 nonnegative least-squares solution (SciPy's Lawson-Hanson NNLS), proximal
 gradient without momentum and with an exact prox never increases the
-objective, A = I reaches the prox of p in one step, and the stopping tests."""
+objective, A = I reaches the prox of p in one step, the stopping tests, and
+the momentum-step recurrence for A c that the GPU solver's objective uses."""
 import numpy as np
 import pytest
 from scipy.optimize import nnls
@@ -98,3 +99,36 @@ def test_unmixing_step_converges_to_per_voxel_nnls():
                 # the per-voxel blocks are ill-conditioned (similar switching
                 # curves), so the iteration is compared at a 1e-4 relative level
                 np.testing.assert_allclose(c[:, iy, ix, iz], ref, rtol=1e-4, atol=1e-6)
+
+
+def test_objective_recurrence_of_the_momentum_step():
+    """A c_{k+1} = (A xi_{k+1} + beta_k A c_k) / (1 + beta_k), chained from
+    A c_0 = A xi_0 (xi_0 = c_0), reproduces the direct data term of every
+    iterate of Alg. alg:prox-outer (here with the nonnegativity prox), since
+    xi_{k+1} = c_{k+1} + beta_k (c_{k+1} - c_k) and A is linear; the same
+    chain with the next step's weight beta_{k+1} does not."""
+    M, p, shape = _tiny_problem(3)
+    lam = np.linalg.eigvalsh(M.T @ M)[-1]
+    alpha = 1.0 / lam
+    c = np.zeros(M.shape[1])
+    xi = c.copy()
+    t = 1.0
+    yc = M @ xi                      # A c_0
+    yc_wrong = yc.copy()
+    betas, direct, rec, wrong = [], [], [], []
+    for k in range(12):
+        c_next = np.maximum(xi - alpha * (M.T @ (M @ xi - p)), 0.0)
+        t, beta = oracle.fista_momentum(t)
+        betas.append(beta)
+        xi = c_next + beta * (c_next - c)
+        c = c_next
+        y_xi = M @ xi                # what H computes at xi_{k+1}
+        yc = (y_xi + beta * yc) / (1.0 + beta)
+        direct.append(0.5 * float(np.sum((M @ c - p) ** 2)))
+        rec.append(0.5 * float(np.sum((yc - p) ** 2)))
+        bw = oracle.fista_momentum(t)[1]   # beta_{k+1}: the wrong index
+        yc_wrong = (y_xi + bw * yc_wrong) / (1.0 + bw)
+        wrong.append(0.5 * float(np.sum((yc_wrong - p) ** 2)))
+    assert betas[0] == 0.0 and betas[-1] > 0.3
+    np.testing.assert_allclose(rec, direct, rtol=1e-12)
+    assert max(abs(a - b) / b for a, b in zip(wrong, direct)) > 1e-4
